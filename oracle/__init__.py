@@ -1,0 +1,289 @@
+"""ORACLE — test infrastructure only.
+
+A plain, slow FP64 CPU implementation of the SV-MPR conditional Monte Carlo method (arXiv 2212.01317), written
+from the paper.  The arithmetic lives in ``mpr_oracle.c`` (built with gcc, no fast-math); this module loads it
+with ctypes and adds numpy-level drivers.  Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import it.  It shares no code with the HIP library ``paper_2212_01317_amd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mpr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, IEEE semantics: no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, _SRC,
+                               "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        _lib = ctypes.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_flt = ctypes.c_float
+_dbl = ctypes.c_double
+
+
+def _declare(L: ctypes.CDLL) -> None:
+    L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_philox4x32_10.restype = None
+    L.orc_site_uniforms.argtypes = [_u64, _u32, _u32, _u32, _u32, _i64, _i64, _i64, _f64p]
+    L.orc_site_uniforms.restype = None
+    L.orc_map_angles.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _f64p]
+    L.orc_map_angles.restype = ctypes.c_int
+    L.orc_bond_energy.argtypes = [_flt, _flt, _flt, _flt]
+    L.orc_bond_energy.restype = _dbl
+    L.orc_block_stats.argtypes = [_f32p, _u8p, _i64, _i64, _i32, _i32, _flt, _flt, _f64p, _i32p, _f64p, _i32p]
+    L.orc_block_stats.restype = None
+    L.orc_curve_inverse.argtypes = [_dbl, _f64p, _f64p, _i32]
+    L.orc_curve_inverse.restype = _dbl
+    L.orc_calibrate_blocks.argtypes = [_f64p, _i32p, _i64, _flt, _f64p, _f64p, _i32, _f32p]
+    L.orc_calibrate_blocks.restype = ctypes.c_int
+    L.orc_sweep.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _u64, _u32, _u32, _u32]
+    L.orc_sweep.restype = None
+    L.orc_energy.argtypes = [_f32p, _i64, _i64, _flt, _flt]
+    L.orc_energy.restype = _dbl
+    L.orc_reference_curve.argtypes = [_flt, _f32p, _i32, _i32, _i32, _i32, _u64, _f64p]
+    L.orc_reference_curve.restype = None
+    L.orc_unconditional_sample.argtypes = [_flt, _flt, _i32, _i32, _u64, _u32, _f32p]
+    L.orc_unconditional_sample.restype = None
+    L.orc_ols_slope.argtypes = [_f64p, _i32]
+    L.orc_ols_slope.restype = _dbl
+    L.orc_stop_check.argtypes = [_f64p, _i32, _i32, _i32]
+    L.orc_stop_check.restype = ctypes.c_int
+    L.orc_simulate.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _i32, _i32, _i32, _i32,
+                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _f32p, _f64p, _f64p,
+                               ctypes.POINTER(_i32)]
+    L.orc_simulate.restype = _i32
+    L.orc_predict.argtypes = [_f64p, _f32p, _u8p, _i64, _i64, _i64, _f64p, _f32p]
+    L.orc_predict.restype = None
+    L.orc_validate.argtypes = [_f32p, _f32p, _u8p, _i64, _f64p]
+    L.orc_validate.restype = None
+    L.orc_chain_trace.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _u64, _u32, _u32, _i32,
+                                  _i32, _i64p, _i32, _f32p]
+    L.orc_chain_trace.restype = None
+
+
+# ---------------------------------------------------------------------------------------------------------------
+# thin numpy-facing wrappers
+# ---------------------------------------------------------------------------------------------------------------
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_c(ctr, np.uint32), _c(key, np.uint32), out)
+    return out
+
+
+def site_uniforms(seed, scene, tag, sweep, real, W, x, y):
+    out = np.zeros(2, np.float64)
+    lib().orc_site_uniforms(seed, scene, tag, sweep, real, W, x, y, out)
+    return out
+
+
+def map_angles(z, mask):
+    z = _c(z, np.float32)
+    mask = _c(mask, np.uint8)
+    H, W = z.shape
+    t = np.zeros_like(z)
+    rng = np.zeros(2, np.float64)
+    rc = lib().orc_map_angles(z, mask, H, W, t, rng)
+    if rc != 0:
+        raise ValueError({-1: "no observed site", -2: "non-finite observed value"}[rc])
+    return t, rng
+
+
+def bond_energy(ta, tb, q=0.5, J=1.0) -> float:
+    return lib().orc_bond_energy(ta, tb, q, J)
+
+
+def n_blocks(H, W, lb_h, lb_w):
+    return (-(-H // lb_h)), (-(-W // lb_w))
+
+
+def block_stats(t, mask, lb_h, lb_w, q=0.5, J=1.0):
+    t = _c(t, np.float32)
+    mask = _c(mask, np.uint8)
+    H, W = t.shape
+    nby, nbx = n_blocks(H, W, lb_h, lb_w)
+    B = nby * nbx
+    S = np.zeros(B, np.float64)
+    N = np.zeros(B, np.int32)
+    Ts = np.zeros(B, np.float64)
+    No = np.zeros(B, np.int32)
+    lib().orc_block_stats(t, mask, H, W, lb_h, lb_w, q, J, S, N, Ts, No)
+    return S, N, Ts, No
+
+
+def curve_inverse(e, curve_T, curve_e) -> float:
+    cT = _c(curve_T, np.float64)
+    ce = _c(curve_e, np.float64)
+    return lib().orc_curve_inverse(float(e), cT, ce, len(cT))
+
+
+def calibrate_blocks(S, N, curve_T, curve_e, J=1.0):
+    S = _c(S, np.float64)
+    N = _c(N, np.int32)
+    cT = _c(curve_T, np.float64)
+    ce = _c(curve_e, np.float64)
+    T = np.zeros(len(S), np.float32)
+    rc = lib().orc_calibrate_blocks(S, N, len(S), J, cT, ce, len(cT), T)
+    if rc != 0:
+        raise ValueError("no sample bonds")
+    return T
+
+
+def calibrate_temperature(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    """Eq. (2) per block followed by energy matching and the median fill (Sec. 2.2.2)."""
+    H, W = np.shape(t)
+    S, N, _, _ = block_stats(t, mask, lb_h, lb_w, q, J)
+    T = calibrate_blocks(S, N, curve_T, curve_e, J)
+    nby, nbx = n_blocks(H, W, lb_h, lb_w)
+    return T.reshape(nby, nbx), S.reshape(nby, nbx), N.reshape(nby, nbx)
+
+
+def sweep(state, mask, T_blocks, lb_h, lb_w, k, q=0.5, J=1.0, seed=0, scene=0, real=0):
+    assert state.dtype == np.float32 and state.flags["C_CONTIGUOUS"]
+    H, W = state.shape
+    lib().orc_sweep(state, _c(mask, np.uint8), H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, q, J, seed,
+                    scene, real, k)
+
+
+def energy(state, q=0.5, J=1.0) -> float:
+    s = _c(state, np.float32)
+    H, W = s.shape
+    return lib().orc_energy(s, H, W, q, J)
+
+
+def reference_curve(T_grid, L=64, n_therm=200, n_meas=400, seed=0, q=0.5):
+    Tg = _c(T_grid, np.float32)
+    e = np.zeros(len(Tg), np.float64)
+    lib().orc_reference_curve(q, Tg, len(Tg), L, n_therm, n_meas, seed, e)
+    return e
+
+
+def unconditional_sample(T, L=64, n_sweeps=300, seed=0, chain=0, q=0.5):
+    out = np.zeros((L, L), np.float32)
+    lib().orc_unconditional_sample(q, T, L, n_sweeps, seed, chain, out)
+    return out
+
+
+def ols_slope(y) -> float:
+    y = _c(y, np.float64)
+    return lib().orc_ols_slope(y, len(y))
+
+
+def stop_check(e, k, n_fit=20, n_f=5) -> bool:
+    return bool(lib().orc_stop_check(_c(e, np.float64), k, n_fit, n_f))
+
+
+@dataclass
+class SimConfig:
+    q: float = 0.5
+    J: float = 1.0
+    n_real: int = 1
+    real_offset: int = 0
+    init_mode: int = 1          # 0 random start (MPR), 1 block-mean start (SV-MPR)
+    stop_mode: int = 0          # 0 fixed n_eq, 1 automatic equilibrium test
+    n_eq: int = 50
+    n_samp: int = 1
+    n_fit: int = 20
+    n_f: int = 5
+    n_max: int = 1000
+    seed: int = 0
+    scene: int = 0
+
+
+@dataclass
+class SimResult:
+    state: np.ndarray
+    acc: np.ndarray
+    energy: np.ndarray
+    k_star: int
+    converged: bool
+
+
+def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
+    t = _c(t, np.float32)
+    mask = _c(mask, np.uint8)
+    H, W = t.shape
+    R = cfg.n_real
+    state = np.zeros((R, H, W), np.float32)
+    acc = np.zeros((H, W), np.float64)
+    ncap = (cfg.n_max if cfg.stop_mode == 1 else cfg.n_eq) + 1
+    en = np.zeros(ncap, np.float64)
+    conv = _i32(0)
+    k = lib().orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
+                           cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp, cfg.n_fit, cfg.n_f,
+                           cfg.n_max, cfg.seed, cfg.scene, state, acc, en, ctypes.byref(conv))
+    return SimResult(state=state, acc=acc, energy=en[: k + 1].copy(), k_star=int(k), converged=bool(conv.value))
+
+
+def predict(acc, z, mask, n_samples, rng):
+    acc = _c(acc, np.float64)
+    z = _c(z, np.float32)
+    H, W = z.shape
+    zhat = np.zeros_like(z)
+    lib().orc_predict(acc, z, _c(mask, np.uint8), H, W, n_samples, _c(rng, np.float64), zhat)
+    return zhat
+
+
+def validate(zhat, truth, eval_mask):
+    out = np.zeros(2, np.float64)
+    zh = _c(zhat, np.float32).ravel()
+    lib().orc_validate(zh, _c(truth, np.float32).ravel(), _c(eval_mask, np.uint8).ravel(), zh.size, out)
+    return float(out[0]), float(out[1])
+
+
+def chain_trace(state, mask, T_blocks, lb_h, lb_w, k_start, n_sweeps, sites, q=0.5, J=1.0, seed=0, scene=0,
+                real=0):
+    assert state.dtype == np.float32 and state.flags["C_CONTIGUOUS"]
+    H, W = state.shape
+    sites = _c(sites, np.int64)
+    tr = np.zeros((n_sweeps, len(sites)), np.float32)
+    lib().orc_chain_trace(state, _c(mask, np.uint8), H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, q, J, seed,
+                          scene, real, k_start, n_sweeps, sites, len(sites), tr)
+    return tr
+
+
+def run_pipeline(z, mask, lb_h, lb_w, curve_T, curve_e, cfg: SimConfig):
+    """Sec. 2: map -> per-block calibration -> conditional simulation -> conditional-mean prediction."""
+    t, rng = map_angles(z, mask)
+    T, _, _ = calibrate_temperature(t, mask, lb_h, lb_w, curve_T, curve_e, cfg.q, cfg.J)
+    res = simulate(t, mask, T, lb_h, lb_w, cfg)
+    zhat = predict(res.acc, z, mask, cfg.n_real * cfg.n_samp, rng)
+    return dict(t=t, range=rng, T=T, sim=res, zhat=zhat)
