@@ -1,0 +1,169 @@
+/*
+ * mpr.h — C ABI of the MI355X (gfx950) implementation of the SV-MPR gap-filling method:
+ * conditional Monte Carlo simulation of the modified planar rotator (MPR) model with per-block temperatures
+ * (Lach & Zukovic, arXiv 2212.01317, Sec. 2).
+ *
+ * The problem (Sec. 2.1): an H x W grid whose sites are either samples (G_S, value known) or gaps (G_P, value to
+ * predict).  The data are mapped linearly onto spin angles, a temperature is calibrated per block of lb_h x lb_w
+ * sites by energy matching (Sec. 2.2.2), the gap spins are relaxed by checkerboard Metropolis sweeps with the
+ * samples held fixed until the energy series stops drifting (Sec. 3.4), and the prediction at each gap is the
+ * mean of the conditional distribution, estimated over realizations and sampling sweeps (Sec. 2.1).
+ *
+ * Conventions (every entry point):
+ *   - Pointers are DEVICE pointers owned by the caller unless marked "host".  Arrays are row-major and contiguous:
+ *     site n = y * W + x.  mask: 1 = sample (observed), 0 = gap.  z at a gap is ignored (it may be NaN).
+ *   - Spin angles are stored in turns t in [0, 1] (phi = 2 pi t).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is enqueued on it; a call returns
+ *     without waiting unless its comment says it synchronises the stream.
+ *   - Nothing is allocated on the device by the library: scratch memory is the caller's `workspace`, whose size is
+ *     given by the matching *_workspace_bytes query.  The workspace must stay valid until the enqueued work ends.
+ *   - The return value is an mpr_status; nothing throws across the ABI.  On any non-OK status mpr_last_error()
+ *     returns a message (thread-local).  Argument checks happen before any work is enqueued.  A device error is
+ *     reported as MPR_ERR_HIP by the call that observes it.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low 32 bits, seed high 32 bits) and
+ *     counter = (pair, sweep, realization, scene << 4 | tag << 1 | colour), where the same-colour sites of a row are
+ *     paired four columns apart (pair = y * ceil(W/4) + x/4; the site with ((x >> 1) & 1) == 0 takes words 0 and 1,
+ *     the other words 2 and 3); a word w becomes the uniform (w >> 8) * 2^-24.  Tags: 0 sweep, 1 random start,
+ *     2 reference lattice.  Realizations are keyed by their global index (real_offset + r), so any subset of the
+ *     realizations reproduces the same chains.
+ */
+#ifndef MPR_H
+#define MPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPR_OK = 0,
+    MPR_ERR_INVALID_ARG = 1,        /* a pointer, size or parameter is invalid */
+    MPR_ERR_SHAPE = 2,              /* grid or block shape out of the supported range */
+    MPR_ERR_NO_SAMPLES = 3,         /* the mask has no observed site */
+    MPR_ERR_NO_SAMPLE_BONDS = 4,    /* no pair of neighbouring samples anywhere: T cannot be estimated */
+    MPR_ERR_NONFINITE_INPUT = 5,    /* an observed value is NaN or infinite */
+    MPR_ERR_WORKSPACE_TOO_SMALL = 6,
+    MPR_ERR_HIP = 7,                /* a HIP runtime call failed */
+    MPR_WARN_NOT_CONVERGED = 8      /* AUTO stopping reached n_max without declaring equilibrium (results valid) */
+} mpr_status;
+
+enum { MPR_INIT_RANDOM = 0, MPR_INIT_BLOCK_MEAN = 1 };
+enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
+
+/* Parameters of one conditional simulation (host struct). */
+typedef struct {
+    float q;              /* modification parameter of Eq. (1), 0 < q <= 1/2 */
+    float J;              /* coupling of Eq. (1), J > 0 */
+    int32_t n_real;       /* number of realizations R (independent chains), 1 .. 65535 */
+    int32_t real_offset;  /* global index of realization 0 (for splitting the realizations over calls) */
+    int32_t init_mode;    /* MPR_INIT_BLOCK_MEAN (SV-MPR, Sec. 3.3) or MPR_INIT_RANDOM (MPR) */
+    int32_t stop_mode;    /* MPR_STOP_AUTO (Sec. 3.4 equilibrium test) or MPR_STOP_FIXED (n_eq sweeps) */
+    int32_t n_eq;         /* FIXED: number of equilibration sweeps */
+    int32_t n_samp;       /* sampling sweeps S after equilibrium, each accumulated into the mean */
+    int32_t n_fit;        /* AUTO: memory length of the energy series (paper default 20) */
+    int32_t n_f;          /* AUTO: check every n_f sweeps (paper default 5); first check at n_fit + n_f */
+    int32_t n_max;        /* AUTO: cap on the equilibration sweeps */
+    uint64_t seed;
+    uint32_t scene_id;    /* 0 .. 2^28 - 1, separates the random streams of different scenes */
+} mpr_sim_config;
+
+/* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;
+ * t = fl32((z - zmin) / (zmax - zmin)) at samples (so the extremes map to exactly 0 and 1 turn), t = 0 at gaps and
+ * everywhere when zmax == zmin.  Writes t_out[H*W] and range_out[2] = {zmin, zmax} (double).
+ * Synchronises the stream (it must know whether there is a sample and whether all samples are finite).
+ * Errors: MPR_ERR_NO_SAMPLES, MPR_ERR_NONFINITE_INPUT, MPR_ERR_SHAPE (H, W < 1).
+ * Workspace: mpr_map_workspace_bytes. */
+size_t mpr_map_workspace_bytes(int64_t H, int64_t W);
+mpr_status mpr_map_angles(const float* z, const uint8_t* mask, int64_t H, int64_t W, float* t_out,
+                          double* range_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Eq. (2) per block (Sec. 2.2.2): for each T-block b of lb_h x lb_w sites (ceil division; blocks are numbered
+ * row-major, nbx = ceil(W / lb_w)), S_out[b] = sum over bonds between two samples owned by b of -J cos(2 pi q dt),
+ * where every site owns the bonds to its right and lower neighbour; N_out[b] = number of such bonds;
+ * Tsum_out[b] / Nobs_out[b] = sum / count of the sample angles in b.  FP64 sums.  Any output may be NULL.
+ * Asynchronous.  Workspace: mpr_block_stats_workspace_bytes. */
+size_t mpr_block_stats_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w);
+mpr_status mpr_block_stats(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w,
+                           float q, float J, double* S_out, int32_t* N_out, double* Tsum_out, int32_t* Nobs_out,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* Energy-matching curve (Sec. 2.1, a reading of the matching step): the equilibrium energy per bond of the
+ * unconditional MPR model at J = 1 on a periodic L x L lattice, for each temperature T_grid[i] (device, float,
+ * increasing).  Chain i starts from t = 1/2, runs n_therm sweeps, then averages the per-bond energy over n_meas
+ * sweeps; the chains use the reference-lattice stream (tag 2, realization i, scene 0).  e_out[nT] (device, double).
+ * L even, 2 .. 4096.  Asynchronous.  Workspace: mpr_reference_curve_workspace_bytes. */
+size_t mpr_reference_curve_workspace_bytes(int32_t nT, int32_t L);
+mpr_status mpr_reference_curve(float q, const float* T_grid, int32_t nT, int32_t L, int32_t n_therm,
+                               int32_t n_meas, uint64_t seed, double* e_out, void* workspace, size_t ws_bytes,
+                               void* stream);
+
+/* Block-specific temperatures (Sec. 2.2.2): e_b = S_b / (J N_b) from mpr_block_stats, T_b = J g(e_b) where g
+ * inverts the matching curve (curve_T[n_curve] increasing, curve_e[n_curve]; device, double): the curve is made
+ * non-decreasing by a running maximum, g is piecewise linear in (e, log T) between points, linear in T between
+ * (e = -1, T = 0) and the first point, 0 for e <= -1 and curve_T[n_curve - 1] beyond the last point.  A block
+ * without sample bonds gets the median of the other blocks' T (even count: mean of the two middle values).
+ * lb_h >= H and lb_w >= W gives the single global temperature of the plain MPR method.  T_out[B] (float);
+ * e_blocks_out[B] and nbonds_out[B] are optional (NULL).  Synchronises the stream (to report
+ * MPR_ERR_NO_SAMPLE_BONDS).  Workspace: mpr_calibrate_workspace_bytes. */
+size_t mpr_calibrate_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w);
+mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h,
+                                     int32_t lb_w, float q, float J, const double* curve_T, const double* curve_e,
+                                     int32_t n_curve, float* T_out, double* e_blocks_out, int32_t* nbonds_out,
+                                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Conditional simulation (Sec. 2.1, Sec. 2.2.2, Sec. 3.3, Sec. 3.4).
+ *   t[H*W]: mapped angles (samples used); T_blocks[B]: block temperatures (float) with the same lb_h x lb_w layout.
+ *   Start: gaps take the block mean of the sample angles (a block without samples: the global sample mean), or a
+ *   uniform draw (tag 1).  Then sweeps k = 1, 2, ...: all gap sites of colour (x + y) % 2 == 0, then of colour 1,
+ *   each an independent-uniform Metropolis proposal t' = u1 accepted iff u2 < exp(-dE / T_b) (T_b = 0: iff
+ *   dE <= 0), dE from Eq. (1) over the in-grid nearest neighbours (open boundaries).  After each sweep the
+ *   realization-averaged whole-grid energy per bond e(k) is recorded (e(0) before the first sweep).
+ *   FIXED: k* = n_eq.  AUTO: at k = n_fit + j n_f the ordinary least-squares slope beta of the last n_fit energies
+ *   is taken; equilibrium when beta * sign(e(k) - e(0)) <= 0; the cap n_max gives MPR_WARN_NOT_CONVERGED.
+ *   Then n_samp sampling sweeps (k* + 1 ...), after each of which every realization's gap angles are added to
+ *   acc_out in realization order (FP64; samples' entries are 0).
+ * Outputs: state[n_real*H*W] (float; in: ignored, out: final states), acc_out[H*W] (double), energy_out[k* + 1]
+ * (double, optional NULL; size n_max + 1 for AUTO, n_eq + 1 for FIXED), *sweeps_done_out = k* (host, optional).
+ * FIXED mode is asynchronous; AUTO synchronises the stream at every check.  Workspace:
+ * mpr_simulate_workspace_bytes.  Calls with the same arguments give bit-identical results. */
+size_t mpr_simulate_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg);
+mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks,
+                        int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, float* state, double* acc_out,
+                        double* energy_out, int32_t* sweeps_done_out, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* Continuation of chains: sweeps k_first .. k_first + n_sweeps - 1 (the sweep counter keys the random stream) on
+ * `state` [n_real*H*W] in place, with exactly the per-sweep arithmetic of mpr_simulate (no start, no stopping rule,
+ * no accumulation).  Uses cfg->q, J, n_real, real_offset, seed, scene_id.  Resuming a saved state with the next
+ * sweep counter reproduces an uninterrupted run bit for bit.  energy_out[n_sweeps] (optional): the
+ * realization-averaged energy per bond after each sweep.  Asynchronous.  Workspace: mpr_sweep_workspace_bytes. */
+size_t mpr_sweep_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg);
+mpr_status mpr_sweep(float* state, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks, int32_t lb_h,
+                     int32_t lb_w, const mpr_sim_config* cfg, int32_t k_first, int32_t n_sweeps, double* energy_out,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Prediction (Sec. 2.1, last step): at gaps zhat = fl32(zmin + (zmax - zmin) * acc / n_samples) with
+ * range = {zmin, zmax} from mpr_map_angles; at samples zhat = z.  Asynchronous. */
+mpr_status mpr_predict(const double* acc, const float* z, const uint8_t* mask, int64_t H, int64_t W,
+                       int64_t n_samples, const double* range, float* zhat_out, void* stream);
+
+/* Eq. (3) and Eq. (4): out[0] = AAE = mean |truth - zhat|, out[1] = RASE = sqrt(mean (truth - zhat)^2) over the
+ * n sites with eval_mask != 0 (0 when there is none).  FP64, device out[2].  Asynchronous.
+ * Workspace: mpr_validate_workspace_bytes. */
+size_t mpr_validate_workspace_bytes(int64_t n);
+mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* eval_mask, int64_t n, double* out,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char* mpr_last_error(void);
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int32_t mpr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPR_H */

@@ -1,0 +1,71 @@
+"""SV-MPR gap filling on MI355X (gfx950): conditional Monte Carlo simulation of the modified planar rotator model
+with block-specific temperatures (Lach & Zukovic, arXiv 2212.01317).
+
+The compute runs in libmpr.so (HIP kernels behind the C ABI of include/mpr.h); this package is its thin binding.
+``predict`` chains the ABI calls of one gap-filling run: map -> calibrate -> simulate -> predict.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, MprError, SimConfig, SimOutput, lib,
+                   mpr_block_stats, mpr_calibrate_temperature, mpr_map_angles, mpr_predict, mpr_reference_curve,
+                   mpr_simulate, mpr_sweep, mpr_validate)
+
+__all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "MprError", "SimConfig", "SimOutput",
+           "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_map_angles", "mpr_predict",
+           "mpr_reference_curve", "mpr_simulate", "mpr_sweep", "mpr_validate", "default_T_grid", "reference_curve", "predict",
+           "Prediction", "CURVE_SPEC"]
+
+# The matching curve used by default: 121 temperatures log-spaced over [1e-3, 1e2] (24 per decade), periodic
+# 128 x 128 lattice, 1000 sweeps to equilibrate and 2000 to average, fixed seed.
+CURVE_SPEC = dict(L=128, n_therm=1000, n_meas=2000, seed=2212013170, decades=(-3, 2), per_decade=24)
+
+_curve_cache: dict = {}
+
+
+def default_T_grid(device="cuda") -> torch.Tensor:
+    lo, hi = CURVE_SPEC["decades"]
+    n = (hi - lo) * CURVE_SPEC["per_decade"] + 1
+    T = [10.0 ** (lo + i / CURVE_SPEC["per_decade"]) for i in range(n)]
+    return torch.tensor(T, dtype=torch.float32, device=device)
+
+
+def reference_curve(q: float = 0.5, device="cuda", spec: dict | None = None):
+    """(curve_T float64, curve_e float64) on the device, computed once per (q, spec) by mpr_reference_curve."""
+    sp = dict(CURVE_SPEC if spec is None else spec)
+    key = (float(q), str(torch.device(device)), tuple(sorted((k, str(v)) for k, v in sp.items())))
+    if key not in _curve_cache:
+        Tg = default_T_grid(device) if spec is None or "T_grid" not in sp else sp["T_grid"]
+        e = mpr_reference_curve(Tg, L=sp["L"], n_therm=sp["n_therm"], n_meas=sp["n_meas"], seed=sp["seed"], q=q)
+        _curve_cache[key] = (Tg.to(torch.float64), e)
+    return _curve_cache[key]
+
+
+@dataclass
+class Prediction:
+    zhat: torch.Tensor         # [H, W] float32
+    T: torch.Tensor            # [nby, nbx] float32 block temperatures
+    sim: SimOutput
+    range: torch.Tensor        # [2] float64 (zmin, zmax)
+
+
+def predict(z: torch.Tensor, mask: torch.Tensor, block=(32, 32), n_real: int = 100, *, q: float = 0.5,
+            J: float = 1.0, init_mode: int = INIT_BLOCK_MEAN, stop_mode: int = STOP_AUTO, n_eq: int = 50,
+            n_samp: int = 1, n_fit: int = 20, n_f: int = 5, n_max: int = 1000, seed: int = 0, scene_id: int = 0,
+            curve=None, T_blocks: torch.Tensor | None = None) -> Prediction:
+    """Fill the gaps (mask == 0) of z: Sec. 2.1 map, Sec. 2.2.2 block temperatures (block = (lb_h, lb_w); a block
+    as large as the grid gives the plain MPR method), conditional simulation with the Sec. 3.4 stopping rule, and
+    the conditional mean over n_real realizations x n_samp sampling sweeps."""
+    lb_h, lb_w = int(block[0]), int(block[1])
+    t, rng = mpr_map_angles(z, mask)
+    if T_blocks is None:
+        cT, ce = reference_curve(q, z.device) if curve is None else curve
+        T_blocks, _, _ = mpr_calibrate_temperature(t, mask, lb_h, lb_w, cT, ce, q, J)
+    cfg = SimConfig(q=q, J=J, n_real=n_real, init_mode=init_mode, stop_mode=stop_mode, n_eq=n_eq, n_samp=n_samp,
+                    n_fit=n_fit, n_f=n_f, n_max=n_max, seed=seed, scene_id=scene_id)
+    sim = mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg)
+    zhat = mpr_predict(sim.acc, z, mask, n_real * n_samp, rng)
+    return Prediction(zhat=zhat, T=T_blocks, sim=sim, range=rng)

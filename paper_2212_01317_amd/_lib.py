@@ -1,0 +1,283 @@
+"""ctypes binding of libmpr.so (include/mpr.h).  Argument marshalling only: every function here validates tensor
+placement/dtype, allocates the outputs and the workspace the C ABI asks for, and calls the entry point of the same
+name on torch's current HIP stream.  There is no CPU fallback: without the built library every call raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmpr.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "mpr.h")
+
+MPR_OK = 0
+MPR_WARN_NOT_CONVERGED = 8
+_STATUS = {0: "MPR_OK", 1: "MPR_ERR_INVALID_ARG", 2: "MPR_ERR_SHAPE", 3: "MPR_ERR_NO_SAMPLES",
+           4: "MPR_ERR_NO_SAMPLE_BONDS", 5: "MPR_ERR_NONFINITE_INPUT", 6: "MPR_ERR_WORKSPACE_TOO_SMALL",
+           7: "MPR_ERR_HIP", 8: "MPR_WARN_NOT_CONVERGED"}
+INIT_RANDOM, INIT_BLOCK_MEAN = 0, 1
+STOP_FIXED, STOP_AUTO = 0, 1
+
+
+class MprError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mpr_sim_config(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_float), ("J", ctypes.c_float), ("n_real", ctypes.c_int32),
+                ("real_offset", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
+                ("n_eq", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_fit", ctypes.c_int32),
+                ("n_f", ctypes.c_int32), ("n_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("scene_id", ctypes.c_uint32)]
+
+
+@dataclass
+class SimConfig:
+    """Python mirror of mpr_sim_config (defaults: the paper's n_fit = 20, n_f = 5)."""
+    q: float = 0.5
+    J: float = 1.0
+    n_real: int = 1
+    real_offset: int = 0
+    init_mode: int = INIT_BLOCK_MEAN
+    stop_mode: int = STOP_AUTO
+    n_eq: int = 50
+    n_samp: int = 1
+    n_fit: int = 20
+    n_f: int = 5
+    n_max: int = 1000
+    seed: int = 0
+    scene_id: int = 0
+
+    def to_c(self) -> mpr_sim_config:
+        return mpr_sim_config(self.q, self.J, self.n_real, self.real_offset, self.init_mode, self.stop_mode,
+                              self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id)
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f32 = ctypes.c_float
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "mpr_abi_version": ([], _i32),
+    "mpr_last_error": ([], ctypes.c_char_p),
+    "mpr_map_workspace_bytes": ([_i64, _i64], _sz),
+    "mpr_map_angles": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_block_stats_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
+    "mpr_block_stats": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                        ctypes.c_int),
+    "mpr_reference_curve_workspace_bytes": ([_i32, _i32], _sz),
+    "mpr_reference_curve": ([_f32, _vp, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_calibrate_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
+    "mpr_calibrate_temperature": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
+                                   _sz, _vp], ctypes.c_int),
+    "mpr_simulate_workspace_bytes": ([_i64, _i64, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
+    "mpr_simulate": ([_vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _vp, _vp, _vp,
+                      ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
+    "mpr_sweep_workspace_bytes": ([_i64, _i64, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
+    "mpr_sweep": ([_vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _i32, _i32, _vp, _vp, _sz,
+                   _vp], ctypes.c_int),
+    "mpr_predict": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "mpr_validate_workspace_bytes": ([_i64], _sz),
+    "mpr_validate": ([_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], ctypes.c_int),
+}
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/mpr.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpr_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow_warn: bool = False) -> int:
+    if status == MPR_OK or (allow_warn and status == MPR_WARN_NOT_CONVERGED):
+        return status
+    raise MprError(status, lib().mpr_last_error().decode())
+
+
+def _p(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _hw(x: torch.Tensor):
+    if x.dim() != 2:
+        raise ValueError("grids are 2-D [H, W]")
+    return int(x.shape[0]), int(x.shape[1])
+
+
+# ---------------------------------------------------------------------------------------------------------------
+
+def mpr_map_angles(z: torch.Tensor, mask: torch.Tensor):
+    _dev(z, torch.float32, "z")
+    _dev(mask, torch.uint8, "mask")
+    H, W = _hw(z)
+    t = torch.empty_like(z)
+    rng = torch.empty(2, dtype=torch.float64, device=z.device)
+    ws = _ws(lib().mpr_map_workspace_bytes(H, W), z.device)
+    _check(lib().mpr_map_angles(_p(z), _p(mask), H, W, _p(t), _p(rng), _p(ws), ws.numel(), _stream()))
+    return t, rng
+
+
+def mpr_block_stats(t, mask, lb_h, lb_w, q=0.5, J=1.0):
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    H, W = _hw(t)
+    nby, nbx = -(-H // lb_h), -(-W // lb_w)
+    dev = t.device
+    S = torch.empty(nby * nbx, dtype=torch.float64, device=dev)
+    N = torch.empty(nby * nbx, dtype=torch.int32, device=dev)
+    Ts = torch.empty(nby * nbx, dtype=torch.float64, device=dev)
+    No = torch.empty(nby * nbx, dtype=torch.int32, device=dev)
+    ws = _ws(lib().mpr_block_stats_workspace_bytes(H, W, lb_h, lb_w), dev)
+    _check(lib().mpr_block_stats(_p(t), _p(mask), H, W, lb_h, lb_w, q, J, _p(S), _p(N), _p(Ts), _p(No), _p(ws),
+                                 ws.numel(), _stream()))
+    return S, N, Ts, No
+
+
+def mpr_reference_curve(T_grid: torch.Tensor, L: int = 128, n_therm: int = 1000, n_meas: int = 2000,
+                        seed: int = 0, q: float = 0.5):
+    _dev(T_grid, torch.float32, "T_grid")
+    nT = int(T_grid.numel())
+    e = torch.empty(nT, dtype=torch.float64, device=T_grid.device)
+    ws = _ws(lib().mpr_reference_curve_workspace_bytes(nT, L), T_grid.device)
+    _check(lib().mpr_reference_curve(q, _p(T_grid), nT, L, n_therm, n_meas, seed, _p(e), _p(ws), ws.numel(),
+                                     _stream()))
+    return e
+
+
+def mpr_calibrate_temperature(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(curve_T, torch.float64, "curve_T")
+    _dev(curve_e, torch.float64, "curve_e")
+    H, W = _hw(t)
+    nby, nbx = -(-H // lb_h), -(-W // lb_w)
+    dev = t.device
+    T = torch.empty((nby, nbx), dtype=torch.float32, device=dev)
+    eb = torch.empty((nby, nbx), dtype=torch.float64, device=dev)
+    nb = torch.empty((nby, nbx), dtype=torch.int32, device=dev)
+    ws = _ws(lib().mpr_calibrate_workspace_bytes(H, W, lb_h, lb_w), dev)
+    _check(lib().mpr_calibrate_temperature(_p(t), _p(mask), H, W, lb_h, lb_w, q, J, _p(curve_T), _p(curve_e),
+                                           int(curve_T.numel()), _p(T), _p(eb), _p(nb), _p(ws), ws.numel(),
+                                           _stream()))
+    return T, eb, nb
+
+
+@dataclass
+class SimOutput:
+    state: torch.Tensor        # [R, H, W] float32
+    acc: torch.Tensor          # [H, W] float64
+    energy: torch.Tensor       # [k* + 1] float64 (empty if not requested)
+    sweeps: int                # k*
+    converged: bool
+
+
+def mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, state=None, want_energy=True,
+                 workspace: torch.Tensor | None = None) -> SimOutput:
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(T_blocks, torch.float32, "T_blocks")
+    H, W = _hw(t)
+    dev = t.device
+    c = cfg.to_c()
+    if state is None:
+        state = torch.empty((cfg.n_real, H, W), dtype=torch.float32, device=dev)
+    else:
+        _dev(state, torch.float32, "state")
+        if tuple(state.shape) != (cfg.n_real, H, W):
+            raise ValueError("state must be [n_real, H, W]")
+    acc = torch.empty((H, W), dtype=torch.float64, device=dev)
+    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    energy = torch.empty(cap, dtype=torch.float64, device=dev) if want_energy else None
+    need = lib().mpr_simulate_workspace_bytes(H, W, lb_h, lb_w, ctypes.byref(c))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    k = _i32(0)
+    st = _check(lib().mpr_simulate(_p(t), _p(mask), H, W, _p(T_blocks), lb_h, lb_w, ctypes.byref(c), _p(state),
+                                   _p(acc), _p(energy), ctypes.byref(k), _p(ws), ws.numel(), _stream()),
+                allow_warn=True)
+    ks = int(k.value)
+    en = energy[: ks + 1] if energy is not None else torch.empty(0, dtype=torch.float64, device=dev)
+    return SimOutput(state=state, acc=acc, energy=en, sweeps=ks, converged=(st == MPR_OK))
+
+
+def mpr_sweep(state, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, k_first: int, n_sweeps: int, want_energy=False,
+              workspace: torch.Tensor | None = None):
+    """Continue the chains in `state` [n_real, H, W] in place with sweeps k_first .. k_first + n_sweeps - 1."""
+    _dev(state, torch.float32, "state")
+    _dev(mask, torch.uint8, "mask")
+    _dev(T_blocks, torch.float32, "T_blocks")
+    H, W = _hw(mask)
+    if tuple(state.shape) != (cfg.n_real, H, W):
+        raise ValueError("state must be [n_real, H, W]")
+    c = cfg.to_c()
+    energy = torch.empty(max(n_sweeps, 1), dtype=torch.float64, device=state.device) if want_energy else None
+    need = lib().mpr_sweep_workspace_bytes(H, W, lb_h, lb_w, ctypes.byref(c))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, state.device)
+    _check(lib().mpr_sweep(_p(state), _p(mask), H, W, _p(T_blocks), lb_h, lb_w, ctypes.byref(c), int(k_first),
+                           int(n_sweeps), _p(energy), _p(ws), ws.numel(), _stream()))
+    return energy[:n_sweeps] if energy is not None else None
+
+
+def mpr_predict(acc, z, mask, n_samples, rng):
+    _dev(acc, torch.float64, "acc")
+    _dev(z, torch.float32, "z")
+    _dev(mask, torch.uint8, "mask")
+    _dev(rng, torch.float64, "range")
+    H, W = _hw(z)
+    zhat = torch.empty_like(z)
+    _check(lib().mpr_predict(_p(acc), _p(z), _p(mask), H, W, int(n_samples), _p(rng), _p(zhat), _stream()))
+    return zhat
+
+
+def mpr_validate(zhat, truth, eval_mask):
+    _dev(zhat, torch.float32, "zhat")
+    _dev(truth, torch.float32, "truth")
+    _dev(eval_mask, torch.uint8, "eval_mask")
+    n = int(zhat.numel())
+    out = torch.empty(2, dtype=torch.float64, device=zhat.device)
+    ws = _ws(lib().mpr_validate_workspace_bytes(n), zhat.device)
+    _check(lib().mpr_validate(_p(zhat), _p(truth), _p(eval_mask), n, _p(out), _p(ws), ws.numel(), _stream()))
+    return out

@@ -1,0 +1,918 @@
+// gfx950 kernels of the SV-MPR conditional simulation (Lach & Zukovic, arXiv 2212.01317).
+//
+// Built with -ffp-contract=off: every FP64 expression that must reproduce the published-formula arithmetic
+// (map, bond energies, the exact Metropolis decision, prediction) is evaluated exactly as written; the FP32 hot
+// path uses explicit fmaf where a fused multiply-add is wanted.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "mpr_internal.hpp"
+#include "philox.hpp"
+
+namespace mpr {
+
+// ------------------------------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------------------------------
+
+// cos / sin of 2 pi x for x in revolutions (gfx950 v_cos_f32 / v_sin_f32; valid for |x| <= 256).
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of one value per thread over a workgroup of NT threads; result valid in thread 0.  Fixed order.
+template <int NT, class T>
+__device__ __forceinline__ T block_sum(T v, T* lds /* NT / 64 entries */)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    T s = T(0);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Sec. 2.1: linear map of the samples onto angles
+// ------------------------------------------------------------------------------------------------------------
+constexpr int MAP_NT = 256;
+
+int map_reduce_blocks(int64_t n)
+{
+    int64_t b = (n + (int64_t)MAP_NT * 16 - 1) / ((int64_t)MAP_NT * 16);
+    return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+__global__ __launch_bounds__(MAP_NT) void k_map_reduce(const float* __restrict__ z, const uint8_t* __restrict__ mask,
+                                                        int64_t n, float* pmin, float* pmax, unsigned long long* pcnt,
+                                                        unsigned long long* pbad)
+{
+    __shared__ float smn[MAP_NT], smx[MAP_NT];
+    __shared__ unsigned long long sc[MAP_NT], sb[MAP_NT];
+    float mn = INFINITY, mx = -INFINITY;
+    unsigned long long cnt = 0, bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * MAP_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * MAP_NT) {
+        if (mask[i]) {
+            const float v = z[i];
+            if (isfinite(v)) {
+                mn = fminf(mn, v);
+                mx = fmaxf(mx, v);
+            } else {
+                ++bad;
+            }
+            ++cnt;
+        }
+    }
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    sc[threadIdx.x] = cnt;
+    sb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = MAP_NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + s]);
+            smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + s]);
+            sc[threadIdx.x] += sc[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pmin[blockIdx.x] = smn[0];
+        pmax[blockIdx.x] = smx[0];
+        pcnt[blockIdx.x] = sc[0];
+        pbad[blockIdx.x] = sb[0];
+    }
+}
+
+__global__ __launch_bounds__(MAP_NT) void k_map_finalize(const float* pmin, const float* pmax,
+                                                          const unsigned long long* pcnt,
+                                                          const unsigned long long* pbad, int nblocks, double* range,
+                                                          unsigned long long* counts)
+{
+    __shared__ float smn[MAP_NT], smx[MAP_NT];
+    __shared__ unsigned long long sc[MAP_NT], sb[MAP_NT];
+    float mn = INFINITY, mx = -INFINITY;
+    unsigned long long cnt = 0, bad = 0;
+    for (int i = threadIdx.x; i < nblocks; i += MAP_NT) {
+        mn = fminf(mn, pmin[i]);
+        mx = fmaxf(mx, pmax[i]);
+        cnt += pcnt[i];
+        bad += pbad[i];
+    }
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    sc[threadIdx.x] = cnt;
+    sb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = MAP_NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + s]);
+            smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + s]);
+            sc[threadIdx.x] += sc[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        range[0] = (double)smn[0];
+        range[1] = (double)smx[0];
+        counts[0] = sc[0];
+        counts[1] = sb[0];
+    }
+}
+
+__global__ __launch_bounds__(MAP_NT) void k_map_apply(const float* __restrict__ z, const uint8_t* __restrict__ mask,
+                                                       int64_t n, const double* __restrict__ range,
+                                                       float* __restrict__ t)
+{
+    const int64_t i = (int64_t)blockIdx.x * MAP_NT + threadIdx.x;
+    if (i >= n) return;
+    const double zmin = range[0];
+    const double span = range[1] - range[0];
+    float v = 0.0f;
+    if (mask[i] && span != 0.0) v = (float)(((double)z[i] - zmin) / span);
+    t[i] = v;
+}
+
+hipError_t launch_map_reduce(const float* z, const uint8_t* mask, int64_t n, float* pmin, float* pmax,
+                             unsigned long long* pcnt, unsigned long long* pbad, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_map_reduce, dim3(nblocks), dim3(MAP_NT), 0, s, z, mask, n, pmin, pmax, pcnt, pbad);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_finalize(const float* pmin, const float* pmax, const unsigned long long* pcnt,
+                               const unsigned long long* pbad, int nblocks, double* range, unsigned long long* counts,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_map_finalize, dim3(1), dim3(MAP_NT), 0, s, pmin, pmax, pcnt, pbad, nblocks, range, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_apply(const float* z, const uint8_t* mask, int64_t n, const double* range, float* t,
+                            hipStream_t s)
+{
+    const int64_t nb = (n + MAP_NT - 1) / MAP_NT;
+    hipLaunchKernelGGL(k_map_apply, dim3((unsigned)nb), dim3(MAP_NT), 0, s, z, mask, n, range, t);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Eq. (2) per T-block (Sec. 2.2.2): sample-bond energies and counts, sample-angle sums and counts.
+// One workgroup per (block, chunk of block rows); a second pass sums the chunks of a block in order.
+// ------------------------------------------------------------------------------------------------------------
+constexpr int STATS_NT = 256;
+
+StatsGeom stats_geom(int64_t H, int64_t W, int lb_h, int lb_w)
+{
+    StatsGeom g;
+    g.H = H;
+    g.W = W;
+    g.lb_h = lb_h;
+    g.lb_w = lb_w;
+    g.nbx = (int)((W + lb_w - 1) / lb_w);
+    g.nby = (int)((H + lb_h - 1) / lb_h);
+    const int64_t ew = lb_w < W ? lb_w : W;
+    const int64_t eh = lb_h < H ? lb_h : H;
+    int64_t G = 4096 / ew;
+    if (G < 1) G = 1;
+    if (G > eh) G = eh;
+    g.G = (int)G;
+    g.nchunk = (int)((eh + G - 1) / G);
+    return g;
+}
+
+__global__ __launch_bounds__(STATS_NT) void k_block_stats(const float* __restrict__ t,
+                                                           const uint8_t* __restrict__ mask, StatsGeom g,
+                                                           double two_pi_q, double J, double* pS, int* pN,
+                                                           double* pTs, int* pNo)
+{
+    __shared__ double lds_d[STATS_NT / 64];
+    __shared__ int lds_i[STATS_NT / 64];
+    const int b = blockIdx.x / g.nchunk, c = blockIdx.x % g.nchunk;
+    const int by = b / g.nbx, bx = b % g.nbx;
+    const int64_t yb = (int64_t)by * g.lb_h;
+    int64_t y_start = yb + (int64_t)c * g.G;
+    int64_t y_end = yb + (int64_t)(c + 1) * g.G;
+    if (y_end > yb + g.lb_h) y_end = yb + g.lb_h;
+    if (y_end > g.H) y_end = g.H;
+    const int64_t x_start = (int64_t)bx * g.lb_w;
+    int64_t x_end = x_start + g.lb_w;
+    if (x_end > g.W) x_end = g.W;
+    const int64_t rows = y_end - y_start, cols = x_end - x_start;
+    double S = 0.0, Ts = 0.0;
+    int N = 0, No = 0;
+    if (rows > 0 && cols > 0) {
+        for (int64_t i = threadIdx.x; i < rows * cols; i += STATS_NT) {
+            const int64_t y = y_start + i / cols, x = x_start + i % cols;
+            const int64_t n = y * g.W + x;
+            if (!mask[n]) continue;
+            const double tn = (double)t[n];
+            Ts += tn;
+            ++No;
+            if (x + 1 < g.W && mask[n + 1]) {
+                S += -J * cos(two_pi_q * (tn - (double)t[n + 1]));
+                ++N;
+            }
+            if (y + 1 < g.H && mask[n + g.W]) {
+                S += -J * cos(two_pi_q * (tn - (double)t[n + g.W]));
+                ++N;
+            }
+        }
+    }
+    S = block_sum<STATS_NT>(S, lds_d);
+    Ts = block_sum<STATS_NT>(Ts, lds_d);
+    N = block_sum<STATS_NT>(N, lds_i);
+    No = block_sum<STATS_NT>(No, lds_i);
+    if (threadIdx.x == 0) {
+        pS[blockIdx.x] = S;
+        pN[blockIdx.x] = N;
+        pTs[blockIdx.x] = Ts;
+        pNo[blockIdx.x] = No;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_stats_final(const double* pS, const int* pN, const double* pTs,
+                                                            const int* pNo, int64_t B, int nchunk, double* S, int* N,
+                                                            double* Ts, int* No)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0, ts = 0.0;
+    int nn = 0, no = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        const int64_t i = b * nchunk + c;
+        s += pS[i];
+        nn += pN[i];
+        ts += pTs[i];
+        no += pNo[i];
+    }
+    if (S) S[b] = s;
+    if (N) N[b] = nn;
+    if (Ts) Ts[b] = ts;
+    if (No) No[b] = no;
+}
+
+hipError_t launch_block_stats(const float* t, const uint8_t* mask, const StatsGeom& g, double two_pi_q, double J,
+                              double* pS, int* pN, double* pTs, int* pNo, double* S, int* N, double* Ts, int* No,
+                              hipStream_t s)
+{
+    const int64_t B = g.B();
+    const int64_t nwg = B * g.nchunk;
+    hipLaunchKernelGGL(k_block_stats, dim3((unsigned)nwg), dim3(STATS_NT), 0, s, t, mask, g, two_pi_q, J, pS, pN,
+                       pTs, pNo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_block_stats_final, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, pS, pN, pTs, pNo, B,
+                       g.nchunk, S, N, Ts, No);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Energy matching (Sec. 2.1, Sec. 2.2.2): inverse of the matching curve, median fill of blocks without bonds.
+// ------------------------------------------------------------------------------------------------------------
+__device__ double curve_inverse(double e, const double* cT, const double* ce, int n)
+{
+    if (e <= -1.0) return 0.0;
+    double prev = ce[0];
+    if (e <= prev) {
+        const double denom = prev + 1.0;
+        return denom > 0.0 ? cT[0] * (e + 1.0) / denom : cT[0];
+    }
+    for (int i = 1; i < n; ++i) {
+        const double cur = ce[i] > prev ? ce[i] : prev;
+        if (cur >= e) {
+            if (cur == prev) return cT[i];
+            const double lam = (e - prev) / (cur - prev);
+            return exp((1.0 - lam) * log(cT[i - 1]) + lam * log(cT[i]));
+        }
+        prev = cur;
+    }
+    return cT[n - 1];
+}
+
+__global__ __launch_bounds__(256) void k_calibrate(const double* S, const int* N, int64_t B, double J,
+                                                    const double* cT, const double* ce, int nc, float* T_out,
+                                                    double* e_out, int* nb_out)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    const int nb = N[b];
+    double e = 0.0;
+    float T = -1.0f;   // marker: filled by the median pass
+    if (nb > 0) {
+        e = S[b] / (J * (double)nb);
+        T = (float)(J * curve_inverse(e, cT, ce, nc));
+    }
+    T_out[b] = T;
+    if (e_out) e_out[b] = e;
+    if (nb_out) nb_out[b] = nb;
+}
+
+constexpr int MED_NT = 1024;
+
+// k-th smallest (0-based) of the T values of blocks with N > 0, by a 4-pass 8-bit radix select on the FP32 bit
+// patterns (T >= 0, so the bit patterns are ordered like the values).
+__device__ float radix_select(const float* T, const int* N, int64_t B, unsigned k, unsigned* hist, unsigned* sh)
+{
+    unsigned prefix = 0u, pmask = 0u;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int i = threadIdx.x; i < 256; i += MED_NT) hist[i] = 0u;
+        __syncthreads();
+        for (int64_t b = threadIdx.x; b < B; b += MED_NT) {
+            if (N[b] > 0) {
+                const unsigned key = __float_as_uint(T[b]);
+                if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned cum = 0u, d = 0u;
+            for (d = 0u; d < 256u; ++d) {
+                if (cum + hist[d] > k) break;
+                cum += hist[d];
+            }
+            sh[0] = prefix | (d << shift);
+            sh[1] = k - cum;
+        }
+        __syncthreads();
+        prefix = sh[0];
+        k = sh[1];
+        pmask |= 255u << shift;
+        __syncthreads();
+    }
+    return __uint_as_float(prefix);
+}
+
+__global__ __launch_bounds__(MED_NT) void k_median_fill(float* T, const int* N, int64_t B, unsigned* n_have)
+{
+    __shared__ unsigned hist[256];
+    __shared__ unsigned sh[2];
+    __shared__ unsigned scount[MED_NT / 64];
+    unsigned cnt = 0;
+    for (int64_t b = threadIdx.x; b < B; b += MED_NT) cnt += N[b] > 0 ? 1u : 0u;
+    cnt = block_sum<MED_NT>(cnt, scount);
+    if (threadIdx.x == 0) sh[0] = cnt;
+    __syncthreads();
+    const unsigned count = sh[0];
+    __syncthreads();
+    if (threadIdx.x == 0) *n_have = count;
+    if (count == 0u) return;
+    const float lo = radix_select(T, N, B, (count - 1u) / 2u, hist, sh);
+    float med = lo;
+    if ((count & 1u) == 0u) {
+        const float hi = radix_select(T, N, B, count / 2u, hist, sh);
+        med = (float)(((double)lo + (double)hi) * 0.5);
+    }
+    for (int64_t b = threadIdx.x; b < B; b += MED_NT)
+        if (N[b] == 0) T[b] = med;
+}
+
+hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, const double* cT, const double* ce,
+                            int nc, float* T_out, double* e_out, int* nb_out, unsigned* n_have, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_calibrate, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, S, N, B, J, cT, ce, nc,
+                       T_out, e_out, nb_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_median_fill, dim3(1), dim3(MED_NT), 0, s, T_out, N, B, n_have);
+    return hipGetLastError();
+}
+
+__global__ void k_global_mean(const double* Ts, const int* No, int64_t B, float* gmean)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double sum = 0.0;
+    long long cnt = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        sum += Ts[b];
+        cnt += No[b];
+    }
+    *gmean = cnt > 0 ? (float)(sum / (double)cnt) : 0.0f;
+}
+
+hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float* gmean, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_global_mean, dim3(1), dim3(64), 0, s, Ts, No, B, gmean);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_tpairs(const float* T, int64_t B, TPair* tp)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    const float Tv = T[b];
+    TPair p;
+    p.T = Tv;
+    p.nl2T = Tv > 0.0f ? (float)(-1.4426950408889634074 / (double)Tv) : 0.0f;
+    tp[b] = p;
+}
+
+hipError_t launch_tpairs(const float* T, int64_t B, TPair* tp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tpairs, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, T, B, tp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Start of the chains (Sec. 3.3): block means of the sample angles (SV-MPR) or uniform draws (MPR).
+// ------------------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init(InitArgs a)
+{
+    const int64_t HW = a.H * a.W;
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (n >= HW) return;
+    const int64_t y = n / a.W, x = n % a.W;
+    float v;
+    if (a.mask[n]) {
+        v = a.t[n];
+    } else if (a.mode == 1) {
+        const int64_t b = (y / a.lb_h) * a.nbx + (x / a.lb_w);
+        v = a.No[b] > 0 ? (float)(a.Ts[b] / (double)a.No[b]) : *a.gmean;
+    } else {
+        const uint32_t Mw = (uint32_t)((a.W + 3) / 4);
+        const uint32_t pair = (uint32_t)y * Mw + (uint32_t)(x >> 2);
+        const uint32_t colour = (uint32_t)((x + y) & 1);
+        const U4 w = philox4x32_10(pair, 0u, a.real_offset + (uint32_t)r, ctr_word3(a.scene, TAG_INIT, colour),
+                                   a.key0, a.key1);
+        v = u24(((x >> 1) & 1) ? w.z : w.x);
+    }
+    a.state[(int64_t)r * HW + n] = v;
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s)
+{
+    const int64_t HW = a.H * a.W;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)((HW + 255) / 256), (unsigned)a.R), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Metropolis decision: FP32 filter with an error band, exact FP64 decision inside the band.
+// ------------------------------------------------------------------------------------------------------------
+
+// Returns 1 = accept, 0 = reject, -1 = inside the error band (the exact FP64 test must decide).
+// dE is the FP32 energy change with |dE - dE_exact| <= delta (absolute).  The exact test is u2 < exp(-dE/T)
+// (T > 0) or dE <= 0 (T == 0).
+__device__ __forceinline__ int metropolis_filter(float dE, TPair tp, float u2, float delta)
+{
+    if (tp.T > 0.0f) {
+        const float y = dE * tp.nl2T;            // log2 of the acceptance ratio
+        if (y >= 1.0f) return 1;                  // ratio >= 2 (1 - O(delta / T)) > u2
+        const float w = exp2_fast(y);
+        // relative error of w: ln 2 * |y - y_exact| + exp2 error, |y - y_exact| <= delta |nl2T| + |y| 2^-22
+        const float rel = 1.25f * (0.6931472f * fmaf(delta, fabsf(tp.nl2T), fabsf(y) * 2.3841858e-7f) + 2.3841858e-7f);
+        if (fabsf(u2 - w) <= fmaf(w, rel, 9.3132257e-10f)) return -1;
+        return u2 < w ? 1 : 0;
+    }
+    if (fabsf(dE) <= delta) return -1;
+    return dE <= 0.0f ? 1 : 0;
+}
+
+// Exact decision, evaluated as the published formula: dE = -J sum_j [cos 2 pi q (t' - t_j) - cos 2 pi q (t - t_j)]
+// over the existing neighbours in the order up, left, right, down; accept iff u2 < exp(-dE / T) (T > 0) or
+// dE <= 0 (T == 0).
+__device__ __noinline__ bool metropolis_exact(float tp, float to, const float* nb, int cnt, double two_pi_q, double J,
+                                              float T, float u2)
+{
+    double acc = 0.0;
+    const double dtp = (double)tp, dto = (double)to;
+    for (int i = 0; i < cnt; ++i) {
+        const double tj = (double)nb[i];
+        acc += cos(two_pi_q * (dtp - tj)) - cos(two_pi_q * (dto - tj));
+    }
+    const double dE = -J * acc;
+    if ((double)T > 0.0) return (double)u2 < exp(-dE / (double)T);
+    return dE <= 0.0;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// One half-sweep (Sec. 2.2.2): every gap site of one colour, in parallel (same-colour sites share no bond).
+// Workgroup = one TW x TH tile of one realization; the tile and a one-site halo of angles are staged in LDS with
+// their (cos, sin) of 2 pi q t; each thread owns one same-colour pair (the two sites of one Philox block).
+// With colour 1 and e_partial set, the workgroup also sums Eq. (1) over the bonds of its colour-1 sites after
+// the update (every bond has exactly one colour-1 end, so the tiles together count each bond once).
+// ------------------------------------------------------------------------------------------------------------
+constexpr int TW = 64, TH = 16, SWEEP_NT = 256;
+constexpr int LW = TW + 2, LH = TH + 2;
+
+void sweep_tiles(int64_t H, int64_t W, int* ntx, int* nty)
+{
+    *ntx = (int)((W + TW - 1) / TW);
+    *nty = (int)((H + TH - 1) / TH);
+}
+
+__global__ __launch_bounds__(SWEEP_NT) void k_sweep_half(SweepArgs a)
+{
+    __shared__ float s_t[LH][LW];
+    __shared__ float2 s_cs[LH][LW];
+    __shared__ int s_bcol[TW];
+    __shared__ int s_brow[TH];
+    __shared__ double s_red[SWEEP_NT / 64];
+
+    const int tile = blockIdx.x;
+    const int r = blockIdx.y;
+    const int tx0 = (tile % a.ntx) * TW, ty0 = (tile / a.ntx) * TH;
+    const int64_t HW = (int64_t)a.H * a.W;
+    float* __restrict__ st = a.state + (int64_t)r * HW;
+
+    for (int i = threadIdx.x; i < LH * LW; i += SWEEP_NT) {
+        const int ly = i / LW, lx = i - ly * LW;
+        const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
+        float v = 0.0f;
+        float2 cs = make_float2(0.0f, 0.0f);
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+            v = st[(int64_t)gy * a.W + gx];
+            const float ang = a.q * v;
+            cs = make_float2(cos_rev(ang), sin_rev(ang));
+        }
+        s_t[ly][lx] = v;
+        s_cs[ly][lx] = cs;
+    }
+    if (threadIdx.x < TW) {
+        const int gx = tx0 + threadIdx.x;
+        s_bcol[threadIdx.x] = gx < a.W ? gx / a.lb_w : 0;
+    } else if (threadIdx.x < TW + TH) {
+        const int gy = ty0 + threadIdx.x - TW;
+        s_brow[threadIdx.x - TW] = gy < a.H ? (gy / a.lb_h) * a.nbx : 0;
+    }
+    __syncthreads();
+
+    const int row = threadIdx.x >> 4, m = threadIdx.x & 15;
+    const int gy = ty0 + row;
+    const int xa = tx0 + 4 * m + ((gy + a.colour) & 1);
+    const bool want_energy = a.e_partial != nullptr;
+    float e_sum = 0.0f;
+    if (gy < a.H && xa < a.W) {
+        const uint32_t pair = (uint32_t)gy * (uint32_t)a.Mw + (uint32_t)(xa >> 2);
+        const U4 w = philox4x32_10(pair, a.sweep, a.real_offset + (uint32_t)r, ctr_word3(a.scene, TAG_SWEEP, a.colour),
+                                   a.key0, a.key1);
+        const int ly = row + 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gx = xa + 2 * h;
+            if (gx >= a.W) break;
+            const int lx = gx - tx0 + 1;
+            const int64_t n = (int64_t)gy * a.W + gx;
+            const bool gap = a.mask[n] == 0;
+            if (!gap && !want_energy) continue;
+            const float2 up = s_cs[ly - 1][lx], lf = s_cs[ly][lx - 1], rt = s_cs[ly][lx + 1], dn = s_cs[ly + 1][lx];
+            const float Cx = ((up.x + lf.x) + rt.x) + dn.x;
+            const float Sy = ((up.y + lf.y) + rt.y) + dn.y;
+            float2 cs = s_cs[ly][lx];
+            if (gap) {
+                const float tp = u24(h ? w.z : w.x);
+                const float u2 = u24(h ? w.w : w.y);
+                const float ang = a.q * tp;
+                const float cp = cos_rev(ang), sp = sin_rev(ang);
+                const float dE = -a.J * fmaf(cp - cs.x, Cx, (sp - cs.y) * Sy);
+                const TPair T = a.Tb[s_brow[row] + s_bcol[gx - tx0]];
+                int dec = metropolis_filter(dE, T, u2, a.delta_e);
+                if (dec < 0) {
+                    float nb[4];
+                    int cnt = 0;
+                    if (gy > 0) nb[cnt++] = s_t[ly - 1][lx];
+                    if (gx > 0) nb[cnt++] = s_t[ly][lx - 1];
+                    if (gx + 1 < a.W) nb[cnt++] = s_t[ly][lx + 1];
+                    if (gy + 1 < a.H) nb[cnt++] = s_t[ly + 1][lx];
+                    dec = metropolis_exact(tp, s_t[ly][lx], nb, cnt, a.two_pi_q, a.Jd, T.T, u2) ? 1 : 0;
+                }
+                if (dec) {
+                    st[n] = tp;
+                    cs = make_float2(cp, sp);
+                }
+            }
+            if (want_energy) e_sum += -a.J * fmaf(cs.x, Cx, cs.y * Sy);
+        }
+    }
+    if (want_energy) {
+        const double tot = block_sum<SWEEP_NT>((double)e_sum, s_red);
+        if (threadIdx.x == 0) a.e_partial[(int64_t)tile * gridDim.y + r] = tot;
+    }
+}
+
+hipError_t launch_sweep_half(const SweepArgs& a, int R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sweep_half, dim3((unsigned)(a.ntx * a.nty), (unsigned)R), dim3(SWEEP_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// Whole-grid energy of the current states (used for e(0)): every site's right and lower bond, FP32 terms,
+// FP64 per-workgroup sums.  partial layout [part][R].
+constexpr int EN_NT = 256;
+
+int energy_full_parts(int64_t H, int64_t W)
+{
+    const int64_t HW = H * W;
+    int64_t p = (HW + EN_NT * 8 - 1) / (EN_NT * 8);
+    return (int)(p < 1 ? 1 : (p > 4096 ? 4096 : p));
+}
+
+__global__ __launch_bounds__(EN_NT) void k_energy_full(const float* __restrict__ state, int64_t H, int64_t W, float q,
+                                                        float J, double* partial)
+{
+    __shared__ double s_red[EN_NT / 64];
+    const int r = blockIdx.y;
+    const int64_t HW = H * W;
+    const float* st = state + (int64_t)r * HW;
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * EN_NT + threadIdx.x; n < HW; n += (int64_t)gridDim.x * EN_NT) {
+        const int64_t y = n / W, x = n - y * W;
+        const float tn = st[n];
+        float e = 0.0f;
+        if (x + 1 < W) e += -J * cos_rev(q * (tn - st[n + 1]));
+        if (y + 1 < H) e += -J * cos_rev(q * (tn - st[n + W]));
+        acc += (double)e;
+    }
+    const double tot = block_sum<EN_NT>(acc, s_red);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + r] = tot;
+}
+
+hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
+                              int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_full, dim3((unsigned)nparts, (unsigned)R), dim3(EN_NT), 0, s, state, H, W, q, J,
+                       partial);
+    return hipGetLastError();
+}
+
+// e_out = mean over realizations of (sum over parts of partial[p][r]) * inv_norm, parts summed in order.
+__global__ __launch_bounds__(256) void k_energy_reduce(const double* partial, int nparts, int R, double inv_norm,
+                                                        double* e_real, double* e_out)
+{
+    for (int r = threadIdx.x; r < R; r += 256) {
+        double s = 0.0;
+        for (int p = 0; p < nparts; ++p) s += partial[(int64_t)p * R + r];
+        e_real[r] = s * inv_norm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int r = 0; r < R; ++r) s += e_real[r];
+        *e_out = s / (double)R;
+    }
+}
+
+hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_out,
+                                hipStream_t s)
+{
+    // e_real scratch lives right after the partials (the caller sizes the buffer nparts * R + R)
+    double* e_real = const_cast<double*>(partial) + (int64_t)nparts * R;
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partial, nparts, R, inv_norm, e_real, e_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Sampling (Sec. 2.1): acc[n] += sum over realizations (in order) of the gap angle; first pass starts from 0.
+// ------------------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_accumulate(const float* __restrict__ state, const uint8_t* __restrict__ mask,
+                                                     int64_t HW, int R, int first, double* __restrict__ acc)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= HW) return;
+    if (mask[n]) {
+        if (first) acc[n] = 0.0;
+        return;
+    }
+    double a = first ? 0.0 : acc[n];
+    for (int r = 0; r < R; ++r) a += (double)state[(int64_t)r * HW + n];
+    acc[n] = a;
+}
+
+hipError_t launch_accumulate(const float* state, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, state, mask, HW, R, first,
+                       acc);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Back-transform of the conditional mean (Sec. 2.1) and the validation measures (Eq. 3, Eq. 4).
+// ------------------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_predict(const double* __restrict__ acc, const float* __restrict__ z,
+                                                  const uint8_t* __restrict__ mask, int64_t n, int64_t n_samples,
+                                                  const double* __restrict__ range, float* __restrict__ zhat)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (mask[i]) {
+        zhat[i] = z[i];
+        return;
+    }
+    const double zmin = range[0], span = range[1] - range[0];
+    const double tbar = acc[i] / (double)n_samples;
+    zhat[i] = (float)(zmin + span * tbar);
+}
+
+hipError_t launch_predict(const double* acc, const float* z, const uint8_t* mask, int64_t n, int64_t n_samples,
+                          const double* range, float* zhat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc, z, mask, n, n_samples,
+                       range, zhat);
+    return hipGetLastError();
+}
+
+constexpr int VAL_NT = 256;
+
+int validate_blocks(int64_t n)
+{
+    int64_t b = (n + VAL_NT * 16 - 1) / (VAL_NT * 16);
+    return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+__global__ __launch_bounds__(VAL_NT) void k_validate_part(const float* __restrict__ zhat,
+                                                           const float* __restrict__ truth,
+                                                           const uint8_t* __restrict__ ev, int64_t n, double* part)
+{
+    __shared__ double s_red[VAL_NT / 64];
+    double sa = 0.0, s2 = 0.0, cnt = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VAL_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VAL_NT) {
+        if (!ev[i]) continue;
+        const double e = (double)truth[i] - (double)zhat[i];
+        sa += fabs(e);
+        s2 += e * e;
+        cnt += 1.0;
+    }
+    sa = block_sum<VAL_NT>(sa, s_red);
+    s2 = block_sum<VAL_NT>(s2, s_red);
+    cnt = block_sum<VAL_NT>(cnt, s_red);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = sa;
+        part[3 * blockIdx.x + 1] = s2;
+        part[3 * blockIdx.x + 2] = cnt;
+    }
+}
+
+__global__ void k_validate_final(const double* part, int nblocks, double* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double sa = 0.0, s2 = 0.0, cnt = 0.0;
+    for (int i = 0; i < nblocks; ++i) {
+        sa += part[3 * i];
+        s2 += part[3 * i + 1];
+        cnt += part[3 * i + 2];
+    }
+    out[0] = cnt > 0.0 ? sa / cnt : 0.0;
+    out[1] = cnt > 0.0 ? sqrt(s2 / cnt) : 0.0;
+}
+
+hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t* ev, int64_t n, double* part,
+                           int nblocks, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_validate_part, dim3(nblocks), dim3(VAL_NT), 0, s, zhat, truth, ev, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_validate_final, dim3(1), dim3(64), 0, s, part, nblocks, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Matching curve: the unconditional MPR model on a periodic L x L lattice, one chain per temperature.
+// ------------------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ref_fill(float* state, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) state[i] = v;
+}
+
+hipError_t launch_ref_fill(float* state, int64_t n, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ref_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, state, n, v);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
+{
+    const int chain = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int L = a.L;
+    if (p >= L * a.Mw) return;
+    const int y = p / a.Mw, m = p - y * a.Mw;
+    const int xa = 4 * m + ((y + a.colour) & 1);
+    if (xa >= L) return;
+    float* st = a.state + (int64_t)chain * L * L;
+    const float T = a.Tgrid[chain];
+    TPair tp;
+    tp.T = T;
+    tp.nl2T = T > 0.0f ? (float)(-1.4426950408889634074 / (double)T) : 0.0f;
+    const U4 w = philox4x32_10((uint32_t)p, a.sweep, (uint32_t)chain, ctr_word3(0u, TAG_REFLAT, a.colour), a.key0,
+                               a.key1);
+    const int yu = (y + L - 1) % L, yd = (y + 1) % L;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int x = xa + 2 * h;
+        if (x >= L) break;
+        const int xl = (x + L - 1) % L, xr = (x + 1) % L;
+        float nb[4];
+        nb[0] = st[yu * L + x];
+        nb[1] = st[y * L + xl];
+        nb[2] = st[y * L + xr];
+        nb[3] = st[yd * L + x];
+        float Cx = 0.0f, Sy = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float ang = a.q * nb[j];
+            Cx += cos_rev(ang);
+            Sy += sin_rev(ang);
+        }
+        const float to = st[y * L + x];
+        const float co = cos_rev(a.q * to), so = sin_rev(a.q * to);
+        const float tpv = u24(h ? w.z : w.x);
+        const float u2 = u24(h ? w.w : w.y);
+        const float cp = cos_rev(a.q * tpv), sp = sin_rev(a.q * tpv);
+        const float dE = -fmaf(cp - co, Cx, (sp - so) * Sy);
+        int dec = metropolis_filter(dE, tp, u2, a.delta_e);
+        if (dec < 0) dec = metropolis_exact(tpv, to, nb, 4, a.two_pi_q, 1.0, T, u2) ? 1 : 0;
+        if (dec) st[y * L + x] = tpv;
+    }
+}
+
+hipError_t launch_ref_half(const RefArgs& a, int nT, hipStream_t s)
+{
+    const int np = a.L * a.Mw;
+    hipLaunchKernelGGL(k_ref_half, dim3((unsigned)((np + 255) / 256), (unsigned)nT), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int ref_energy_parts(int L)
+{
+    const int64_t n = (int64_t)L * L;
+    int64_t p = (n + 256 * 8 - 1) / (256 * 8);
+    return (int)(p < 1 ? 1 : (p > 1024 ? 1024 : p));
+}
+
+__global__ __launch_bounds__(256) void k_ref_energy(const float* __restrict__ state, int L, float q, double* partial)
+{
+    __shared__ double s_red[4];
+    const int chain = blockIdx.y;
+    const float* st = state + (int64_t)chain * L * L;
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < (int64_t)L * L; n += (int64_t)gridDim.x * 256) {
+        const int y = (int)(n / L), x = (int)(n - (int64_t)y * L);
+        const float tn = st[n];
+        const float e = -cos_rev(q * (tn - st[y * L + (x + 1) % L])) - cos_rev(q * (tn - st[((y + 1) % L) * L + x]));
+        acc += (double)e;
+    }
+    const double tot = block_sum<256>(acc, s_red);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + chain] = tot;
+}
+
+hipError_t launch_ref_energy(const float* state, int L, int nT, float q, double* partial, int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ref_energy, dim3((unsigned)nparts, (unsigned)nT), dim3(256), 0, s, state, L, q, partial);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_ref_accumulate(const double* partial, int nparts, int nT, double inv_norm,
+                                                         double* e_sum, int first)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nT) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += partial[(int64_t)p * nT + i];
+    const double e = s * inv_norm;
+    e_sum[i] = first ? e : e_sum[i] + e;
+}
+
+hipError_t launch_ref_accumulate(const double* partial, int nparts, int nT, double inv_norm, double* e_sum, int first,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ref_accumulate, dim3((unsigned)((nT + 255) / 256)), dim3(256), 0, s, partial, nparts, nT,
+                       inv_norm, e_sum, first);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_ref_finish(const double* e_sum, int nT, double n_meas, double* e_out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nT) return;
+    e_out[i] = n_meas > 0.0 ? e_sum[i] / n_meas : 0.0;
+}
+
+hipError_t launch_ref_finish(const double* e_sum, int nT, double n_meas, double* e_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ref_finish, dim3((unsigned)((nT + 255) / 256)), dim3(256), 0, s, e_sum, nT, n_meas, e_out);
+    return hipGetLastError();
+}
+
+}  // namespace mpr

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host API and the kernel launchers of libmpr (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mpr {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Absolute bound on |dE_fp32 - dE_exact| / J for the FP32 Metropolis filter of the sweep kernels.  Derivation:
+// every stored cos/sin of an angle carries at most e = 3.2e-7 absolute error (the gfx950 v_sin/v_cos_f32 error
+// measured exhaustively over [0, 1/2] revolution is 1.25e-7; rounding of q * t adds at most 2 pi * 2^-25);
+// dE/J = -((c' - c) Cx + (s' - s) Sy) with |(c' - c, s' - s)| <= 2 and |(Cx, Sy)| <= 4 accumulates at most
+// 22.6 e + 3.7e-6 including every FP32 rounding; 1.25e-5 leaves margin.
+constexpr float kDeltaE = 1.25e-5f;
+
+// Per-block temperature as the sweep kernels read it.
+struct TPair {
+    float T;       // temperature (0 allowed)
+    float nl2T;    // -log2(e) / T, or 0 when T == 0
+};
+
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t used;
+    size_t cap;
+    template <class T>
+    T* take(size_t count)
+    {
+        size_t off = (used + 255) & ~(size_t)255;
+        used = off + count * sizeof(T);
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_map_reduce(const float* z, const uint8_t* mask, int64_t n, float* pmin, float* pmax,
+                             unsigned long long* pcnt, unsigned long long* pbad, int nblocks, hipStream_t s);
+hipError_t launch_map_finalize(const float* pmin, const float* pmax, const unsigned long long* pcnt,
+                               const unsigned long long* pbad, int nblocks, double* range, unsigned long long* counts,
+                               hipStream_t s);
+hipError_t launch_map_apply(const float* z, const uint8_t* mask, int64_t n, const double* range, float* t,
+                            hipStream_t s);
+int map_reduce_blocks(int64_t n);
+
+struct StatsGeom {
+    int64_t H, W;
+    int lb_h, lb_w, nbx, nby, nchunk, G;
+    int64_t B() const { return (int64_t)nbx * nby; }
+};
+StatsGeom stats_geom(int64_t H, int64_t W, int lb_h, int lb_w);
+hipError_t launch_block_stats(const float* t, const uint8_t* mask, const StatsGeom& g, double two_pi_q, double J,
+                              double* pS, int* pN, double* pTs, int* pNo, double* S, int* N, double* Ts, int* No,
+                              hipStream_t s);
+hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, const double* cT, const double* ce,
+                            int nc, float* T_out, double* e_out, int* nb_out, unsigned* n_have, hipStream_t s);
+hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float* gmean, hipStream_t s);
+hipError_t launch_tpairs(const float* T, int64_t B, TPair* tp, hipStream_t s);
+
+struct InitArgs {
+    float* state;
+    const float* t;
+    const uint8_t* mask;
+    const double* Ts;
+    const int* No;
+    const float* gmean;
+    int64_t H, W;
+    int lb_h, lb_w, nbx;
+    int R;
+    uint32_t real_offset, scene, key0, key1;
+    int mode;
+};
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+
+struct SweepArgs {
+    float* state;
+    const uint8_t* mask;
+    const TPair* Tb;
+    int H, W, lb_h, lb_w, nbx, ntx, nty, Mw;
+    int colour;
+    uint32_t sweep, real_offset, scene, key0, key1;
+    float q, J, delta_e;
+    double two_pi_q, Jd;
+    double* e_partial;   // [R][ntx * nty] when the energy epilogue runs (colour 1), else null
+};
+void sweep_tiles(int64_t H, int64_t W, int* ntx, int* nty);
+hipError_t launch_sweep_half(const SweepArgs& a, int R, hipStream_t s);
+hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
+                              int nparts, hipStream_t s);
+int energy_full_parts(int64_t H, int64_t W);
+hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_out,
+                                hipStream_t s);
+hipError_t launch_accumulate(const float* state, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
+                             hipStream_t s);
+hipError_t launch_predict(const double* acc, const float* z, const uint8_t* mask, int64_t n, int64_t n_samples,
+                          const double* range, float* zhat, hipStream_t s);
+hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t* ev, int64_t n, double* part,
+                           int nblocks, double* out, hipStream_t s);
+int validate_blocks(int64_t n);
+
+struct RefArgs {
+    float* state;          // [nT][L][L]
+    const float* Tgrid;
+    int L, Mw, colour;
+    uint32_t sweep, key0, key1;
+    float q, delta_e;
+    double two_pi_q;
+};
+hipError_t launch_ref_fill(float* state, int64_t n, float v, hipStream_t s);
+hipError_t launch_ref_half(const RefArgs& a, int nT, hipStream_t s);
+hipError_t launch_ref_energy(const float* state, int L, int nT, float q, double* partial, int nparts,
+                             hipStream_t s);
+int ref_energy_parts(int L);
+hipError_t launch_ref_accumulate(const double* partial, int nparts, int nT, double inv_norm, double* e_sum,
+                                 int first, hipStream_t s);
+hipError_t launch_ref_finish(const double* e_sum, int nT, double inv_meas, double* e_out, hipStream_t s);
+
+}  // namespace mpr

@@ -1,0 +1,338 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded inputs.
+
+Bars: integer and index results bit-exact; FP32 angles bit-exact where both sides round the same FP64 value;
+chain states equal at >= 99.99 % of (realization, site) after fixed sweeps (the accept/reject decision is exact in
+FP64 on both sides, so states differ only after an FP64 near-tie); predictions within a mean |delta phi| of 1e-3
+rad; energies within 1e-5 per bond (the kernel sums FP32 bond terms).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import SimConfig as OCfg
+from paper_2212_01317_amd import _lib as M
+from paper_2212_01317_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+STATE_AGREE = 0.9999
+DPHI_MAX = 1e-3
+E_TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def curve():
+    T = np.geomspace(1e-3, 1e2, 31).astype(np.float32)
+    e = oracle.reference_curve(T, L=24, n_therm=200, n_meas=300, seed=21)
+    return T.astype(np.float64), e
+
+
+def gpu_cfg(o: OCfg) -> M.SimConfig:
+    return M.SimConfig(q=o.q, J=o.J, n_real=o.n_real, real_offset=o.real_offset, init_mode=o.init_mode,
+                       stop_mode=o.stop_mode, n_eq=o.n_eq, n_samp=o.n_samp, n_fit=o.n_fit, n_f=o.n_f, n_max=o.n_max,
+                       seed=o.seed, scene_id=o.scene)
+
+
+def run_both(t, mask, T, lb_h, lb_w, ocfg: OCfg):
+    ores = oracle.simulate(t, mask, T, lb_h, lb_w, ocfg)
+    g = M.mpr_simulate(dev(t), dev(mask), dev(np.asarray(T, np.float32)), lb_h, lb_w, gpu_cfg(ocfg))
+    return ores, g
+
+
+def agree_frac(a, b):
+    return float(np.mean(a == b))
+
+
+# ------------------------------------------------------------------------------------------------------------------
+# map, block statistics, calibration, prediction, validation
+# ------------------------------------------------------------------------------------------------------------------
+
+def test_map_parity():
+    rng = np.random.default_rng(1)
+    for H, W in ((1, 1), (3, 70), (97, 131), (256, 200)):
+        z = (rng.standard_normal((H, W)) * 30 + 5).astype(np.float32)
+        m = (rng.random((H, W)) < 0.6).astype(np.uint8)
+        m.ravel()[0] = 1
+        zi = z.copy()
+        zi[m == 0] = np.nan
+        to, ro = oracle.map_angles(zi, m)
+        tg, rg = M.mpr_map_angles(dev(zi), dev(m))
+        assert np.array_equal(host(tg), to)
+        assert np.array_equal(host(rg), ro)
+
+
+def test_map_errors():
+    z = np.ones((8, 8), np.float32)
+    with pytest.raises(M.MprError) as e:
+        M.mpr_map_angles(dev(z), dev(np.zeros((8, 8), np.uint8)))
+    assert e.value.status == 3
+    z[2, 2] = np.inf
+    with pytest.raises(M.MprError) as e:
+        M.mpr_map_angles(dev(z), dev(np.ones((8, 8), np.uint8)))
+    assert e.value.status == 5
+    t, r = M.mpr_map_angles(dev(np.full((5, 7), 3.0, np.float32)), dev(np.ones((5, 7), np.uint8)))
+    assert np.all(host(t) == 0) and host(r).tolist() == [3.0, 3.0]
+
+
+@pytest.mark.parametrize("H,W,lb_h,lb_w", [(97, 131, 16, 12), (64, 64, 64, 64), (33, 29, 1, 1), (1000, 7, 4096, 3)])
+def test_block_stats_parity(H, W, lb_h, lb_w):
+    rng = np.random.default_rng(H * W)
+    t = rng.random((H, W)).astype(np.float32)
+    m = (rng.random((H, W)) < 0.55).astype(np.uint8)
+    So, No, To, Oo = oracle.block_stats(t, m, lb_h, lb_w)
+    Sg, Ng, Tg, Og = (host(x) for x in M.mpr_block_stats(dev(t), dev(m), lb_h, lb_w))
+    assert np.array_equal(Ng, No) and np.array_equal(Og, Oo)
+    assert np.allclose(Sg, So, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Tg, To, rtol=1e-12, atol=1e-12)
+
+
+def _ulp_close_frac(a, b):
+    """Fraction of entries equal; the rest must be within one FP32 ulp."""
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    eq = a == b
+    if not eq.all():
+        ia = a.view(np.int32).astype(np.int64)
+        ib = b.view(np.int32).astype(np.int64)
+        assert np.all(np.abs(ia - ib) <= 1)
+    return float(eq.mean())
+
+
+@pytest.mark.parametrize("which", ["c1_global", "c2_blocks16", "ragged_blocks"])
+def test_calibrate_parity(curve, which):
+    cT, ce = curve
+    if which == "c1_global":
+        sc = synth.config1()
+        lb = sc.block
+    elif which == "c2_blocks16":
+        sc = synth.config2(512, 512)
+        lb = (16, 16)
+    else:
+        sc = synth.random_small(203, 157, 0.7, seed=9)
+        lb = (10, 13)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    To, So, No = oracle.calibrate_temperature(t, sc.mask, lb[0], lb[1], cT, ce)
+    Tg, eg, ng = M.mpr_calibrate_temperature(dev(t), dev(sc.mask), lb[0], lb[1], dev(cT), dev(ce))
+    assert np.array_equal(host(ng), No)
+    assert _ulp_close_frac(host(Tg), To) >= 0.999
+
+
+def test_calibrate_without_bonds_fails(curve):
+    cT, ce = curve
+    m = np.zeros((6, 6), np.uint8)
+    m[::2, ::2] = 1                                 # isolated samples: no sample-sample bond
+    t = np.random.default_rng(0).random((6, 6)).astype(np.float32)
+    with pytest.raises(M.MprError) as e:
+        M.mpr_calibrate_temperature(dev(t), dev(m), 3, 3, dev(cT), dev(ce))
+    assert e.value.status == 4
+
+
+def test_predict_and_validate_parity():
+    rng = np.random.default_rng(5)
+    H, W = 77, 91
+    z = rng.standard_normal((H, W)).astype(np.float32)
+    m = (rng.random((H, W)) < 0.5).astype(np.uint8)
+    acc = np.where(m == 0, rng.random((H, W)) * 37.0, 0.0)
+    r = np.array([-2.5, 3.25])
+    zo = oracle.predict(acc, z, m, 37, r)
+    zg = host(M.mpr_predict(dev(acc), dev(z), dev(m), 37, dev(r)))
+    assert np.array_equal(zg, zo)
+    truth = z + rng.standard_normal((H, W)).astype(np.float32)
+    ev = (1 - m).astype(np.uint8)
+    ao, ro = oracle.validate(zo, truth, ev)
+    out = host(M.mpr_validate(dev(zo), dev(truth), dev(ev)))
+    assert out[0] == pytest.approx(ao, rel=1e-12) and out[1] == pytest.approx(ro, rel=1e-12)
+
+
+# ------------------------------------------------------------------------------------------------------------------
+# starts of the chains (pins the device Philox stream bit-exactly)
+# ------------------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_init_parity(mode):
+    sc = synth.random_small(45, 67, 0.5, seed=3)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T = np.full(((45 + 7) // 8) * ((67 + 7) // 8), 0.1, np.float32)
+    oc = OCfg(n_real=3, real_offset=5, init_mode=mode, stop_mode=0, n_eq=0, n_samp=0, seed=0xDEADBEEF12345, scene=7)
+    o, g = run_both(t, sc.mask, T, 8, 8, oc)
+    assert np.array_equal(host(g.state), o.state)
+    assert np.all(host(g.acc) == 0)
+
+
+# ------------------------------------------------------------------------------------------------------------------
+# the sweep
+# ------------------------------------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1_runs(curve):
+    """Config 1 in full: 128^2 GRF, 33 % uniform gaps, one global T, random start, 100 + 100 sweeps, R = 10."""
+    cT, ce = curve
+    sc = synth.config1()
+    t, rg = oracle.map_angles(sc.z_obs, sc.mask)
+    T, _, _ = oracle.calibrate_temperature(t, sc.mask, 128, 128, cT, ce)
+    oc = OCfg(n_real=10, init_mode=0, stop_mode=0, n_eq=100, n_samp=100, seed=synth.seed_for(1, 2))
+    o, g = run_both(t, sc.mask, T, 128, 128, oc)
+    return sc, t, rg, T, o, g
+
+
+def test_c1_state_parity(c1_runs):
+    sc, t, rg, T, o, g = c1_runs
+    gs = host(g.state)
+    assert g.sweeps == 100 and o.k_star == 100
+    frac = agree_frac(gs, o.state)
+    print(f"c1 state agreement {frac:.7f}, T = {T.ravel()[0]:.5f}")
+    assert frac >= STATE_AGREE
+    obs = sc.mask == 1
+    assert np.all(gs[:, obs] == t[obs])
+
+
+def test_c1_energy_and_prediction_parity(c1_runs):
+    sc, t, rg, T, o, g = c1_runs
+    eg = host(g.energy)
+    assert eg.shape == o.energy.shape
+    assert np.max(np.abs(eg - o.energy)) <= E_TOL
+    n = 10 * 100
+    tbar_o = o.acc / n
+    tbar_g = host(g.acc) / n
+    gap = sc.mask == 0
+    dphi = 2 * math.pi * np.abs(tbar_g[gap] - tbar_o[gap])
+    print(f"c1 mean |dphi| = {dphi.mean():.3e} rad, max {dphi.max():.3e}")
+    assert dphi.mean() <= DPHI_MAX
+    zo = oracle.predict(o.acc, sc.z_obs, sc.mask, n, rg)
+    zg = host(M.mpr_predict(g.acc, dev(sc.z_obs), dev(sc.mask), n, dev(rg)))
+    ao, _ = oracle.validate(zo, sc.z_true, sc.eval_mask)
+    ag, _ = oracle.validate(zg, sc.z_true, sc.eval_mask)
+    print(f"c1 validation MAE oracle {ao:.6f} gpu {ag:.6f}")
+    assert abs(ag - ao) <= 1e-3 * ao
+
+
+@pytest.mark.parametrize("init_mode", [0, 1])
+def test_ragged_blocks_auto_parity(curve, init_mode):
+    cT, ce = curve
+    H, W = 150, 233                       # not multiples of the 64 x 16 tile
+    sc = synth.random_small(H, W, 0.45, seed=11)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T, _, _ = oracle.calibrate_temperature(t, sc.mask, 16, 16, cT, ce)
+    oc = OCfg(n_real=4, init_mode=init_mode, stop_mode=1, n_max=200, n_samp=2, seed=77, scene=3)
+    o, g = run_both(t, sc.mask, T, 16, 16, oc)
+    eg = host(g.energy)
+    print(f"k* oracle {o.k_star} gpu {g.sweeps}")
+    assert np.max(np.abs(eg[: min(len(eg), len(o.energy))] - o.energy[: len(eg)])) <= E_TOL
+    if g.sweeps == o.k_star:
+        assert agree_frac(host(g.state), o.state) >= STATE_AGREE
+    else:
+        # the stop decision may only differ where the oracle's slope test is marginal
+        k = min(g.sweeps, o.k_star)
+        w = o.energy[k - 19: k + 1]
+        beta = oracle.ols_slope(w)
+        assert abs(beta) < 1e-5
+
+
+def test_zero_temperature_and_per_site_blocks(curve):
+    H, W = 40, 50
+    sc = synth.random_small(H, W, 0.5, seed=2)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    rng = np.random.default_rng(0)
+    T = rng.choice(np.array([0.0, 0.02, 0.3], np.float32), size=H * W)      # 1 x 1 blocks, some at T = 0
+    oc = OCfg(n_real=2, init_mode=0, stop_mode=0, n_eq=30, n_samp=1, seed=5)
+    o, g = run_both(t, sc.mask, T, 1, 1, oc)
+    assert agree_frac(host(g.state), o.state) >= STATE_AGREE
+    assert np.max(np.abs(host(g.energy) - o.energy)) <= E_TOL
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 2), (2, 1), (1, 97), (97, 1), (2, 2), (3, 3), (65, 17)])
+def test_tiny_and_thin_grids(H, W):
+    rng = np.random.default_rng(H * 1000 + W)
+    t = rng.random((H, W)).astype(np.float32)
+    m = (rng.random((H, W)) < 0.5).astype(np.uint8)
+    T = np.array([0.2], np.float32)
+    oc = OCfg(n_real=3, init_mode=0, stop_mode=0, n_eq=7, n_samp=2, seed=H + W)
+    o, g = run_both(t, m, T, 4096, 4096, oc)
+    assert np.array_equal(host(g.state), o.state)
+    assert np.max(np.abs(host(g.energy) - o.energy)) <= E_TOL
+
+
+def test_no_gaps_is_identity():
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal((33, 70)).astype(np.float32)
+    m = np.ones((33, 70), np.uint8)
+    t, rg = M.mpr_map_angles(dev(z), dev(m))
+    g = M.mpr_simulate(t, dev(m), dev(np.array([0.1], np.float32)), 64, 128,
+                       M.SimConfig(n_real=2, stop_mode=M.STOP_AUTO, n_max=100, n_samp=1))
+    assert g.sweeps == 25                               # constant energy: equilibrium at the first check
+    assert np.array_equal(host(g.state[0]), host(t)) and np.array_equal(host(g.state[1]), host(t))
+    zh = M.mpr_predict(g.acc, dev(z), dev(m), 2, rg)
+    assert np.array_equal(host(zh), z)
+
+
+def test_realization_subsets_and_determinism():
+    sc = synth.random_small(70, 90, 0.5, seed=8)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T = dev(np.array([0.05, 0.5, 0.1, 0.2], np.float32))
+    base = dict(init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=15, n_samp=1, seed=123)
+    full = M.mpr_simulate(dev(t), dev(sc.mask), T, 35, 45, M.SimConfig(n_real=4, **base))
+    again = M.mpr_simulate(dev(t), dev(sc.mask), T, 35, 45, M.SimConfig(n_real=4, **base))
+    a = M.mpr_simulate(dev(t), dev(sc.mask), T, 35, 45, M.SimConfig(n_real=2, real_offset=0, **base))
+    b = M.mpr_simulate(dev(t), dev(sc.mask), T, 35, 45, M.SimConfig(n_real=2, real_offset=2, **base))
+    fs = host(full.state)
+    assert np.array_equal(fs, host(again.state))
+    assert np.array_equal(host(full.acc), host(again.acc))
+    assert np.array_equal(fs[:2], host(a.state)) and np.array_equal(fs[2:], host(b.state))
+
+
+def test_single_gap_distribution_on_gpu():
+    """3 x 3 grid, one gap: the GPU chain's stationary histogram is the exact Boltzmann density (quadrature)."""
+    from scipy import integrate, stats
+    T0 = 0.35
+    g3 = np.array([[0.2, 0.9, 0.4], [0.1, 0.0, 0.7], [0.3, 0.6, 0.5]], np.float32)
+    m = np.ones((3, 3), np.uint8)
+    m[1, 1] = 0
+    R = 60000
+    g = M.mpr_simulate(dev(g3), dev(m), dev(np.array([T0], np.float32)), 3, 3,
+                       M.SimConfig(n_real=R, init_mode=M.INIT_RANDOM, stop_mode=M.STOP_FIXED, n_eq=60, n_samp=0,
+                                   seed=4242))
+    samp = host(g.state)[:, 1, 1].astype(np.float64)
+    nbr = [0.9, 0.1, 0.7, 0.6]
+    f = lambda x: math.exp(sum(math.cos(math.pi * (x - v)) for v in nbr) / T0)
+    Z = integrate.quad(f, 0, 1)[0]
+    edges = np.linspace(0, 1, 41)
+    probs = np.array([integrate.quad(f, a, b)[0] / Z for a, b in zip(edges[:-1], edges[1:])])
+    cnt, _ = np.histogram(samp, edges)
+    chi2 = np.sum((cnt - R * probs) ** 2 / (R * probs))
+    assert stats.chi2.sf(chi2, 39) > 1e-4
+    # and it is the oracle's chain
+    o = oracle.simulate(g3, m, np.array([T0], np.float32), 3, 3,
+                        OCfg(n_real=2000, init_mode=0, stop_mode=0, n_eq=60, n_samp=0, seed=4242))
+    assert agree_frac(host(g.state)[:2000], o.state) >= STATE_AGREE
+
+
+def test_reference_curve_parity():
+    Tg = np.array([0.003, 0.02, 0.2, 2.0, 50.0], np.float32)
+    eo = oracle.reference_curve(Tg, L=16, n_therm=30, n_meas=40, seed=99)
+    eg = host(M.mpr_reference_curve(dev(Tg), L=16, n_therm=30, n_meas=40, seed=99))
+    print("ref curve", eo, eg)
+    assert np.max(np.abs(eg - eo)) <= 1e-6
+
+
+def test_default_reference_curve_limits():
+    import paper_2212_01317_amd as P
+    cT, ce = P.reference_curve(0.5)
+    T = host(cT)
+    e = host(ce)
+    lo = T < 0.02
+    assert np.all(np.abs(e[lo] - (-1 + T[lo] / 4)) < 0.02 * T[lo] + 1e-5)
+    hi = T > 50
+    assert np.all(np.abs(e[hi] - (-4 / math.pi ** 2 - 0.566064191183 / T[hi])) < 5e-4)
+    assert np.all(np.diff(e[T < 10]) > 0)

@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every entry point include/mpr.h declares; host-side checks reject bad
+arguments before any device work (no GPU needed)."""
+import ctypes
+
+import pytest
+
+from paper_2212_01317_amd import _lib
+
+
+def test_header_symbols_exported():
+    L = _lib.lib()
+    names = _lib.header_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib._SIGS), "binding signatures and header declarations differ"
+
+
+def test_abi_version():
+    assert _lib.lib().mpr_abi_version() == 10000
+
+
+def test_workspace_queries_are_host_only():
+    L = _lib.lib()
+    assert L.mpr_map_workspace_bytes(128, 128) > 0
+    assert L.mpr_block_stats_workspace_bytes(4096, 4096, 32, 32) >= 128 * 128 * 24
+    assert L.mpr_calibrate_workspace_bytes(1024, 1024, 16, 16) > 0
+    assert L.mpr_reference_curve_workspace_bytes(121, 128) >= 121 * 128 * 128 * 4
+    cfg = _lib.SimConfig(n_real=256).to_c()
+    big = L.mpr_simulate_workspace_bytes(4096, 4096, 32, 32, ctypes.byref(cfg))
+    assert big > 0
+    cfg2 = _lib.SimConfig(n_real=512).to_c()
+    assert L.mpr_simulate_workspace_bytes(4096, 4096, 32, 32, ctypes.byref(cfg2)) > big
+    assert L.mpr_validate_workspace_bytes(0) > 0
+
+
+@pytest.mark.parametrize("H,W", [(0, 5), (5, 0), (-1, 3), (1 << 21, 4)])
+def test_bad_shapes_rejected_before_device_work(H, W):
+    L = _lib.lib()
+    st = L.mpr_map_angles(None, None, H, W, None, None, None, 0, None)
+    assert st == 2
+    assert b"grid" in L.mpr_last_error()
+
+
+def test_bad_config_rejected():
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(0x1000)     # never dereferenced: the checks fail first
+    for kw in (dict(q=0.75), dict(J=0.0), dict(n_real=0), dict(init_mode=7), dict(stop_mode=3),
+               dict(stop_mode=_lib.STOP_AUTO, n_fit=1), dict(scene_id=1 << 28)):
+        cfg = _lib.SimConfig(**kw).to_c()
+        st = L.mpr_simulate(dummy, dummy, 8, 8, dummy, 4, 4, ctypes.byref(cfg), dummy, dummy, None, None, dummy,
+                            1 << 30, None)
+        assert st == 1, kw
+    cfg = _lib.SimConfig().to_c()
+    st = L.mpr_simulate(dummy, dummy, 8, 8, dummy, 4, 4, ctypes.byref(cfg), dummy, dummy, None, None, dummy, 16, None)
+    assert st == 6      # workspace too small
+    st = L.mpr_simulate(dummy, dummy, 8, 8, dummy, 0, 4, ctypes.byref(cfg), dummy, dummy, None, None, dummy, 16, None)
+    assert st == 2      # bad block
+
+
+def test_reference_curve_rejects_odd_lattice():
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.mpr_reference_curve(0.5, dummy, 4, 15, 10, 10, 0, dummy, dummy, 1 << 30, None) == 2
+    assert L.mpr_reference_curve(0.6, dummy, 4, 16, 10, 10, 0, dummy, dummy, 1 << 30, None) == 1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        _lib.mpr_map_angles(torch.zeros(4, 4), torch.ones(4, 4, dtype=torch.uint8))
