@@ -124,6 +124,7 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
  *   is taken; equilibrium when beta * sign(e(k) - e(0)) <= 0; the cap n_max gives MPR_WARN_NOT_CONVERGED.
  *   Then n_samp sampling sweeps (k* + 1 ...), after each of which every realization's gap angles are added to
  *   acc_out in realization order (FP64; samples' entries are 0).
+ * The workspace holds a second state buffer of n_real*H*W floats (the sweep reads one buffer and writes the other).
  * Outputs: state[n_real*H*W] (float; in: ignored, out: final states), acc_out[H*W] (double), energy_out[k* + 1]
  * (double, optional NULL; size n_max + 1 for AUTO, n_eq + 1 for FIXED), *sweeps_done_out = k* (host, optional).
  * FIXED mode is asynchronous; AUTO synchronises the stream at every check.  Workspace:
@@ -134,15 +135,18 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
                         double* energy_out, int32_t* sweeps_done_out, void* workspace, size_t ws_bytes,
                         void* stream);
 
-/* Continuation of chains: sweeps k_first .. k_first + n_sweeps - 1 (the sweep counter keys the random stream) on
- * `state` [n_real*H*W] in place, with exactly the per-sweep arithmetic of mpr_simulate (no start, no stopping rule,
- * no accumulation).  Uses cfg->q, J, n_real, real_offset, seed, scene_id.  Resuming a saved state with the next
- * sweep counter reproduces an uninterrupted run bit for bit.  energy_out[n_sweeps] (optional): the
- * realization-averaged energy per bond after each sweep.  Asynchronous.  Workspace: mpr_sweep_workspace_bytes. */
+/* Continuation of chains: sweeps k_first .. k_first + n_sweeps - 1 (the sweep counter keys the random stream) with
+ * exactly the per-sweep arithmetic of mpr_simulate (no start, no stopping rule, no accumulation).  The sweeps
+ * alternate between two buffers [n_real*H*W]: sweep k_first reads `state` and writes `state_alt`, the next one reads
+ * `state_alt` and writes `state`, and so on, so the result is in `state` when n_sweeps is even and in `state_alt`
+ * when it is odd.  Both buffers must hold the same sample angles (e.g. state_alt a copy of state); only gap cells
+ * are written.  Uses cfg->q, J, n_real, real_offset, seed, scene_id.  Resuming a saved state with the next sweep
+ * counter reproduces an uninterrupted run bit for bit.  energy_out[n_sweeps] (optional): the realization-averaged
+ * energy per bond after each sweep.  Asynchronous.  Workspace: mpr_sweep_workspace_bytes. */
 size_t mpr_sweep_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg);
-mpr_status mpr_sweep(float* state, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks, int32_t lb_h,
-                     int32_t lb_w, const mpr_sim_config* cfg, int32_t k_first, int32_t n_sweeps, double* energy_out,
-                     void* workspace, size_t ws_bytes, void* stream);
+mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks,
+                     int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, int32_t k_first, int32_t n_sweeps,
+                     double* energy_out, void* workspace, size_t ws_bytes, void* stream);
 
 /* Prediction (Sec. 2.1, last step): at gaps zhat = fl32(zmin + (zmax - zmin) * acc / n_samples) with
  * range = {zmin, zmax} from mpr_map_angles; at samples zhat = z.  Asynchronous. */

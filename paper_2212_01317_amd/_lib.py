@@ -84,8 +84,8 @@ _SIGS = {
     "mpr_simulate": ([_vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _vp, _vp, _vp,
                       ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
     "mpr_sweep_workspace_bytes": ([_i64, _i64, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
-    "mpr_sweep": ([_vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _i32, _i32, _vp, _vp, _sz,
-                   _vp], ctypes.c_int),
+    "mpr_sweep": ([_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _i32, _i32, _vp, _vp,
+                   _sz, _vp], ctypes.c_int),
     "mpr_predict": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "mpr_validate_workspace_bytes": ([_i64], _sz),
     "mpr_validate": ([_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -244,20 +244,30 @@ def mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, state=None, want
 
 
 def mpr_sweep(state, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, k_first: int, n_sweeps: int, want_energy=False,
-              workspace: torch.Tensor | None = None):
-    """Continue the chains in `state` [n_real, H, W] in place with sweeps k_first .. k_first + n_sweeps - 1."""
+              state_alt: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Continue the chains in `state` [n_real, H, W] with sweeps k_first .. k_first + n_sweeps - 1.  The kernels
+    alternate between `state` and `state_alt` (a copy of `state` is made when it is not given); the result is
+    copied back into `state` when it ends in `state_alt`.  Returns the energies after each sweep (or None)."""
     _dev(state, torch.float32, "state")
     _dev(mask, torch.uint8, "mask")
     _dev(T_blocks, torch.float32, "T_blocks")
     H, W = _hw(mask)
     if tuple(state.shape) != (cfg.n_real, H, W):
         raise ValueError("state must be [n_real, H, W]")
+    if state_alt is None:
+        state_alt = state.clone()
+    else:
+        _dev(state_alt, torch.float32, "state_alt")
+        if state_alt.shape != state.shape:
+            raise ValueError("state_alt must have the shape of state")
     c = cfg.to_c()
     energy = torch.empty(max(n_sweeps, 1), dtype=torch.float64, device=state.device) if want_energy else None
     need = lib().mpr_sweep_workspace_bytes(H, W, lb_h, lb_w, ctypes.byref(c))
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, state.device)
-    _check(lib().mpr_sweep(_p(state), _p(mask), H, W, _p(T_blocks), lb_h, lb_w, ctypes.byref(c), int(k_first),
-                           int(n_sweeps), _p(energy), _p(ws), ws.numel(), _stream()))
+    _check(lib().mpr_sweep(_p(state), _p(state_alt), _p(mask), H, W, _p(T_blocks), lb_h, lb_w, ctypes.byref(c),
+                           int(k_first), int(n_sweeps), _p(energy), _p(ws), ws.numel(), _stream()))
+    if n_sweeps % 2 == 1:
+        state.copy_(state_alt)
     return energy[:n_sweeps] if energy is not None else None
 
 

@@ -117,15 +117,18 @@ size_t cal_ws(Carve& c, const mpr::StatsGeom& g, CalWs* w)
     return c.used;
 }
 
+int fused_tiles(int64_t H, int64_t W, int R);
+
 struct SimWs {
     StatsWs st;
     double* Ts;
     int* No;
     float* gmean;
     mpr::TPair* tp;
-    double* epart;      // [max(ntiles, nfull)] x R partials + R
+    double* epart;      // [R][max(ntiles, nfull)]
+    double* e_real;     // [R]
     double* series;     // [cap + 1]
-    int nparts_max;
+    float* alt;         // [R][H][W] second state buffer
 };
 size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SimWs* w)
 {
@@ -136,14 +139,14 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     x.No = c.take<int>(g.B());
     x.gmean = c.take<float>(1);
     x.tp = c.take<mpr::TPair>(g.B());
-    int ntx, nty;
-    mpr::sweep_tiles(H, W, &ntx, &nty);
-    const int nfull = mpr::energy_full_parts(H, W);
-    x.nparts_max = ntx * nty > nfull ? ntx * nty : nfull;
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
-    x.epart = c.take<double>((int64_t)x.nparts_max * R + R);
+    const int nt = fused_tiles(H, W, (int)R);
+    const int nfull = mpr::energy_full_parts(H, W);
+    x.epart = c.take<double>((int64_t)(nt > nfull ? nt : nfull) * R);
+    x.e_real = c.take<double>(R);
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
+    x.alt = c.take<float>(R * H * W);
     if (w) *w = x;
     return c.used;
 }
@@ -208,21 +211,23 @@ mpr_status check_sim_config(const mpr_sim_config& c)
     return MPR_OK;
 }
 
-// Runs red/black sweeps with the per-block temperatures already converted to TPairs.
+// Runs fused sweeps (one launch per sweep) alternating between two state buffers.
 struct SweepRunner {
-    mpr::SweepArgs a;
-    int R;
-    int ntiles;
+    mpr::SweepFusedArgs a;
+    float* buf[2];
+    int cur;
     double inv_norm;
-    double* epart;
+    double* epart;     // [R][ntiles]
+    double* e_real;    // [R]
     hipStream_t s;
 
-    SweepRunner(float* state, const uint8_t* mask, int64_t H, int64_t W, const mpr::TPair* tp, int32_t lb_h,
-                int32_t lb_w, const mpr_sim_config& c, double* epart_, hipStream_t s_)
+    SweepRunner(float* state, float* alt, const uint8_t* mask, int64_t H, int64_t W, const mpr::TPair* tp,
+                int32_t lb_h, int32_t lb_w, const mpr_sim_config& c, double* epart_, double* e_real_, hipStream_t s_)
     {
-        int ntx, nty;
-        mpr::sweep_tiles(H, W, &ntx, &nty);
-        a.state = state;
+        int ntx, nty, rchunk, nchunks;
+        mpr::fused_geometry(H, W, c.n_real, &ntx, &nty, &rchunk, &nchunks);
+        a.src = state;
+        a.dst = alt;
         a.mask = mask;
         a.Tb = tp;
         a.H = (int)H;
@@ -232,7 +237,12 @@ struct SweepRunner {
         a.nbx = (int)((W + lb_w - 1) / lb_w);
         a.ntx = ntx;
         a.nty = nty;
+        a.ntiles = ntx * nty;
         a.Mw = (int)((W + 3) / 4);
+        a.R = c.n_real;
+        a.rchunk = rchunk;
+        a.nchunks = nchunks;
+        a.HW = H * W;
         a.real_offset = (uint32_t)c.real_offset;
         a.scene = c.scene_id;
         a.key0 = (uint32_t)(c.seed & 0xffffffffu);
@@ -243,43 +253,52 @@ struct SweepRunner {
         a.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
         a.Jd = (double)c.J;
         a.e_partial = nullptr;
-        R = c.n_real;
-        ntiles = ntx * nty;
+        buf[0] = state;
+        buf[1] = alt;
+        cur = 0;
         const int64_t nbonds = H * (W - 1) + W * (H - 1);
         inv_norm = nbonds > 0 ? 1.0 / ((double)c.J * (double)nbonds) : 0.0;
         epart = epart_;
+        e_real = e_real_;
         s = s_;
     }
 
-    // one sweep (colour 0 then colour 1); with e_dst set, e(k) is written there
+    float* current() const { return buf[cur]; }
+
+    // one sweep k; with e_dst set, e(k) is written there
     hipError_t run(uint32_t k, double* e_dst)
     {
         a.sweep = k;
-        a.colour = 0;
-        a.e_partial = nullptr;
-        hipError_t e = mpr::launch_sweep_half(a, R, s);
-        if (e != hipSuccess) return e;
-        a.colour = 1;
+        a.src = buf[cur];
+        a.dst = buf[cur ^ 1];
         a.e_partial = e_dst ? epart : nullptr;
-        e = mpr::launch_sweep_half(a, R, s);
+        hipError_t e = mpr::launch_sweep_fused(a, s);
         if (e != hipSuccess) return e;
-        if (e_dst) e = mpr::launch_energy_reduce(epart, ntiles, R, inv_norm, e_dst, s);
+        cur ^= 1;
+        if (e_dst) e = mpr::launch_energy_reduce(epart, a.ntiles, a.R, inv_norm, e_real, e_dst, s);
         return e;
     }
 };
 
+int fused_tiles(int64_t H, int64_t W, int R)
+{
+    int ntx, nty, rc, nc;
+    mpr::fused_geometry(H, W, R, &ntx, &nty, &rc, &nc);
+    return ntx * nty;
+}
+
 struct SweepWs {
     mpr::TPair* tp;
     double* epart;
+    double* e_real;
 };
 size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SweepWs* w)
 {
     SweepWs x;
     x.tp = c.take<mpr::TPair>(nblocks_of(H, W, lb_h, lb_w));
-    int ntx, nty;
-    mpr::sweep_tiles(H, W, &ntx, &nty);
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
-    x.epart = c.take<double>((int64_t)ntx * nty * R + R);
+    x.epart = c.take<double>((int64_t)fused_tiles(H, W, (int)R) * R);
+    x.e_real = c.take<double>(R);
     if (w) *w = x;
     return c.used;
 }
@@ -483,6 +502,7 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     }
     mpr::InitArgs ia;
     ia.state = state;
+    ia.state2 = w.alt;
     ia.t = t;
     ia.mask = mask;
     ia.Ts = w.Ts;
@@ -503,11 +523,11 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     MPR_HIP(mpr::launch_tpairs(T_blocks, B, w.tp, s));
 
     const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
-    SweepRunner runner(state, mask, H, W, w.tp, lb_h, lb_w, c, w.epart, s);
+    SweepRunner runner(state, w.alt, mask, H, W, w.tp, lb_h, lb_w, c, w.epart, w.e_real, s);
     if (need_energy) {
         const int nfull = mpr::energy_full_parts(H, W);
         MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
-        MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.series, s));
+        MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series, s));
     }
     auto sweep = [&](uint32_t k, bool energy) -> hipError_t { return runner.run(k, energy ? w.series + k : nullptr); };
 
@@ -539,7 +559,10 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     }
     for (int32_t si = 1; si <= c.n_samp; ++si) {
         MPR_HIP(sweep((uint32_t)(k_star + si), false));
-        MPR_HIP(mpr::launch_accumulate(state, mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
+        MPR_HIP(mpr::launch_accumulate(runner.current(), mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
+    }
+    if (runner.current() != state) {
+        MPR_HIP(hipMemcpyAsync(state, runner.current(), sizeof(float) * (size_t)(R * HW), hipMemcpyDeviceToDevice, s));
     }
     if (energy_out && need_energy) {
         MPR_HIP(hipMemcpyAsync(energy_out, w.series, sizeof(double) * (size_t)(k_star + 1), hipMemcpyDeviceToDevice,
@@ -557,15 +580,16 @@ size_t mpr_sweep_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_
     return sweep_ws(c, H, W, lb_h, lb_w, cfg, nullptr);
 }
 
-mpr_status mpr_sweep(float* state, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks, int32_t lb_h,
-                     int32_t lb_w, const mpr_sim_config* cfg, int32_t k_first, int32_t n_sweeps, double* energy_out,
-                     void* workspace, size_t ws_bytes, void* stream)
+mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks,
+                     int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, int32_t k_first, int32_t n_sweeps,
+                     double* energy_out, void* workspace, size_t ws_bytes, void* stream)
 {
     mpr_status st = check_grid(H, W);
     if (st != MPR_OK) return st;
     if ((st = check_blocks(H, W, lb_h, lb_w)) != MPR_OK) return st;
     if (!cfg) return fail(MPR_ERR_INVALID_ARG, "cfg is NULL");
-    if (!state || !mask || !T_blocks) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: NULL pointer");
+    if (!state || !state_alt || !mask || !T_blocks) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: NULL pointer");
+    if (state == state_alt) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: state and state_alt must be distinct buffers");
     if ((st = check_sim_config(*cfg)) != MPR_OK) return st;
     if (k_first < 1 || n_sweeps < 0) return fail(MPR_ERR_INVALID_ARG, "need k_first >= 1 and n_sweeps >= 0");
     st = check_ws(workspace, ws_bytes, mpr_sweep_workspace_bytes(H, W, lb_h, lb_w, cfg));
@@ -575,7 +599,7 @@ mpr_status mpr_sweep(float* state, const uint8_t* mask, int64_t H, int64_t W, co
     SweepWs w;
     sweep_ws(cv, H, W, lb_h, lb_w, cfg, &w);
     MPR_HIP(mpr::launch_tpairs(T_blocks, nblocks_of(H, W, lb_h, lb_w), w.tp, s));
-    SweepRunner runner(state, mask, H, W, w.tp, lb_h, lb_w, *cfg, w.epart, s);
+    SweepRunner runner(state, state_alt, mask, H, W, w.tp, lb_h, lb_w, *cfg, w.epart, w.e_real, s);
     for (int32_t i = 0; i < n_sweeps; ++i)
         MPR_HIP(runner.run((uint32_t)(k_first + i), energy_out ? energy_out + i : nullptr));
     return ok();

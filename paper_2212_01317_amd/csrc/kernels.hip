@@ -9,19 +9,13 @@
 #include <cmath>
 #include <cstdint>
 
-#include "mpr_internal.hpp"
-#include "philox.hpp"
+#include "metropolis.hpp"
 
 namespace mpr {
 
 // ------------------------------------------------------------------------------------------------------------
 // small device helpers
 // ------------------------------------------------------------------------------------------------------------
-
-// cos / sin of 2 pi x for x in revolutions (gfx950 v_cos_f32 / v_sin_f32; valid for |x| <= 256).
-__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
-__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
-__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v)
@@ -457,6 +451,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
         v = u24(((x >> 1) & 1) ? w.z : w.x);
     }
     a.state[(int64_t)r * HW + n] = v;
+    if (a.state2) a.state2[(int64_t)r * HW + n] = v;
 }
 
 hipError_t launch_init(const InitArgs& a, hipStream_t s)
@@ -466,158 +461,8 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------------------------------------------
-// Metropolis decision: FP32 filter with an error band, exact FP64 decision inside the band.
-// ------------------------------------------------------------------------------------------------------------
-
-// Returns 1 = accept, 0 = reject, -1 = inside the error band (the exact FP64 test must decide).
-// dE is the FP32 energy change with |dE - dE_exact| <= delta (absolute).  The exact test is u2 < exp(-dE/T)
-// (T > 0) or dE <= 0 (T == 0).
-__device__ __forceinline__ int metropolis_filter(float dE, TPair tp, float u2, float delta)
-{
-    if (tp.T > 0.0f) {
-        const float y = dE * tp.nl2T;            // log2 of the acceptance ratio
-        if (y >= 1.0f) return 1;                  // ratio >= 2 (1 - O(delta / T)) > u2
-        const float w = exp2_fast(y);
-        // relative error of w: ln 2 * |y - y_exact| + exp2 error, |y - y_exact| <= delta |nl2T| + |y| 2^-22
-        const float rel = 1.25f * (0.6931472f * fmaf(delta, fabsf(tp.nl2T), fabsf(y) * 2.3841858e-7f) + 2.3841858e-7f);
-        if (fabsf(u2 - w) <= fmaf(w, rel, 9.3132257e-10f)) return -1;
-        return u2 < w ? 1 : 0;
-    }
-    if (fabsf(dE) <= delta) return -1;
-    return dE <= 0.0f ? 1 : 0;
-}
-
-// Exact decision, evaluated as the published formula: dE = -J sum_j [cos 2 pi q (t' - t_j) - cos 2 pi q (t - t_j)]
-// over the existing neighbours in the order up, left, right, down; accept iff u2 < exp(-dE / T) (T > 0) or
-// dE <= 0 (T == 0).
-__device__ __noinline__ bool metropolis_exact(float tp, float to, const float* nb, int cnt, double two_pi_q, double J,
-                                              float T, float u2)
-{
-    double acc = 0.0;
-    const double dtp = (double)tp, dto = (double)to;
-    for (int i = 0; i < cnt; ++i) {
-        const double tj = (double)nb[i];
-        acc += cos(two_pi_q * (dtp - tj)) - cos(two_pi_q * (dto - tj));
-    }
-    const double dE = -J * acc;
-    if ((double)T > 0.0) return (double)u2 < exp(-dE / (double)T);
-    return dE <= 0.0;
-}
-
-// ------------------------------------------------------------------------------------------------------------
-// One half-sweep (Sec. 2.2.2): every gap site of one colour, in parallel (same-colour sites share no bond).
-// Workgroup = one TW x TH tile of one realization; the tile and a one-site halo of angles are staged in LDS with
-// their (cos, sin) of 2 pi q t; each thread owns one same-colour pair (the two sites of one Philox block).
-// With colour 1 and e_partial set, the workgroup also sums Eq. (1) over the bonds of its colour-1 sites after
-// the update (every bond has exactly one colour-1 end, so the tiles together count each bond once).
-// ------------------------------------------------------------------------------------------------------------
-constexpr int TW = 64, TH = 16, SWEEP_NT = 256;
-constexpr int LW = TW + 2, LH = TH + 2;
-
-void sweep_tiles(int64_t H, int64_t W, int* ntx, int* nty)
-{
-    *ntx = (int)((W + TW - 1) / TW);
-    *nty = (int)((H + TH - 1) / TH);
-}
-
-__global__ __launch_bounds__(SWEEP_NT) void k_sweep_half(SweepArgs a)
-{
-    __shared__ float s_t[LH][LW];
-    __shared__ float2 s_cs[LH][LW];
-    __shared__ int s_bcol[TW];
-    __shared__ int s_brow[TH];
-    __shared__ double s_red[SWEEP_NT / 64];
-
-    const int tile = blockIdx.x;
-    const int r = blockIdx.y;
-    const int tx0 = (tile % a.ntx) * TW, ty0 = (tile / a.ntx) * TH;
-    const int64_t HW = (int64_t)a.H * a.W;
-    float* __restrict__ st = a.state + (int64_t)r * HW;
-
-    for (int i = threadIdx.x; i < LH * LW; i += SWEEP_NT) {
-        const int ly = i / LW, lx = i - ly * LW;
-        const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
-        float v = 0.0f;
-        float2 cs = make_float2(0.0f, 0.0f);
-        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
-            v = st[(int64_t)gy * a.W + gx];
-            const float ang = a.q * v;
-            cs = make_float2(cos_rev(ang), sin_rev(ang));
-        }
-        s_t[ly][lx] = v;
-        s_cs[ly][lx] = cs;
-    }
-    if (threadIdx.x < TW) {
-        const int gx = tx0 + threadIdx.x;
-        s_bcol[threadIdx.x] = gx < a.W ? gx / a.lb_w : 0;
-    } else if (threadIdx.x < TW + TH) {
-        const int gy = ty0 + threadIdx.x - TW;
-        s_brow[threadIdx.x - TW] = gy < a.H ? (gy / a.lb_h) * a.nbx : 0;
-    }
-    __syncthreads();
-
-    const int row = threadIdx.x >> 4, m = threadIdx.x & 15;
-    const int gy = ty0 + row;
-    const int xa = tx0 + 4 * m + ((gy + a.colour) & 1);
-    const bool want_energy = a.e_partial != nullptr;
-    float e_sum = 0.0f;
-    if (gy < a.H && xa < a.W) {
-        const uint32_t pair = (uint32_t)gy * (uint32_t)a.Mw + (uint32_t)(xa >> 2);
-        const U4 w = philox4x32_10(pair, a.sweep, a.real_offset + (uint32_t)r, ctr_word3(a.scene, TAG_SWEEP, a.colour),
-                                   a.key0, a.key1);
-        const int ly = row + 1;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int gx = xa + 2 * h;
-            if (gx >= a.W) break;
-            const int lx = gx - tx0 + 1;
-            const int64_t n = (int64_t)gy * a.W + gx;
-            const bool gap = a.mask[n] == 0;
-            if (!gap && !want_energy) continue;
-            const float2 up = s_cs[ly - 1][lx], lf = s_cs[ly][lx - 1], rt = s_cs[ly][lx + 1], dn = s_cs[ly + 1][lx];
-            const float Cx = ((up.x + lf.x) + rt.x) + dn.x;
-            const float Sy = ((up.y + lf.y) + rt.y) + dn.y;
-            float2 cs = s_cs[ly][lx];
-            if (gap) {
-                const float tp = u24(h ? w.z : w.x);
-                const float u2 = u24(h ? w.w : w.y);
-                const float ang = a.q * tp;
-                const float cp = cos_rev(ang), sp = sin_rev(ang);
-                const float dE = -a.J * fmaf(cp - cs.x, Cx, (sp - cs.y) * Sy);
-                const TPair T = a.Tb[s_brow[row] + s_bcol[gx - tx0]];
-                int dec = metropolis_filter(dE, T, u2, a.delta_e);
-                if (dec < 0) {
-                    float nb[4];
-                    int cnt = 0;
-                    if (gy > 0) nb[cnt++] = s_t[ly - 1][lx];
-                    if (gx > 0) nb[cnt++] = s_t[ly][lx - 1];
-                    if (gx + 1 < a.W) nb[cnt++] = s_t[ly][lx + 1];
-                    if (gy + 1 < a.H) nb[cnt++] = s_t[ly + 1][lx];
-                    dec = metropolis_exact(tp, s_t[ly][lx], nb, cnt, a.two_pi_q, a.Jd, T.T, u2) ? 1 : 0;
-                }
-                if (dec) {
-                    st[n] = tp;
-                    cs = make_float2(cp, sp);
-                }
-            }
-            if (want_energy) e_sum += -a.J * fmaf(cs.x, Cx, cs.y * Sy);
-        }
-    }
-    if (want_energy) {
-        const double tot = block_sum<SWEEP_NT>((double)e_sum, s_red);
-        if (threadIdx.x == 0) a.e_partial[(int64_t)tile * gridDim.y + r] = tot;
-    }
-}
-
-hipError_t launch_sweep_half(const SweepArgs& a, int R, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sweep_half, dim3((unsigned)(a.ntx * a.nty), (unsigned)R), dim3(SWEEP_NT), 0, s, a);
-    return hipGetLastError();
-}
-
 // Whole-grid energy of the current states (used for e(0)): every site's right and lower bond, FP32 terms,
-// FP64 per-workgroup sums.  partial layout [part][R].
+// FP64 per-workgroup sums.  partial layout [R][part].
 constexpr int EN_NT = 256;
 
 int energy_full_parts(int64_t H, int64_t W)
@@ -644,7 +489,7 @@ __global__ __launch_bounds__(EN_NT) void k_energy_full(const float* __restrict__
         acc += (double)e;
     }
     const double tot = block_sum<EN_NT>(acc, s_red);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + r] = tot;
+    if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = tot;
 }
 
 hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
@@ -655,29 +500,35 @@ hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, f
     return hipGetLastError();
 }
 
-// e_out = mean over realizations of (sum over parts of partial[p][r]) * inv_norm, parts summed in order.
-__global__ __launch_bounds__(256) void k_energy_reduce(const double* partial, int nparts, int R, double inv_norm,
-                                                        double* e_real, double* e_out)
+// e_real[r] = (sum over parts of partial[r][p]) * inv_norm, one workgroup per realization, fixed order;
+// then e_out = mean over realizations (in order).
+__global__ __launch_bounds__(256) void k_energy_real(const double* __restrict__ partial, int nparts, double inv_norm,
+                                                      double* e_real)
 {
-    for (int r = threadIdx.x; r < R; r += 256) {
-        double s = 0.0;
-        for (int p = 0; p < nparts; ++p) s += partial[(int64_t)p * R + r];
-        e_real[r] = s * inv_norm;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int r = 0; r < R; ++r) s += e_real[r];
-        *e_out = s / (double)R;
-    }
+    __shared__ double s_red[4];
+    const int r = blockIdx.x;
+    const double* row = partial + (int64_t)r * nparts;
+    double s = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += 256) s += row[p];
+    s = block_sum<256>(s, s_red);
+    if (threadIdx.x == 0) e_real[r] = s * inv_norm;
 }
 
-hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_out,
-                                hipStream_t s)
+__global__ void k_energy_mean(const double* e_real, int R, double* e_out)
 {
-    // e_real scratch lives right after the partials (the caller sizes the buffer nparts * R + R)
-    double* e_real = const_cast<double*>(partial) + (int64_t)nparts * R;
-    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partial, nparts, R, inv_norm, e_real, e_out);
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) s += e_real[r];
+    *e_out = s / (double)R;
+}
+
+hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_real,
+                                double* e_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_real, dim3((unsigned)R), dim3(256), 0, s, partial, nparts, inv_norm, e_real);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_energy_mean, dim3(1), dim3(64), 0, s, e_real, R, e_out);
     return hipGetLastError();
 }
 
@@ -815,7 +666,7 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
     TPair tp;
     tp.T = T;
     tp.nl2T = T > 0.0f ? (float)(-1.4426950408889634074 / (double)T) : 0.0f;
-    const U4 w = philox4x32_10((uint32_t)p, a.sweep, (uint32_t)chain, ctr_word3(0u, TAG_REFLAT, a.colour), a.key0,
+    const U4 w = philox_x3((uint32_t)p, a.sweep, (uint32_t)chain, ctr_word3(0u, TAG_REFLAT, a.colour), a.key0,
                                a.key1);
     const int yu = (y + L - 1) % L, yd = (y + 1) % L;
 #pragma unroll
@@ -841,8 +692,8 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
         const float u2 = u24(h ? w.w : w.y);
         const float cp = cos_rev(a.q * tpv), sp = sin_rev(a.q * tpv);
         const float dE = -fmaf(cp - co, Cx, (sp - so) * Sy);
-        int dec = metropolis_filter(dE, tp, u2, a.delta_e);
-        if (dec < 0) dec = metropolis_exact(tpv, to, nb, 4, a.two_pi_q, 1.0, T, u2) ? 1 : 0;
+        int dec = filter32(dE, tp, u2, a.delta_e);
+        if (dec < 0) dec = exact64(tpv, to, nb[0], nb[1], nb[2], nb[3], 15u, a.two_pi_q, 1.0, T, u2) ? 1 : 0;
         if (dec) st[y * L + x] = tpv;
     }
 }

@@ -1,0 +1,84 @@
+// Device helpers of the Metropolis update shared by the sweep kernels: the gfx950 transcendental intrinsics, the
+// FP32 acceptance filter with its error band, and the exact FP64 decision.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mpr_internal.hpp"
+#include "philox.hpp"
+
+namespace mpr {
+
+// cos / sin of 2 pi x for x in revolutions (v_cos_f32 / v_sin_f32, valid for |x| <= 256); 2^x (v_exp_f32).
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// a ^ b ^ k in one gfx950 three-input bit operation (truth table 0x96 over the inputs a = 0xF0, b = 0xCC, k = 0xAA);
+// k is wave-uniform (a Philox round key) and stays in a scalar register.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
+// Philox4x32-10 written with the three-input xor (the same function as philox4x32_10).
+__device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// FP32 Metropolis filter.  Returns 1 = accept, 0 = reject, -1 = inside the error band (the exact FP64 test decides).
+// dE is the FP32 energy change with |dE - dE_exact| <= delta.  The exact test is u2 < exp(-dE/T) (T > 0) or
+// dE <= 0 (T == 0).  With y = dE * nl2T = log2 of the acceptance ratio, |y - y_exact| <= delta |nl2T| + |y| 2^-22,
+// and the relative error of w = 2^y is ln 2 |y - y_exact| plus the v_exp_f32 error (below 2^-22); the band is that
+// bound with a 25 % margin, plus an absolute 2^-30 for results that flush to zero.
+__device__ __forceinline__ int filter32(float dE, TPair tp, float u2, float delta)
+{
+    if (tp.T > 0.0f) {
+        const float y = dE * tp.nl2T;
+        if (y >= 1.0f) return 1;
+        const float w = exp2_fast(y);
+        const float rel = 1.25f * (0.6931472f * fmaf(delta, fabsf(tp.nl2T), fabsf(y) * 2.3841858e-7f) + 2.3841858e-7f);
+        if (fabsf(u2 - w) <= fmaf(w, rel, 9.3132257e-10f)) return -1;
+        return u2 < w ? 1 : 0;
+    }
+    if (fabsf(dE) <= delta) return -1;
+    return dE <= 0.0f ? 1 : 0;
+}
+
+// The exact decision, evaluated as the published formula: dE = -J sum_j [cos 2 pi q (t' - t_j) - cos 2 pi q (t - t_j)]
+// over the present neighbours in the order up, left, right, down; accept iff u2 < exp(-dE / T) (T > 0) or dE <= 0.
+__device__ __noinline__ bool exact64(float tp, float to, float nu, float nl, float nr, float nd, unsigned present,
+                                     double two_pi_q, double J, float T, float u2)
+{
+    double acc = 0.0;
+    const double dtp = (double)tp, dto = (double)to;
+    if (present & 1u) acc += cos(two_pi_q * (dtp - (double)nu)) - cos(two_pi_q * (dto - (double)nu));
+    if (present & 2u) acc += cos(two_pi_q * (dtp - (double)nl)) - cos(two_pi_q * (dto - (double)nl));
+    if (present & 4u) acc += cos(two_pi_q * (dtp - (double)nr)) - cos(two_pi_q * (dto - (double)nr));
+    if (present & 8u) acc += cos(two_pi_q * (dtp - (double)nd)) - cos(two_pi_q * (dto - (double)nd));
+    const double dE = -J * acc;
+    if ((double)T > 0.0) return (double)u2 < exp(-dE / (double)T);
+    return dE <= 0.0;
+}
+
+}  // namespace mpr

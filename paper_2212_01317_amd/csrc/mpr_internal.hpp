@@ -61,6 +61,7 @@ hipError_t launch_tpairs(const float* T, int64_t B, TPair* tp, hipStream_t s);
 
 struct InitArgs {
     float* state;
+    float* state2;       // optional second buffer that receives the same start
     const float* t;
     const uint8_t* mask;
     const double* Ts;
@@ -74,24 +75,26 @@ struct InitArgs {
 };
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 
-struct SweepArgs {
-    float* state;
+struct SweepFusedArgs {
+    const float* src;    // [R][H][W] state after sweep k-1
+    float* dst;          // [R][H][W] state after sweep k (sample cells must already hold their angles)
     const uint8_t* mask;
     const TPair* Tb;
-    int H, W, lb_h, lb_w, nbx, ntx, nty, Mw;
-    int colour;
+    int H, W, lb_h, lb_w, nbx, ntx, nty, ntiles, Mw, R, rchunk, nchunks;
+    int64_t HW;
     uint32_t sweep, real_offset, scene, key0, key1;
     float q, J, delta_e;
     double two_pi_q, Jd;
-    double* e_partial;   // [R][ntx * nty] when the energy epilogue runs (colour 1), else null
+    double* e_partial;   // [R][ntiles] energy of each tile's colour-1 bonds, or null
 };
-void sweep_tiles(int64_t H, int64_t W, int* ntx, int* nty);
-hipError_t launch_sweep_half(const SweepArgs& a, int R, hipStream_t s);
+void fused_geometry(int64_t H, int64_t W, int R, int* ntx, int* nty, int* rchunk, int* nchunks);
+hipError_t launch_sweep_fused(const SweepFusedArgs& a, hipStream_t s);
 hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
                               int nparts, hipStream_t s);
 int energy_full_parts(int64_t H, int64_t W);
-hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_out,
-                                hipStream_t s);
+// partial layout [R][nparts]; e_real[R] scratch; e_out = mean over r of sum_p partial[r][p] * inv_norm
+hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_real,
+                                double* e_out, hipStream_t s);
 hipError_t launch_accumulate(const float* state, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
                              hipStream_t s);
 hipError_t launch_predict(const double* acc, const float* z, const uint8_t* mask, int64_t n, int64_t n_samples,
