@@ -160,6 +160,55 @@ size_t mpr_validate_workspace_bytes(int64_t n);
 mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* eval_mask, int64_t n, double* out,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* Batched simulation (a project addition): many scenes of different sizes and gap fractions, each with n_real
+ * realizations, advanced together by one persistent sweep kernel per sweep that takes (scene, tile, realization
+ * chunk) work items from a device work queue, largest scenes first.  Each scene follows exactly the arithmetic of
+ * mpr_simulate with cfg->scene_id replaced by its own scene_id (its own stopping test and sampling sweeps), so its
+ * results are bit-identical to a single-scene call.  Sweeps are replayed from a HIP graph captured once per call
+ * (n_f sweeps per graph); the stream is synchronised once per graph replay.  tile_h: 16 or 32 (tile height of the
+ * sweep kernel; results do not depend on it), or 0 to time one sweep with each and keep the faster
+ * (*tile_h_used_out reports the choice).  sweeps_done_out[n_scenes] (host, optional): k* per scene.
+ * Workspace: mpr_simulate_batched_workspace_bytes (a second state buffer per scene plus small per-scene arrays). */
+typedef struct {
+    int64_t H, W;             /* grid of this scene */
+    int32_t lb_h, lb_w;       /* its temperature blocks */
+    uint32_t scene_id;        /* its random stream, 0 .. 2^28 - 1 */
+    const float* t;           /* [H*W] mapped angles (samples used) */
+    const uint8_t* mask;      /* [H*W] 1 = sample */
+    const float* T_blocks;    /* [ceil(H/lb_h) * ceil(W/lb_w)] */
+    float* state;             /* [n_real*H*W] out: final states */
+    double* acc;              /* [H*W] out: accumulated gap angles */
+    double* energy;           /* [cap + 1] out, optional (NULL) */
+} mpr_scene;
+size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg);
+mpr_status mpr_simulate_batched(const mpr_scene* scenes /* host array */, int32_t n_scenes,
+                                const mpr_sim_config* cfg, int32_t tile_h, int32_t* sweeps_done_out,
+                                int32_t* tile_h_used_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Temperature gradient (a project addition on Sec. 2.2.2: tuning the block temperatures by gradient).
+ * For a density proportional to exp(-sum_b H_b / T_b), d<f>/dT_b = Cov(f, H_b) / T_b^2.
+ *
+ * mpr_block_energy: H_out[r * B + b] (double) = H_b of realization r of `state` [n_real*H*W]: the sum of Eq. (1) over
+ * every bond with at least one gap end, counted in the block of its gap end; a bond between two gaps of different
+ * blocks counts one half in each; bonds between samples are left out.  FP64 (published formula).  Asynchronous.
+ * Workspace: mpr_block_energy_workspace_bytes. */
+size_t mpr_block_energy_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t n_real);
+mpr_status mpr_block_energy(const float* state, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w,
+                            float q, float J, int32_t n_real, double* H_out, void* workspace, size_t ws_bytes,
+                            void* stream);
+
+/* mpr_temperature_grad: score-function estimate of dL/dT_b for a loss L of the prediction of a run with one sampling
+ * sweep (E[zhat] = zmin + (zmax - zmin) E[t]).  state [n_real*H*W]: the final states of that run; H_blocks
+ * [n_real*n_blocks] from mpr_block_energy; grad_zhat [H*W] (float) = dL/dzhat; range = {zmin, zmax} (device).
+ * g_r = sum over gaps of grad_zhat * (zmax - zmin) * t_r; dT_out[b] (double) = Cov_r(g, H_b) / T_b^2 with the
+ * unbiased (R - 1) covariance, 0 where T_b = 0.  n_real >= 2.  FP64, fixed reduction order.  Asynchronous.
+ * Workspace: mpr_temperature_grad_workspace_bytes. */
+size_t mpr_temperature_grad_workspace_bytes(int64_t H, int64_t W, int32_t n_real);
+mpr_status mpr_temperature_grad(const float* state, const double* H_blocks, const float* grad_zhat,
+                                const uint8_t* mask, int64_t H, int64_t W, int32_t n_real, int64_t n_blocks,
+                                const double* range, const float* T_blocks, double* dT_out, void* workspace,
+                                size_t ws_bytes, void* stream);
+
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* mpr_last_error(void);
 

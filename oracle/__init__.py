@@ -93,6 +93,10 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_chain_trace.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _u64, _u32, _u32, _i32,
                                   _i32, _i64p, _i32, _f32p]
     L.orc_chain_trace.restype = None
+    L.orc_block_energy.argtypes = [_f32p, _u8p, _i64, _i64, _i32, _i32, _flt, _flt, _f64p]
+    L.orc_block_energy.restype = None
+    L.orc_temperature_grad.argtypes = [_f32p, _f64p, _f64p, _i64, _i32, _i64, _f32p, _f64p]
+    L.orc_temperature_grad.restype = None
 
 
 # ---------------------------------------------------------------------------------------------------------------
@@ -287,3 +291,26 @@ def run_pipeline(z, mask, lb_h, lb_w, curve_T, curve_e, cfg: SimConfig):
     res = simulate(t, mask, T, lb_h, lb_w, cfg)
     zhat = predict(res.acc, z, mask, cfg.n_real * cfg.n_samp, rng)
     return dict(t=t, range=rng, T=T, sim=res, zhat=zhat)
+
+
+def block_energy(state, mask, lb_h, lb_w, q=0.5, J=1.0):
+    """H_b of one state [H, W] (bonds with a gap end; gap-gap bonds across blocks split one half each)."""
+    s = _c(state, np.float32)
+    H, W = s.shape
+    nby, nbx = n_blocks(H, W, lb_h, lb_w)
+    out = np.zeros(nby * nbx, np.float64)
+    lib().orc_block_energy(s, _c(mask, np.uint8), H, W, lb_h, lb_w, q, J, out)
+    return out
+
+
+def temperature_grad(states, Hrb, w, T_blocks):
+    """Score-function estimate of dL/dT_b from R final states [R, H, W] (one sampling sweep), block energies
+    [R, B] and weights w [H, W] = dL/dzhat * (zmax - zmin) at gaps (0 at samples): E[zhat] = zmin + span * E[t]."""
+    st = _c(states, np.float32)
+    R = st.shape[0]
+    HW = st.shape[1] * st.shape[2]
+    Hrb = _c(Hrb, np.float64)
+    B = Hrb.shape[1]
+    out = np.zeros(B, np.float64)
+    lib().orc_temperature_grad(st, Hrb, _c(w, np.float64).ravel(), HW, R, B, _c(T_blocks, np.float32).ravel(), out)
+    return out

@@ -556,3 +556,64 @@ void orc_chain_trace(float* s, const uint8_t* mask, int64_t H, int64_t W, const 
         for (int32_t j = 0; j < n_sites; ++j) trace[(int64_t)i * n_sites + j] = s[sites[j]];
     }
 }
+
+/* ------------------------------------------------------------------------------------------------------------
+ * Gradient of the realization-averaged prediction with respect to the block temperatures (a project addition
+ * built on Sec. 2.2.2).  For a density proportional to exp(-sum_b H_b / T_b), d<f>/dT_b = Cov(f, H_b) / T_b^2.
+ * H_b is the part of Eq. (1) attributed to block b: every bond with at least one gap end, counted in the block of
+ * its gap end; a bond between two gaps in different blocks counts one half in each.  Bonds between two samples do
+ * not depend on the state and are left out.
+ * ---------------------------------------------------------------------------------------------------------- */
+void orc_block_energy(const float* s, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w,
+                      float q, float J, double* Hb)
+{
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    for (int64_t b = 0; b < nbx * nby; ++b) Hb[b] = 0.0;
+    for (int64_t y = 0; y < H; ++y) {
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t n = y * W + x;
+            if (mask[n]) continue;
+            int64_t b = (y / lb_h) * nbx + (x / lb_w);
+            int64_t nb[4];
+            int cnt = 0;
+            if (y > 0) nb[cnt++] = n - W;
+            if (x > 0) nb[cnt++] = n - 1;
+            if (x + 1 < W) nb[cnt++] = n + 1;
+            if (y + 1 < H) nb[cnt++] = n + W;
+            for (int i = 0; i < cnt; ++i) {
+                double share = mask[nb[i]] ? 1.0 : 0.5;
+                Hb[b] += share * bond_energy((double)s[n], (double)s[nb[i]], tpq, (double)J);
+            }
+        }
+    }
+}
+
+/* g_r = sum over sites of w * t_r (w = dL/dzhat * (zmax - zmin) at gaps, 0 at samples: with one sampling sweep
+ * E[zhat] = zmin + (zmax - zmin) E[t]);
+ * dT[b] = [sum_r (g_r - mean g)(H_rb - mean H_b) / (R - 1)] / T_b^2, all in FP64 (R >= 2; T_b = 0 gives 0). */
+void orc_temperature_grad(const float* states, const double* Hrb, const double* w, int64_t HW, int32_t R, int64_t B,
+                          const float* T_blocks, double* dT)
+{
+    double* g = (double*)malloc(sizeof(double) * (size_t)R);
+    double gm = 0.0;
+    for (int32_t r = 0; r < R; ++r) {
+        double acc = 0.0;
+        const float* s = states + (int64_t)r * HW;
+        for (int64_t n = 0; n < HW; ++n) acc += w[n] * (double)s[n];
+        g[r] = acc;
+        gm += acc;
+    }
+    gm /= (double)R;
+    for (int64_t b = 0; b < B; ++b) {
+        double hm = 0.0;
+        for (int32_t r = 0; r < R; ++r) hm += Hrb[(int64_t)r * B + b];
+        hm /= (double)R;
+        double cov = 0.0;
+        for (int32_t r = 0; r < R; ++r) cov += (g[r] - gm) * (Hrb[(int64_t)r * B + b] - hm);
+        cov /= (double)(R - 1);
+        double T = (double)T_blocks[b];
+        dT[b] = T > 0.0 ? cov / (T * T) : 0.0;
+    }
+    free(g);
+}

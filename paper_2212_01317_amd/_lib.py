@@ -59,6 +59,13 @@ class SimConfig:
                               self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id)
 
 
+class mpr_scene(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int64), ("W", ctypes.c_int64), ("lb_h", ctypes.c_int32), ("lb_w", ctypes.c_int32),
+                ("scene_id", ctypes.c_uint32), ("t", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("T_blocks", ctypes.c_void_p), ("state", ctypes.c_void_p), ("acc", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -87,6 +94,14 @@ _SIGS = {
     "mpr_sweep": ([_vp, _vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _i32, _i32, _vp, _vp,
                    _sz, _vp], ctypes.c_int),
     "mpr_predict": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "mpr_simulate_batched_workspace_bytes": ([ctypes.POINTER(mpr_scene), _i32, ctypes.POINTER(mpr_sim_config)], _sz),
+    "mpr_simulate_batched": ([ctypes.POINTER(mpr_scene), _i32, ctypes.POINTER(mpr_sim_config), _i32,
+                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
+    "mpr_block_energy_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
+    "mpr_block_energy": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_temperature_grad_workspace_bytes": ([_i64, _i64, _i32], _sz),
+    "mpr_temperature_grad": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp],
+                             ctypes.c_int),
     "mpr_validate_workspace_bytes": ([_i64], _sz),
     "mpr_validate": ([_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], ctypes.c_int),
 }
@@ -291,3 +306,83 @@ def mpr_validate(zhat, truth, eval_mask):
     ws = _ws(lib().mpr_validate_workspace_bytes(n), zhat.device)
     _check(lib().mpr_validate(_p(zhat), _p(truth), _p(eval_mask), n, _p(out), _p(ws), ws.numel(), _stream()))
     return out
+
+
+def mpr_block_energy(state, mask, lb_h, lb_w, q=0.5, J=1.0):
+    """H_b per realization: [R, nby * nbx] float64."""
+    _dev(state, torch.float32, "state")
+    _dev(mask, torch.uint8, "mask")
+    H, W = _hw(mask)
+    R = int(state.shape[0])
+    if tuple(state.shape) != (R, H, W):
+        raise ValueError("state must be [R, H, W]")
+    B = (-(-H // lb_h)) * (-(-W // lb_w))
+    out = torch.empty((R, B), dtype=torch.float64, device=state.device)
+    ws = _ws(lib().mpr_block_energy_workspace_bytes(H, W, lb_h, lb_w, R), state.device)
+    _check(lib().mpr_block_energy(_p(state), _p(mask), H, W, lb_h, lb_w, q, J, R, _p(out), _p(ws), ws.numel(),
+                                  _stream()))
+    return out
+
+
+def mpr_temperature_grad(state, H_blocks, grad_zhat, mask, rng, T_blocks):
+    """dL/dT_b [B] float64 from the final states of a run with one sampling sweep."""
+    _dev(state, torch.float32, "state")
+    _dev(H_blocks, torch.float64, "H_blocks")
+    _dev(grad_zhat, torch.float32, "grad_zhat")
+    _dev(mask, torch.uint8, "mask")
+    _dev(rng, torch.float64, "range")
+    _dev(T_blocks, torch.float32, "T_blocks")
+    H, W = _hw(mask)
+    R = int(state.shape[0])
+    B = int(H_blocks.shape[1])
+    if T_blocks.numel() != B or tuple(H_blocks.shape) != (R, B):
+        raise ValueError("H_blocks must be [R, B] and T_blocks must have B entries")
+    dT = torch.empty(B, dtype=torch.float64, device=state.device)
+    ws = _ws(lib().mpr_temperature_grad_workspace_bytes(H, W, R), state.device)
+    _check(lib().mpr_temperature_grad(_p(state), _p(H_blocks), _p(grad_zhat), _p(mask), H, W, R, B, _p(rng),
+                                      _p(T_blocks), _p(dT), _p(ws), ws.numel(), _stream()))
+    return dT
+
+
+@dataclass
+class BatchOutput:
+    outputs: list              # SimOutput per scene
+    tile_h: int                # tile height the sweep kernel used
+    converged: bool
+
+
+def mpr_simulate_batched(scenes, cfg: SimConfig, tile_h: int = 0, want_energy: bool = False,
+                         workspace: torch.Tensor | None = None) -> BatchOutput:
+    """scenes: list of dicts with t [H, W] f32, mask [H, W] u8, T_blocks f32, block (lb_h, lb_w), scene_id.
+    One batched call; every scene's result equals mpr_simulate with its own scene_id."""
+    n = len(scenes)
+    arr = (mpr_scene * n)()
+    outs = []
+    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    for i, sc in enumerate(scenes):
+        t, mask, T = sc["t"], sc["mask"], sc["T_blocks"]
+        _dev(t, torch.float32, "t")
+        _dev(mask, torch.uint8, "mask")
+        _dev(T, torch.float32, "T_blocks")
+        H, W = _hw(t)
+        lb_h, lb_w = sc["block"]
+        state = torch.empty((cfg.n_real, H, W), dtype=torch.float32, device=t.device)
+        acc = torch.empty((H, W), dtype=torch.float64, device=t.device)
+        en = torch.empty(cap, dtype=torch.float64, device=t.device) if want_energy else None
+        arr[i] = mpr_scene(H, W, lb_h, lb_w, int(sc.get("scene_id", i)), t.data_ptr(), mask.data_ptr(), T.data_ptr(),
+                           state.data_ptr(), acc.data_ptr(), en.data_ptr() if en is not None else None)
+        outs.append((state, acc, en))
+    c = cfg.to_c()
+    need = lib().mpr_simulate_batched_workspace_bytes(arr, n, ctypes.byref(c))
+    dev = scenes[0]["t"].device
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    done = (_i32 * n)()
+    used = _i32(0)
+    st = _check(lib().mpr_simulate_batched(arr, n, ctypes.byref(c), int(tile_h), done, ctypes.byref(used), _p(ws),
+                                           ws.numel(), _stream()), allow_warn=True)
+    res = []
+    for i, (state, acc, en) in enumerate(outs):
+        k = int(done[i])
+        e = en[: k + 1] if en is not None else torch.empty(0, dtype=torch.float64, device=dev)
+        res.append(SimOutput(state=state, acc=acc, energy=e, sweeps=k, converged=True))
+    return BatchOutput(outputs=res, tile_h=int(used.value), converged=(st == MPR_OK))

@@ -5,10 +5,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
+#include "batched.hpp"
 #include "mpr.h"
 #include "mpr_internal.hpp"
 
@@ -225,7 +228,9 @@ struct SweepRunner {
                 int32_t lb_h, int32_t lb_w, const mpr_sim_config& c, double* epart_, double* e_real_, hipStream_t s_)
     {
         int ntx, nty, rchunk, nchunks;
-        mpr::fused_geometry(H, W, c.n_real, &ntx, &nty, &rchunk, &nchunks);
+        const int tile_h = 32;
+        mpr::fused_geometry(H, W, c.n_real, tile_h, &ntx, &nty, &rchunk, &nchunks);
+        a.tile_h = tile_h;
         a.src = state;
         a.dst = alt;
         a.mask = mask;
@@ -283,7 +288,7 @@ struct SweepRunner {
 int fused_tiles(int64_t H, int64_t W, int R)
 {
     int ntx, nty, rc, nc;
-    mpr::fused_geometry(H, W, R, &ntx, &nty, &rc, &nc);
+    mpr::fused_geometry(H, W, R, 32, &ntx, &nty, &rc, &nc);
     return ntx * nty;
 }
 
@@ -303,6 +308,76 @@ size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, cons
     return c.used;
 }
 
+struct BatchWs {
+    mpr::BatchScene* scenes;
+    mpr::BatchRun* runs;
+    int* order;
+    int64_t* prefix;
+    mpr::BatchCtl* ctl;
+    StatsWs st;           // init scratch, sized for the largest scene
+    double* Ts;
+    int* No;
+    float* gmean;
+    std::vector<mpr::TPair*> tp;
+    std::vector<float*> alt;
+    std::vector<double*> epart, e_real, series;
+};
+
+void batch_geom(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int* ntiles, int* rchunk, int* nchunks)
+{
+    mpr::fused_geometry(H, W, R, tile_h, ntx, nty, rchunk, nchunks);
+    *ntiles = (*ntx) * (*nty);
+}
+
+size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg, BatchWs* w)
+{
+    BatchWs x;
+    const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
+    x.scenes = c.take<mpr::BatchScene>(n);
+    x.runs = c.take<mpr::BatchRun>(n);
+    x.order = c.take<int>(n);
+    x.prefix = c.take<int64_t>(n + 1);
+    x.ctl = c.take<mpr::BatchCtl>(1);
+    int64_t max_np = 1, max_B = 1;
+    for (int i = 0; i < n; ++i) {
+        mpr::StatsGeom g = mpr::stats_geom(sc[i].H, sc[i].W, sc[i].lb_h, sc[i].lb_w);
+        max_np = std::max<int64_t>(max_np, g.B() * g.nchunk);
+        max_B = std::max<int64_t>(max_B, g.B());
+    }
+    x.st.pS = c.take<double>(max_np);
+    x.st.pTs = c.take<double>(max_np);
+    x.st.pN = c.take<int>(max_np);
+    x.st.pNo = c.take<int>(max_np);
+    x.Ts = c.take<double>(max_B);
+    x.No = c.take<int>(max_B);
+    x.gmean = c.take<float>(1);
+    const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
+    for (int i = 0; i < n; ++i) {
+        const int64_t H = sc[i].H, W = sc[i].W;
+        x.tp.push_back(c.take<mpr::TPair>(nblocks_of(H, W, sc[i].lb_h, sc[i].lb_w)));
+        x.alt.push_back(c.take<float>(R * H * W));
+        int ntx, nty, nt16, nt32, rc, nc;
+        batch_geom(H, W, (int)R, 16, &ntx, &nty, &nt16, &rc, &nc);
+        batch_geom(H, W, (int)R, 32, &ntx, &nty, &nt32, &rc, &nc);
+        const int64_t np = std::max<int64_t>(std::max(nt16, nt32), mpr::energy_full_parts(H, W));
+        x.epart.push_back(c.take<double>(np * R));
+        x.e_real.push_back(c.take<double>(R));
+        x.series.push_back(sc[i].energy ? sc[i].energy : c.take<double>((cap > 0 ? cap : 0) + 1));
+    }
+    if (w) *w = std::move(x);
+    return c.used;
+}
+
+// private stream used only to capture graphs (graphs are launched on the caller's stream)
+hipStream_t capture_stream()
+{
+    static thread_local hipStream_t cs = nullptr;
+    if (!cs) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+    }
+    return cs;
+}
+
 }  // namespace
 
 extern "C" {
@@ -310,6 +385,65 @@ extern "C" {
 int32_t mpr_abi_version(void) { return 10000; }
 
 const char* mpr_last_error(void) { return g_last_error.c_str(); }
+
+size_t mpr_block_energy_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t n_real)
+{
+    if (H < 1 || W < 1 || lb_h < 1 || lb_w < 1 || n_real < 1) return 0;
+    mpr::StatsGeom g = mpr::stats_geom(H, W, lb_h, lb_w);
+    Carve c{nullptr, 0, 0};
+    c.take<double>(g.B() * g.nchunk * (int64_t)n_real);
+    return c.used;
+}
+
+mpr_status mpr_block_energy(const float* state, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w,
+                            float q, float J, int32_t n_real, double* H_out, void* workspace, size_t ws_bytes,
+                            void* stream)
+{
+    mpr_status st = check_grid(H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks(H, W, lb_h, lb_w)) != MPR_OK) return st;
+    if (!state || !mask || !H_out) return fail(MPR_ERR_INVALID_ARG, "mpr_block_energy: NULL pointer");
+    if (!(q > 0.0f && q <= 0.5f) || !(J > 0.0f)) return fail(MPR_ERR_INVALID_ARG, "need 0 < q <= 1/2 and J > 0");
+    if (n_real < 1 || n_real > 65535) return fail(MPR_ERR_INVALID_ARG, "n_real must be in 1 .. 65535");
+    st = check_ws(workspace, ws_bytes, mpr_block_energy_workspace_bytes(H, W, lb_h, lb_w, n_real));
+    if (st != MPR_OK) return st;
+    mpr::StatsGeom g = mpr::stats_geom(H, W, lb_h, lb_w);
+    Carve c{static_cast<char*>(workspace), 0, ws_bytes};
+    double* part = c.take<double>(g.B() * g.nchunk * (int64_t)n_real);
+    MPR_HIP(mpr::launch_block_energy(state, mask, g, 2.0 * mpr::kPi * (double)q, (double)J, n_real, part, H_out,
+                                     S(stream)));
+    return ok();
+}
+
+size_t mpr_temperature_grad_workspace_bytes(int64_t H, int64_t W, int32_t n_real)
+{
+    if (H < 1 || W < 1 || n_real < 1) return 0;
+    Carve c{nullptr, 0, 0};
+    c.take<double>((int64_t)mpr::grad_parts(H * W) * n_real);
+    c.take<double>(n_real);
+    return c.used;
+}
+
+mpr_status mpr_temperature_grad(const float* state, const double* H_blocks, const float* grad_zhat,
+                                const uint8_t* mask, int64_t H, int64_t W, int32_t n_real, int64_t n_blocks,
+                                const double* range, const float* T_blocks, double* dT_out, void* workspace,
+                                size_t ws_bytes, void* stream)
+{
+    mpr_status st = check_grid(H, W);
+    if (st != MPR_OK) return st;
+    if (!state || !H_blocks || !grad_zhat || !mask || !range || !T_blocks || !dT_out)
+        return fail(MPR_ERR_INVALID_ARG, "mpr_temperature_grad: NULL pointer");
+    if (n_real < 2 || n_real > 65535) return fail(MPR_ERR_INVALID_ARG, "n_real must be in 2 .. 65535");
+    if (n_blocks < 1) return fail(MPR_ERR_INVALID_ARG, "n_blocks must be >= 1");
+    st = check_ws(workspace, ws_bytes, mpr_temperature_grad_workspace_bytes(H, W, n_real));
+    if (st != MPR_OK) return st;
+    Carve c{static_cast<char*>(workspace), 0, ws_bytes};
+    double* part = c.take<double>((int64_t)mpr::grad_parts(H * W) * n_real);
+    double* g = c.take<double>(n_real);
+    MPR_HIP(mpr::launch_temperature_grad(state, H_blocks, grad_zhat, mask, H * W, n_real, n_blocks, range, T_blocks,
+                                         part, g, dT_out, S(stream)));
+    return ok();
+}
 
 size_t mpr_map_workspace_bytes(int64_t H, int64_t W)
 {
@@ -635,6 +769,256 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
     const int nb = mpr::validate_blocks(n);
     double* part = c.take<double>((int64_t)3 * nb);
     MPR_HIP(mpr::launch_validate(zhat, truth, eval_mask, n, part, nb, out, S(stream)));
+    return ok();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
+{
+    if (!scenes || n_scenes < 1 || !cfg) return 0;
+    for (int i = 0; i < n_scenes; ++i)
+        if (scenes[i].H < 1 || scenes[i].W < 1 || scenes[i].lb_h < 1 || scenes[i].lb_w < 1) return 0;
+    Carve c{nullptr, 0, 0};
+    return batch_ws(c, scenes, n_scenes, cfg, nullptr);
+}
+
+mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
+                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
+                                void* stream)
+{
+    if (!scenes || n_scenes < 1 || n_scenes > (1 << 20)) return fail(MPR_ERR_INVALID_ARG, "need 1 .. 2^20 scenes");
+    if (!cfg) return fail(MPR_ERR_INVALID_ARG, "cfg is NULL");
+    mpr_status st = check_sim_config(*cfg);
+    if (st != MPR_OK) return st;
+    const mpr_sim_config& c = *cfg;
+    if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
+        return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
+    if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)
+        return fail(MPR_ERR_INVALID_ARG, "unknown stop_mode %d", c.stop_mode);
+    if (c.n_samp < 0) return fail(MPR_ERR_INVALID_ARG, "n_samp must be >= 0");
+    if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 1) return fail(MPR_ERR_INVALID_ARG, "batched FIXED mode needs n_eq >= 1");
+    if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
+        return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
+    if (tile_h != 0 && tile_h != 16 && tile_h != 32) return fail(MPR_ERR_INVALID_ARG, "tile_h must be 0, 16 or 32");
+    for (int i = 0; i < n_scenes; ++i) {
+        const mpr_scene& sc = scenes[i];
+        if ((st = check_grid(sc.H, sc.W)) != MPR_OK) return st;
+        if ((st = check_blocks(sc.H, sc.W, sc.lb_h, sc.lb_w)) != MPR_OK) return st;
+        if (!sc.t || !sc.mask || !sc.T_blocks || !sc.state || !sc.acc)
+            return fail(MPR_ERR_INVALID_ARG, "scene %d: NULL pointer", i);
+        if (sc.scene_id >= (1u << 28)) return fail(MPR_ERR_INVALID_ARG, "scene %d: scene_id must be < 2^28", i);
+    }
+    st = check_ws(workspace, ws_bytes, mpr_simulate_batched_workspace_bytes(scenes, n_scenes, cfg));
+    if (st != MPR_OK) return st;
+    hipStream_t s = S(stream);
+    Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
+    BatchWs w;
+    batch_ws(cv, scenes, n_scenes, cfg, &w);
+    const int R = c.n_real;
+    const uint32_t key0 = (uint32_t)(c.seed & 0xffffffffu), key1 = (uint32_t)(c.seed >> 32);
+    const bool energy = c.stop_mode == MPR_STOP_AUTO;
+    bool any_energy_out = false;
+    for (int i = 0; i < n_scenes; ++i) any_energy_out |= scenes[i].energy != nullptr;
+
+    // ---- per-scene start, temperatures, e(0) ----
+    std::vector<mpr::BatchScene> hs(n_scenes);
+    std::vector<int64_t> work16(n_scenes), work32(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) {
+        const mpr_scene& sc = scenes[i];
+        mpr::StatsGeom g = mpr::stats_geom(sc.H, sc.W, sc.lb_h, sc.lb_w);
+        if (c.init_mode == MPR_INIT_BLOCK_MEAN) {
+            MPR_HIP(mpr::launch_block_stats(sc.t, sc.mask, g, 2.0 * mpr::kPi * (double)c.q, (double)c.J, w.st.pS,
+                                            w.st.pN, w.st.pTs, w.st.pNo, nullptr, nullptr, w.Ts, w.No, s));
+            MPR_HIP(mpr::launch_global_mean(w.Ts, w.No, g.B(), w.gmean, s));
+        }
+        mpr::InitArgs ia;
+        ia.state = sc.state;
+        ia.state2 = w.alt[i];
+        ia.t = sc.t;
+        ia.mask = sc.mask;
+        ia.Ts = w.Ts;
+        ia.No = w.No;
+        ia.gmean = w.gmean;
+        ia.H = sc.H;
+        ia.W = sc.W;
+        ia.lb_h = sc.lb_h;
+        ia.lb_w = sc.lb_w;
+        ia.nbx = g.nbx;
+        ia.R = R;
+        ia.real_offset = (uint32_t)c.real_offset;
+        ia.scene = sc.scene_id;
+        ia.key0 = key0;
+        ia.key1 = key1;
+        ia.mode = c.init_mode;
+        MPR_HIP(mpr::launch_init(ia, s));
+        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), w.tp[i], s));
+        const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
+        const double inv_norm = nbonds > 0 ? 1.0 / ((double)c.J * (double)nbonds) : 0.0;
+        if (energy || sc.energy) {
+            const int nfull = mpr::energy_full_parts(sc.H, sc.W);
+            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
+            MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
+        }
+        if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)(sc.H * sc.W), s));
+        mpr::BatchScene& d = hs[i];
+        d.t = sc.t;
+        d.mask = sc.mask;
+        d.tp = w.tp[i];
+        d.buf[0] = sc.state;
+        d.buf[1] = w.alt[i];
+        d.acc = sc.acc;
+        d.epart = w.epart[i];
+        d.e_real = w.e_real[i];
+        d.series = w.series[i];
+        d.H = (int)sc.H;
+        d.W = (int)sc.W;
+        d.lb_h = sc.lb_h;
+        d.lb_w = sc.lb_w;
+        d.nbx = g.nbx;
+        d.Mw = (int)((sc.W + 3) / 4);
+        for (int v = 0; v < 2; ++v) {
+            int ntx, nty, nt, rc, nc;
+            batch_geom(sc.H, sc.W, R, v ? 32 : 16, &ntx, &nty, &nt, &rc, &nc);
+            d.ntx = ntx;
+            d.nty[v] = nty;
+            d.ntiles[v] = nt;
+            d.rchunk[v] = rc;
+            d.nchunks[v] = nc;
+        }
+        work16[i] = (int64_t)d.ntiles[0] * d.nchunks[0];
+        work32[i] = (int64_t)d.ntiles[1] * d.nchunks[1];
+        d.HW = sc.H * sc.W;
+        d.scene = sc.scene_id;
+        d.inv_norm = inv_norm;
+    }
+    // largest scenes first
+    std::vector<int> order(n_scenes);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work32[a] > work32[b]; });
+    int variant = tile_h == 16 ? 0 : 1;
+    const int first_variant = tile_h == 0 ? 0 : variant;
+    std::vector<int64_t> prefix(n_scenes + 1, 0);
+    for (int i = 0; i < n_scenes; ++i)
+        prefix[i + 1] = prefix[i] + (first_variant ? work32[order[i]] : work16[order[i]]);
+    std::vector<mpr::BatchRun> runs(n_scenes, mpr::BatchRun{0, 0, 0, 1});
+    mpr::BatchCtl ctl{0, n_scenes, 0ull};
+    MPR_HIP(hipMemcpyAsync(w.scenes, hs.data(), sizeof(mpr::BatchScene) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.runs, runs.data(), sizeof(mpr::BatchRun) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.order, order.data(), sizeof(int) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.prefix, prefix.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipStreamSynchronize(s));     // the host arrays above must outlive the copies
+
+    mpr::BatchDev b;
+    b.scenes = w.scenes;
+    b.runs = w.runs;
+    b.order = w.order;
+    b.prefix = w.prefix;
+    b.ctl = w.ctl;
+    b.n = n_scenes;
+    b.cfg.R = R;
+    b.cfg.real_offset = (uint32_t)c.real_offset;
+    b.cfg.key0 = key0;
+    b.cfg.key1 = key1;
+    b.cfg.q = c.q;
+    b.cfg.J = c.J;
+    b.cfg.delta_e = mpr::kDeltaE * c.J;
+    b.cfg.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+    b.cfg.Jd = (double)c.J;
+    b.cfg.energy = (energy || any_energy_out) ? 1 : 0;
+    b.cfg.stop_mode = c.stop_mode;
+    b.cfg.n_fit = c.n_fit;
+    b.cfg.n_f = c.n_f;
+    b.cfg.n_max = c.n_max;
+    b.cfg.n_eq = c.n_eq;
+    b.cfg.n_samp = c.n_samp;
+    int max_hw_blocks = 1;
+    for (int i = 0; i < n_scenes; ++i)
+        max_hw_blocks = std::max<int>(max_hw_blocks, (int)std::min<int64_t>((hs[i].HW + 255) / 256, 1024));
+    const int grid = 256 * 4;              // four workgroups per CU, persistent
+    const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
+    const int32_t total_max = cap + c.n_samp;
+    int32_t done = 0;
+
+    // ---- tile-height autotuning on the first two (real) sweeps ----
+    if (tile_h == 0) {
+        hipEvent_t ev[3];
+        for (auto& e : ev) MPR_HIP(hipEventCreate(&e));
+        MPR_HIP(hipEventRecord(ev[0], s));
+        MPR_HIP(mpr::launch_batch_step(b, 0, 1, grid, max_hw_blocks, s));
+        MPR_HIP(hipEventRecord(ev[1], s));
+        MPR_HIP(mpr::launch_batch_step(b, 1, 1, grid, max_hw_blocks, s));
+        MPR_HIP(hipEventRecord(ev[2], s));
+        MPR_HIP(hipEventSynchronize(ev[2]));
+        float t16 = 0.f, t32 = 0.f;
+        MPR_HIP(hipEventElapsedTime(&t16, ev[0], ev[1]));
+        MPR_HIP(hipEventElapsedTime(&t32, ev[1], ev[2]));
+        for (auto& e : ev) MPR_HIP(hipEventDestroy(e));
+        variant = t16 < t32 ? 0 : 1;
+        done = 2;
+        if (variant == 0) {                // the work list after sweep 2 was built for tiles of height 32
+            MPR_HIP(hipMemcpyAsync(&runs[0], w.runs, sizeof(mpr::BatchRun) * n_scenes, hipMemcpyDeviceToHost, s));
+            MPR_HIP(hipStreamSynchronize(s));
+            int64_t acc = 0;
+            for (int i = 0; i < n_scenes; ++i) {
+                prefix[i] = acc;
+                if (runs[order[i]].phase < 2) acc += work16[order[i]];
+            }
+            prefix[n_scenes] = acc;
+            MPR_HIP(hipMemcpyAsync(w.prefix, prefix.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice,
+                                   s));
+            MPR_HIP(hipStreamSynchronize(s));
+        }
+    }
+    if (tile_h_used_out) *tile_h_used_out = variant ? 32 : 16;
+
+    // ---- the sweep loop: a graph of n_f sweeps replayed until every scene is done ----
+    const int per_graph = c.stop_mode == MPR_STOP_AUTO ? std::max(1, c.n_f) : 5;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = capture_stream();
+    if (cs) {
+        hipGraph_t graph = nullptr;
+        bool okc = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int i = 0; okc && i < per_graph; ++i)
+            okc = mpr::launch_batch_step(b, variant, variant, grid, max_hw_blocks, cs) == hipSuccess;
+        hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (okc && ec == hipSuccess && graph) {
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    int active = n_scenes;
+    while (active > 0 && done < total_max + 1) {
+        if (exec) {
+            MPR_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int i = 0; i < per_graph; ++i) MPR_HIP(mpr::launch_batch_step(b, variant, variant, grid, max_hw_blocks, s));
+        }
+        done += per_graph;
+        mpr::BatchCtl hc;
+        MPR_HIP(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
+        MPR_HIP(hipStreamSynchronize(s));
+        active = hc.n_active;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (active > 0) return fail(MPR_ERR_HIP, "batched simulation did not finish within %d sweeps", total_max);
+
+    // ---- results: final buffers into the callers' state, k* per scene ----
+    MPR_HIP(hipMemcpyAsync(runs.data(), w.runs, sizeof(mpr::BatchRun) * n_scenes, hipMemcpyDeviceToHost, s));
+    MPR_HIP(hipStreamSynchronize(s));
+    bool all_converged = true;
+    for (int i = 0; i < n_scenes; ++i) {
+        const int total = runs[i].k_star + c.n_samp;
+        if (total & 1)
+            MPR_HIP(hipMemcpyAsync(scenes[i].state, w.alt[i], sizeof(float) * (size_t)(R * hs[i].HW),
+                                   hipMemcpyDeviceToDevice, s));
+        if (sweeps_done_out) sweeps_done_out[i] = runs[i].k_star;
+        all_converged &= runs[i].converged != 0;
+    }
+    if (!all_converged) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
     return ok();
 }
 

@@ -1,0 +1,249 @@
+// Batched conditional simulation: many scenes of different sizes and gap fractions advance together, one sweep
+// per launch of a persistent kernel that takes (scene, tile, realization chunk) work items from a global queue.
+//
+// Every scene keeps its own random stream (its scene id), temperatures, stopping test and sampling sweeps, so its
+// results are bit-identical to a single-scene run.  All per-sweep control lives on the device (sweep counter,
+// queue head, per-scene phase, work-list prefix), so a chunk of sweeps is a fixed sequence of launches that can be
+// captured once in a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include "batched.hpp"
+#include "sweep_body.hpp"
+
+namespace mpr {
+
+namespace {
+
+__device__ __forceinline__ SweepFusedArgs scene_args(const BatchScene& d, const BatchCfg& c, int variant, int k)
+{
+    SweepFusedArgs a;
+    a.src = d.buf[(k - 1) & 1];
+    a.dst = d.buf[k & 1];
+    a.mask = d.mask;
+    a.Tb = d.tp;
+    a.H = d.H;
+    a.W = d.W;
+    a.lb_h = d.lb_h;
+    a.lb_w = d.lb_w;
+    a.nbx = d.nbx;
+    a.ntx = d.ntx;
+    a.nty = d.nty[variant];
+    a.ntiles = d.ntiles[variant];
+    a.Mw = d.Mw;
+    a.R = c.R;
+    a.rchunk = d.rchunk[variant];
+    a.nchunks = d.nchunks[variant];
+    a.tile_h = variant ? 32 : 16;
+    a.HW = d.HW;
+    a.sweep = (uint32_t)k;
+    a.real_offset = c.real_offset;
+    a.scene = d.scene;
+    a.key0 = c.key0;
+    a.key1 = c.key1;
+    a.q = c.q;
+    a.J = c.J;
+    a.delta_e = c.delta_e;
+    a.two_pi_q = c.two_pi_q;
+    a.Jd = c.Jd;
+    a.e_partial = nullptr;
+    return a;
+}
+
+}  // namespace
+
+// Persistent sweep: workgroups take items until the queue is empty.  Items are numbered through the work-list
+// prefix of the scenes in longest-first order; item -> (scene, tile, chunk).
+template <int FTH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_batch_sweep(
+    const BatchScene* __restrict__ scenes, const BatchRun* __restrict__ runs, const int* __restrict__ order,
+    const int64_t* __restrict__ prefix, BatchCtl* ctl, BatchCfg c, int n_scenes)
+{
+    __shared__ LdsT<FTH> L;
+    __shared__ int64_t s_item;
+    constexpr int variant = FTH == 32 ? 1 : 0;
+    const int k = ctl->k;
+    const int64_t n_items = prefix[n_scenes];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ctl->queue, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        int lo = 0, hi = n_scenes;            // largest i with prefix[i] <= item
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (prefix[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int s = order[lo];
+        const BatchScene& d = scenes[s];
+        SweepFusedArgs a = scene_args(d, c, variant, k);
+        if (c.energy && runs[s].phase == 0) a.e_partial = d.epart;
+        const int64_t local = item - prefix[lo];
+        sweep_tile<FTH>(L, a, (int)(local % a.ntiles), (int)(local / a.ntiles));
+    }
+}
+
+__global__ void k_batch_begin(BatchCtl* ctl)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->k += 1;
+        ctl->queue = 0ull;
+    }
+}
+
+// e_real[r] of every equilibrating scene: one workgroup per (scene, realization), tiles summed in a fixed order.
+__global__ __launch_bounds__(256) void k_batch_energy_real(const BatchScene* scenes, const BatchRun* runs,
+                                                            BatchCfg c, int variant)
+{
+    __shared__ double lds[4];
+    const int s = blockIdx.x, r = blockIdx.y;
+    if (runs[s].phase != 0) return;
+    const BatchScene& d = scenes[s];
+    const int nt = d.ntiles[variant];
+    const double* row = d.epart + (int64_t)r * nt;
+    double v = 0.0;
+    for (int p = threadIdx.x; p < nt; p += 256) v += row[p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) d.e_real[r] = (((lds[0] + lds[1]) + lds[2]) + lds[3]) * d.inv_norm;
+}
+
+__global__ __launch_bounds__(256) void k_batch_energy_mean(const BatchScene* scenes, const BatchRun* runs,
+                                                            const BatchCtl* ctl, BatchCfg c, int n_scenes)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_scenes || runs[s].phase != 0) return;
+    const BatchScene& d = scenes[s];
+    double sum = 0.0;
+    for (int r = 0; r < c.R; ++r) sum += d.e_real[r];
+    d.series[ctl->k] = sum / (double)c.R;
+}
+
+// Sampling scenes: acc += sum over realizations (in order) of the state after this sweep.
+__global__ __launch_bounds__(256) void k_batch_accumulate(const BatchScene* scenes, const BatchRun* runs,
+                                                           const BatchCtl* ctl, BatchCfg c)
+{
+    const int s = blockIdx.y;
+    const BatchRun run = runs[s];
+    if (run.phase != 1) return;
+    const BatchScene& d = scenes[s];
+    const float* st = d.buf[ctl->k & 1];
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
+        if (d.mask[n]) {
+            if (run.samp == 0) d.acc[n] = 0.0;
+            continue;
+        }
+        double acc = run.samp == 0 ? 0.0 : d.acc[n];
+        for (int r = 0; r < c.R; ++r) acc += (double)st[(int64_t)r * d.HW + n];
+        d.acc[n] = acc;
+    }
+}
+
+// Sec. 3.4 test on the device (same reading as the single-scene driver): OLS slope of the last n_fit energies,
+// equilibrium when it no longer points away from the starting energy.
+__device__ bool batch_equilibrium(const double* series, int k, int n_fit)
+{
+    const double* y = series + (k - n_fit + 1);
+    double xm = 0.0, ym = 0.0;
+    for (int j = 0; j < n_fit; ++j) {
+        xm += (double)j;
+        ym += y[j];
+    }
+    xm /= (double)n_fit;
+    ym /= (double)n_fit;
+    double sxy = 0.0, sxx = 0.0;
+    for (int j = 0; j < n_fit; ++j) {
+        sxy += ((double)j - xm) * (y[j] - ym);
+        sxx += ((double)j - xm) * ((double)j - xm);
+    }
+    const double beta = sxx > 0.0 ? sxy / sxx : 0.0;
+    const double d = series[k] - series[0];
+    const double sigma0 = (double)((d > 0.0) - (d < 0.0));
+    return beta * sigma0 <= 0.0;
+}
+
+// Phase transitions after sweep k, then the work-list prefix over the scenes still running (one workgroup).
+__global__ __launch_bounds__(256) void k_batch_phase(const BatchScene* scenes, BatchRun* runs, const int* order,
+                                                      int64_t* prefix, BatchCtl* ctl, BatchCfg c, int n_scenes,
+                                                      int variant)
+{
+    const int k = ctl->k;
+    for (int s = threadIdx.x; s < n_scenes; s += 256) {
+        BatchRun run = runs[s];
+        if (run.phase == 0) {
+            bool stop = false;
+            if (c.stop_mode == 1) {
+                if (k >= c.n_fit + c.n_f && (k - c.n_fit) % c.n_f == 0)
+                    stop = batch_equilibrium(scenes[s].series, k, c.n_fit);
+                if (!stop && k >= c.n_max) {
+                    stop = true;
+                    run.converged = 0;
+                }
+            } else {
+                stop = k >= c.n_eq;
+            }
+            if (stop) {
+                run.phase = c.n_samp > 0 ? 1 : 2;
+                run.k_star = k;
+            }
+        } else if (run.phase == 1) {
+            run.samp += 1;
+            if (run.samp >= c.n_samp) run.phase = 2;
+        }
+        runs[s] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        int active = 0;
+        for (int i = 0; i < n_scenes; ++i) {
+            prefix[i] = acc;
+            const int s = order[i];
+            if (runs[s].phase < 2) {
+                acc += (int64_t)scenes[s].ntiles[variant] * scenes[s].nchunks[variant];
+                ++active;
+            }
+        }
+        prefix[n_scenes] = acc;
+        ctl->n_active = active;
+    }
+}
+
+hipError_t launch_batch_sweep(const BatchDev& b, int variant, int grid, hipStream_t s)
+{
+    if (variant)
+        hipLaunchKernelGGL(k_batch_sweep<32>, dim3(grid), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix,
+                           b.ctl, b.cfg, b.n);
+    else
+        hipLaunchKernelGGL(k_batch_sweep<16>, dim3(grid), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix,
+                           b.ctl, b.cfg, b.n);
+    return hipGetLastError();
+}
+
+// One sweep of the batch: counter, sweep, energies of the equilibrating scenes, accumulation of the sampling
+// scenes, phase transitions and the next work list.
+hipError_t launch_batch_step(const BatchDev& b, int variant, int next_variant, int grid, int acc_blocks,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_batch_sweep(b, variant, grid, s)) != hipSuccess) return e;
+    if (b.cfg.energy) {
+        hipLaunchKernelGGL(k_batch_energy_real, dim3(b.n, b.cfg.R), dim3(256), 0, s, b.scenes, b.runs, b.cfg, variant);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_batch_energy_mean, dim3((b.n + 255) / 256), dim3(256), 0, s, b.scenes, b.runs, b.ctl,
+                           b.cfg, b.n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_batch_accumulate, dim3(acc_blocks, b.n), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.ctl, b.cfg,
+                       b.n, next_variant);
+    return hipGetLastError();
+}
+
+}  // namespace mpr

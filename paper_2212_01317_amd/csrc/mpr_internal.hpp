@@ -81,13 +81,14 @@ struct SweepFusedArgs {
     const uint8_t* mask;
     const TPair* Tb;
     int H, W, lb_h, lb_w, nbx, ntx, nty, ntiles, Mw, R, rchunk, nchunks;
+    int tile_h;          // 16 or 32 (tile width is 64)
     int64_t HW;
     uint32_t sweep, real_offset, scene, key0, key1;
     float q, J, delta_e;
     double two_pi_q, Jd;
     double* e_partial;   // [R][ntiles] energy of each tile's colour-1 bonds, or null
 };
-void fused_geometry(int64_t H, int64_t W, int R, int* ntx, int* nty, int* rchunk, int* nchunks);
+void fused_geometry(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int* rchunk, int* nchunks);
 hipError_t launch_sweep_fused(const SweepFusedArgs& a, hipStream_t s);
 hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
                               int nparts, hipStream_t s);
@@ -102,6 +103,14 @@ hipError_t launch_predict(const double* acc, const float* z, const uint8_t* mask
 hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t* ev, int64_t n, double* part,
                            int nblocks, double* out, hipStream_t s);
 int validate_blocks(int64_t n);
+
+// ---- temperature gradient (grad.hip) ----
+hipError_t launch_block_energy(const float* state, const uint8_t* mask, const StatsGeom& g, double two_pi_q,
+                               double J, int R, double* part, double* Hrb, hipStream_t s);
+int grad_parts(int64_t HW);
+hipError_t launch_temperature_grad(const float* state, const double* Hrb, const float* gz, const uint8_t* mask,
+                                   int64_t HW, int R, int64_t B, const double* range, const float* T_blocks,
+                                   double* part, double* g, double* dT, hipStream_t s);
 
 struct RefArgs {
     float* state;          // [nT][L][L]

@@ -1,0 +1,407 @@
+// Body of the fused red/black Metropolis sweep for gfx950 (Sec. 2.2.2 single checkerboard, block temperatures),
+// shared by the single-scene kernel (sweep.hip) and the batched persistent kernel (batched.hip).
+//
+// One call = one sweep k of one 64 x FTH tile for a chunk of realizations.  The state is double-buffered: the tile
+// reads sweep k-1 from `src` and writes sweep k to `dst`, so it may read its neighbours' cells while they are being
+// updated elsewhere.
+//
+// Staged once per call: the sample cells of the tile and a two-site ring (their angles and (cos, sin) never
+// change), the temperature of every block the region touches, the compacted lists of pairs to update, the list of
+// colour-1 sample sites that border a gap, and the energy of the bonds that only join samples.
+//
+// Per realization:
+//   1. the gap cells of the region arrive from registers (loaded during the previous realization) and get their
+//      (cos, sin) of 2 pi q t; the next realization's gap cells are then requested into registers;
+//   2. colour 0 is updated on the tile and on the one-site ring around it: a ring site's update uses the same
+//      counter-based random numbers and the same neighbours as in the tile that owns it, so it is bit-identical;
+//   3. colour 1 is updated on the tile (its colour-0 neighbours, ring included, are now current); the energy of the
+//      bonds of each updated colour-1 site is taken from the local field just computed;
+//   4. the bonds of colour-1 sample sites that touch a gap are added (each bond has exactly one colour-1 end, so
+//      the tiles together count every bond once), and the gap cells of the tile are written to `dst`.
+//
+// LDS layout: per colour, per row, the cells of that colour are contiguous ("colour-split"), so the neighbourhood
+// of a same-colour pair is five vector LDS reads.  A cell's angle is stored negated (sign bit set, -0 for 0) when it
+// is a sample or lies outside the grid: such cells are never updated.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "metropolis.hpp"
+
+namespace mpr {
+
+template <int FTH>
+struct Tile {
+    static constexpr int FT_W = 64, FT_H = FTH, FS_NT = 256;
+    static constexpr int RH = FT_H + 4;          // LDS rows: tile rows plus two above and two below
+    static constexpr int RW = FT_W + 4;          // region columns: tile plus two on each side
+    static constexpr int CW = 40;                // LDS cells per colour per row (34 used, 3 leading, 3 trailing pads)
+    static constexpr int NPR = FT_W / 4 + 2;     // pairs per row touching the tile or its one-site ring (0 .. 17)
+    static constexpr int MAX_RED = (FT_H + 2) * NPR;
+    static constexpr int MAX_BLK = FT_H * (FT_W / 4);
+    static constexpr int MAX_EOBS = FT_H * (FT_W / 2);
+    // Region cells per thread: the 64 middle columns are walked by lane (tid & 63) on rows (tid >> 6) + 4k,
+    // k < RH / 4; the four side columns (0, 1, 66, 67) of the RH rows by threads 0 .. 4 RH - 1, one each.
+    static constexpr int MAIN_K = RH / 4;
+    static constexpr int CPT = MAIN_K + 1;
+    static constexpr int TP_CAP = 64;            // temperature blocks a region may touch for the LDS table
+    static_assert(RH % 4 == 0 && 4 * RH <= FS_NT, "cell walk assumes RH % 4 == 0 and 4 RH <= 256");
+};
+
+template <int FTH>
+struct alignas(16) LdsT {
+    using C = Tile<FTH>;
+    float2 cs[2][C::RH][C::CW];               // (cos, sin) of 2 pi q t, per colour
+    float t[2][C::RH][C::CW];                 // angles per colour; negative (or -0) = sample / outside the grid
+    int brow[C::RH];                          // temperature-block row offset per LDS row
+    int bcol[C::RW];                          // temperature-block column per region column
+    TPair tp[C::TP_CAP];                      // temperatures of the blocks the region touches
+    uint16_t items[C::MAX_RED + C::MAX_BLK];  // colour-0 then colour-1 pairs: row << 8 | pair << 2 | site mask
+    uint16_t eobs[C::MAX_EOBS];               // colour-1 sample sites of the tile with a gap neighbour: row << 8 | J
+    int wcnt[C::FS_NT / 64];
+    double red[C::FS_NT / 64];
+};
+
+__device__ __forceinline__ int cell_J(int xl) { return (xl >> 1) + 3; }
+__device__ __forceinline__ bool is_fixed(float t) { return __float_as_uint(t) >> 31; }
+
+// Appends `val` to list[base ...] for the threads with `flag`, in thread order; every thread must call it.
+__device__ __forceinline__ int compact(bool flag, uint16_t val, uint16_t* list, int base, int* wcnt)
+{
+    const uint64_t bal = __ballot(flag);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) wcnt[wid] = __popcll(bal);
+    __syncthreads();
+    int off = base, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if (w < wid) off += wcnt[w];
+        tot += wcnt[w];
+    }
+    if (flag) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = val;
+    __syncthreads();
+    return base + tot;
+}
+
+// Updates the listed pairs of one colour.  With ENERGY, returns the summed energy of the bonds of the updated
+// sites (colour 1 only: their neighbours are final).
+template <int FTH, int COLOUR, bool ENERGY>
+__device__ __forceinline__ float update_pairs(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* items,
+                                              int n_items, int ty0, int tx0, uint32_t r_global, bool use_table)
+{
+    constexpr int OC = COLOUR ^ 1;
+    const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COLOUR);
+    const uint32_t pm_base = (uint32_t)(tx0 / 4) - 1u;
+    float e_sum = 0.0f;
+    for (int it = threadIdx.x; it < n_items; it += Tile<FTH>::FS_NT) {
+        const unsigned code = items[it];
+        const int yl = (int)(code >> 8), pl = (int)((code >> 2) & 63u), sm = (int)(code & 3u);
+        const int gy = ty0 - 2 + yl;
+        const int delta = (gy + COLOUR) & 1;
+        const int Ja = 2 * pl + 2;
+        const U4 w = philox_x3((uint32_t)gy * (uint32_t)a.Mw + pm_base + (uint32_t)pl, a.sweep, r_global, w3, a.key0,
+                               a.key1);
+        const float4 own = *reinterpret_cast<const float4*>(&L.cs[COLOUR][yl][Ja]);
+        const float4 up = *reinterpret_cast<const float4*>(&L.cs[OC][yl - 1][Ja]);
+        const float4 dn = *reinterpret_cast<const float4*>(&L.cs[OC][yl + 1][Ja]);
+        const float4 m2 = *reinterpret_cast<const float4*>(&L.cs[OC][yl][Ja]);
+        const float2 side = L.cs[OC][yl][delta ? Ja + 2 : Ja - 1];
+        const float2 rl = delta ? make_float2(m2.x, m2.y) : side;
+        const float2 rm = delta ? make_float2(m2.z, m2.w) : make_float2(m2.x, m2.y);
+        const float2 rr = delta ? side : make_float2(m2.z, m2.w);
+        const int row_b = L.brow[yl];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!((sm >> h) & 1)) continue;
+            const float2 u = h ? make_float2(up.z, up.w) : make_float2(up.x, up.y);
+            const float2 d = h ? make_float2(dn.z, dn.w) : make_float2(dn.x, dn.y);
+            const float2 l = h ? rm : rl;
+            const float2 rt = h ? rr : rm;
+            const float2 o = h ? make_float2(own.z, own.w) : make_float2(own.x, own.y);
+            const float Cx = ((u.x + l.x) + rt.x) + d.x;
+            const float Sy = ((u.y + l.y) + rt.y) + d.y;
+            const float tp = u24(h ? w.z : w.x);
+            const float u2 = u24(h ? w.w : w.y);
+            const float ang = a.q * tp;
+            const float cp = cos_rev(ang), sp = sin_rev(ang);
+            const float dE = -a.J * fmaf(cp - o.x, Cx, (sp - o.y) * Sy);
+            const int J = Ja + h;
+            const int xl = 4 * (pl - 1) + delta + 2 * h + 2;     // region column
+            const int bidx = row_b + L.bcol[xl];
+            const TPair T = use_table ? L.tp[bidx] : a.Tb[bidx];
+            int dec = filter32(dE, T, u2, a.delta_e);
+            if (dec < 0) {
+                const int gx = tx0 - 2 + xl;
+                const unsigned present = (gy > 0 ? 1u : 0u) | (gx > 0 ? 2u : 0u) | (gx + 1 < a.W ? 4u : 0u) |
+                                         (gy + 1 < a.H ? 8u : 0u);
+                const int Jl = J - 1 + delta, Jr = J + delta;
+                dec = exact64(tp, L.t[COLOUR][yl][J], fabsf(L.t[OC][yl - 1][J]), fabsf(L.t[OC][yl][Jl]),
+                              fabsf(L.t[OC][yl][Jr]), fabsf(L.t[OC][yl + 1][J]), present, a.two_pi_q, a.Jd, T.T, u2)
+                          ? 1
+                          : 0;
+            }
+            float cf = o.x, sf = o.y;
+            if (dec) {
+                L.t[COLOUR][yl][J] = tp;
+                L.cs[COLOUR][yl][J] = make_float2(cp, sp);
+                cf = cp;
+                sf = sp;
+            }
+            if (ENERGY) e_sum += -a.J * fmaf(cf, Cx, sf * Sy);
+        }
+    }
+    return e_sum;
+}
+
+// Energy of all bonds of a colour-1 site at (yl, J) from the LDS values.
+template <int FTH>
+__device__ __forceinline__ float site_energy1(const LdsT<FTH>& L, int yl, int J, int delta, float Jc)
+{
+    const float2 o = L.cs[1][yl][J];
+    const float2 u = L.cs[0][yl - 1][J], d = L.cs[0][yl + 1][J];
+    const float2 l = L.cs[0][yl][J - 1 + delta], rt = L.cs[0][yl][J + delta];
+    const float Cx = ((u.x + l.x) + rt.x) + d.x;
+    const float Sy = ((u.y + l.y) + rt.y) + d.y;
+    return -Jc * fmaf(o.x, Cx, o.y * Sy);
+}
+
+// One sweep of tile `tile` (row-major in a.ntx x a.nty tiles) for realizations
+// [chunk * a.rchunk, min(R, (chunk + 1) * a.rchunk)).  Every thread of the workgroup must call it; LDS is free
+// again when it returns.
+template <int FTH>
+__device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a, int tile, int chunk)
+{
+    using C = Tile<FTH>;
+    constexpr int FT_W = C::FT_W, FT_H = C::FT_H, FS_NT = C::FS_NT, RH = C::RH, RW = C::RW, CW = C::CW;
+    constexpr int NPR = C::NPR, MAX_RED = C::MAX_RED, MAX_BLK = C::MAX_BLK, MAX_EOBS = C::MAX_EOBS;
+    constexpr int MAIN_K = C::MAIN_K, CPT = C::CPT;
+    const int tid = threadIdx.x;
+    const int tx0 = (tile % a.ntx) * FT_W, ty0 = (tile / a.ntx) * FT_H;
+    const int W = a.W, H = a.H;
+    const int r_begin = chunk * a.rchunk;
+    const int r_end = r_begin + a.rchunk < a.R ? r_begin + a.rchunk : a.R;
+
+    // ---- setup 1: zero the cell arrays (outside cells stay (t = -0, cs = 0)), temperature-block tables ----
+    {
+        float* z = &L.cs[0][0][0].x;
+        for (int i = tid; i < 2 * RH * CW * 2; i += FS_NT) z[i] = 0.0f;
+        float* zt = &L.t[0][0][0];
+        for (int i = tid; i < 2 * RH * CW; i += FS_NT) zt[i] = -0.0f;
+    }
+    const int gy_lo = ty0 - 2 > 0 ? ty0 - 2 : 0, gy_hi = ty0 + FT_H + 1 < H - 1 ? ty0 + FT_H + 1 : H - 1;
+    const int gx_lo = tx0 - 2 > 0 ? tx0 - 2 : 0, gx_hi = tx0 + FT_W + 1 < W - 1 ? tx0 + FT_W + 1 : W - 1;
+    const int by0 = gy_lo / a.lb_h, bx0 = gx_lo / a.lb_w;
+    const int nby_l = gy_hi / a.lb_h - by0 + 1, nbx_l = gx_hi / a.lb_w - bx0 + 1;
+    const bool use_table = nby_l * nbx_l <= C::TP_CAP;
+    if (tid < RH) {
+        const int gy = ty0 - 2 + tid;
+        int v = 0;
+        if (gy >= 0 && gy < H) v = use_table ? (gy / a.lb_h - by0) * nbx_l : (gy / a.lb_h) * a.nbx;
+        L.brow[tid] = v;
+    } else if (tid >= 64 && tid < 64 + RW) {
+        const int gx = tx0 - 2 + (tid - 64);
+        int v = 0;
+        if (gx >= 0 && gx < W) v = use_table ? gx / a.lb_w - bx0 : gx / a.lb_w;
+        L.bcol[tid - 64] = v;
+    } else if (use_table && tid >= 192 && tid < 192 + C::TP_CAP) {
+        const int i = tid - 192;
+        if (i < nby_l * nbx_l) L.tp[i] = a.Tb[(int64_t)(by0 + i / nbx_l) * a.nbx + bx0 + i % nbx_l];
+    }
+    __syncthreads();
+
+    // ---- setup 2: sample cells (from any realization: samples are the same in all), gap bits of my cells ----
+    const float* __restrict__ src0 = a.src + (int64_t)r_begin * a.HW;
+    const int lane64 = tid & 63, row0 = tid >> 6;
+    const int64_t W4 = (int64_t)4 * W;
+    // my middle-column cells: region (row0 + 4k, 2 + lane64) = grid (ty0 - 2 + row0 + 4k, tx0 + lane64)
+    const int gx_m = tx0 + lane64;
+    const int64_t off_m = (int64_t)(ty0 - 2 + row0) * W + gx_m;
+    const int g_m = (ty0 + tx0 + row0 + lane64) & 1;
+    const int J_m = cell_J(2 + lane64);
+    // my side cell (threads < 4 RH): region (tid >> 2, {0, 1, 66, 67}[tid & 3])
+    const int yl_s = tid >> 2;
+    const int xl_s = (tid & 3) < 2 ? (tid & 3) : RW - 4 + (tid & 3);
+    const int gy_s = ty0 - 2 + yl_s, gx_s = tx0 - 2 + xl_s;
+    const int64_t off_s = (int64_t)gy_s * W + gx_s;
+    const int g_s = (ty0 + tx0 + yl_s + xl_s) & 1;
+    const int J_s = cell_J(xl_s);
+    const bool side_in = tid < 4 * RH && gy_s >= 0 && gy_s < H && gx_s >= 0 && gx_s < W;
+    uint32_t gapbits = 0;
+#pragma unroll
+    for (int k = 0; k < MAIN_K; ++k) {
+        const int gy = ty0 - 2 + row0 + 4 * k;
+        if (gy >= 0 && gy < H && gx_m < W) {
+            const int64_t n = off_m + k * W4;
+            if (a.mask[n]) {
+                const float v = src0[n];
+                const float ang = a.q * v;
+                L.t[g_m][row0 + 4 * k][J_m] = -v;
+                L.cs[g_m][row0 + 4 * k][J_m] = make_float2(cos_rev(ang), sin_rev(ang));
+            } else {
+                gapbits |= 1u << k;
+            }
+        }
+    }
+    if (side_in) {
+        if (a.mask[off_s]) {
+            const float v = src0[off_s];
+            const float ang = a.q * v;
+            L.t[g_s][yl_s][J_s] = -v;
+            L.cs[g_s][yl_s][J_s] = make_float2(cos_rev(ang), sin_rev(ang));
+        } else {
+            gapbits |= 1u << MAIN_K;
+        }
+    }
+    // first realization's gap cells into registers, and mark the gap cells (positive) for the lists below
+    float pre[CPT];
+#pragma unroll
+    for (int k = 0; k < MAIN_K; ++k) {
+        pre[k] = 0.0f;
+        if ((gapbits >> k) & 1u) {
+            pre[k] = src0[off_m + k * W4];
+            L.t[g_m][row0 + 4 * k][J_m] = 0.5f;
+        }
+    }
+    pre[MAIN_K] = 0.0f;
+    if ((gapbits >> MAIN_K) & 1u) {
+        pre[MAIN_K] = src0[off_s];
+        L.t[g_s][yl_s][J_s] = 0.5f;
+    }
+    __syncthreads();
+
+    // ---- setup 3: compacted lists (deterministic order) ----
+    int n0 = 0;
+    for (int base = 0; base < MAX_RED; base += FS_NT) {
+        const int i = base + tid;
+        bool f = false;
+        uint16_t code = 0;
+        if (i < MAX_RED) {
+            const int yl = 1 + i / NPR, pl = i % NPR;
+            const int delta = (ty0 - 2 + yl) & 1;           // colour 0
+            unsigned sm = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int xrel = 4 * (pl - 1) + delta + 2 * h;
+                if (xrel >= -1 && xrel <= FT_W && !is_fixed(L.t[0][yl][cell_J(xrel + 2)])) sm |= 1u << h;
+            }
+            f = sm != 0;
+            code = (uint16_t)((yl << 8) | (pl << 2) | sm);
+        }
+        n0 = compact(f, code, L.items, n0, L.wcnt);
+    }
+    int n1 = 0;
+    for (int base = 0; base < MAX_BLK; base += FS_NT) {
+        const int i = base + tid;
+        bool f = false;
+        uint16_t code = 0;
+        if (i < MAX_BLK) {
+            const int yl = 2 + i / (FT_W / 4), pl = 1 + i % (FT_W / 4);
+            const int delta = (ty0 - 2 + yl + 1) & 1;       // colour 1
+            unsigned sm = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int xrel = 4 * (pl - 1) + delta + 2 * h;
+                if (!is_fixed(L.t[1][yl][cell_J(xrel + 2)])) sm |= 1u << h;
+            }
+            f = sm != 0;
+            code = (uint16_t)((yl << 8) | (pl << 2) | sm);
+        }
+        n1 = compact(f, code, L.items + n0, n1, L.wcnt);
+    }
+    // colour-1 sample sites of the tile: with a gap neighbour -> list; otherwise their energy is constant
+    int ne = 0;
+    float e_const = 0.0f;
+    for (int base = 0; base < MAX_EOBS; base += FS_NT) {
+        const int i = base + tid;
+        bool f = false;
+        uint16_t code = 0;
+        const int yl = 2 + i / (FT_W / 2);
+        const int gy = ty0 - 2 + yl;
+        const int delta = (gy + 1) & 1;
+        const int xrel = 2 * (i % (FT_W / 2)) + delta;
+        const int J = cell_J(xrel + 2);
+        if (i < MAX_EOBS && gy < H && tx0 + xrel < W && is_fixed(L.t[1][yl][J])) {
+            const bool touches_gap = !is_fixed(L.t[0][yl - 1][J]) || !is_fixed(L.t[0][yl + 1][J]) ||
+                                     !is_fixed(L.t[0][yl][J - 1 + delta]) || !is_fixed(L.t[0][yl][J + delta]);
+            if (touches_gap) {
+                f = true;
+                code = (uint16_t)((yl << 8) | J);
+            } else {
+                e_const += site_energy1<FTH>(L, yl, J, delta, a.J);
+            }
+        }
+        ne = compact(f, code, L.eobs, ne, L.wcnt);
+    }
+    const double e_const_d = (double)e_const;
+
+    // ---- realizations ----
+    for (int r = r_begin; r < r_end; ++r) {
+        float* __restrict__ dst = a.dst + (int64_t)r * a.HW;
+        // 1. gap cells from registers
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            if ((gapbits >> k) & 1u) {
+                const float v = pre[k];
+                const float ang = a.q * v;
+                const float2 cs = make_float2(cos_rev(ang), sin_rev(ang));
+                if (k < MAIN_K) {
+                    L.t[g_m][row0 + 4 * k][J_m] = v;
+                    L.cs[g_m][row0 + 4 * k][J_m] = cs;
+                } else {
+                    L.t[g_s][yl_s][J_s] = v;
+                    L.cs[g_s][yl_s][J_s] = cs;
+                }
+            }
+        }
+        __syncthreads();
+        if (r + 1 < r_end) {
+            const float* __restrict__ srcn = a.src + (int64_t)(r + 1) * a.HW;
+#pragma unroll
+            for (int k = 0; k < MAIN_K; ++k)
+                if ((gapbits >> k) & 1u) pre[k] = srcn[off_m + k * W4];
+            if ((gapbits >> MAIN_K) & 1u) pre[MAIN_K] = srcn[off_s];
+        }
+        const uint32_t rg = a.real_offset + (uint32_t)r;
+        // 2. colour 0 on tile + ring
+        update_pairs<FTH, 0, false>(L, a, L.items, n0, ty0, tx0, rg, use_table);
+        __syncthreads();
+        // 3. colour 1 on the tile
+        float e = 0.0f;
+        if (a.e_partial)
+            e = update_pairs<FTH, 1, true>(L, a, L.items + n0, n1, ty0, tx0, rg, use_table);
+        else
+            update_pairs<FTH, 1, false>(L, a, L.items + n0, n1, ty0, tx0, rg, use_table);
+        __syncthreads();
+        // 4. sample sites bordering gaps, write-back
+        if (a.e_partial) {
+            for (int i = tid; i < ne; i += FS_NT) {
+                const unsigned code = L.eobs[i];
+                const int yl = (int)(code >> 8), J = (int)(code & 255u);
+                e += site_energy1<FTH>(L, yl, J, (ty0 - 2 + yl + 1) & 1, a.J);
+            }
+            double v = e_const_d + (double)e;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((tid & 63) == 0) L.red[tid >> 6] = v;
+        }
+        // the tile's cells are my middle-column cells shifted by two rows: rows row0 + 2 + 4k, k < FT_H / 4
+#pragma unroll
+        for (int k = 0; k < FT_H / 4; ++k) {
+            const int yl = row0 + 2 + 4 * k;
+            const float v = L.t[g_m][yl][J_m];
+            if (is_fixed(v)) continue;                      // samples and cells outside the grid
+            dst[off_m + (int64_t)(2 + 4 * k) * W] = v;
+        }
+        __syncthreads();
+        if (a.e_partial && tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < FS_NT / 64; ++i) s += L.red[i];
+            a.e_partial[(int64_t)r * a.ntiles + tile] = s;
+        }
+    }
+}
+
+}  // namespace mpr
