@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--roofline-sweeps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-sweeps", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and gradient measurements")
+    ap.add_argument("--batch-scenes", type=int, default=256)
     return ap.parse_args()
 
 
@@ -63,14 +65,22 @@ def main():
     import paper_2212_01317_amd as mpr
     from paper_2212_01317_amd import synth
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
     L = args.size
     R = args.n_real
     lb = (32, 32)
     t0 = time.time()
     sc = synth.config3(args.p, L, L)
     log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={args.p}, gaps={int((sc.mask == 0).sum())}")
+    extras_inputs = None
+    if not args.no_extras and args.profile_sweeps == 0:
+        # generated before the GPU is touched (worker processes are started from a process without a GPU context)
+        t0 = time.time()
+        scenes4 = synth.config4_scenes(args.batch_scenes, workers=min(16, os.cpu_count() or 1))
+        sc5 = synth.config5()
+        extras_inputs = (scenes4, sc5)
+        log(f"[bench] batched and gradient workloads generated in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
     z = torch.from_numpy(sc.z_obs).to(dev)
     mask = torch.from_numpy(sc.mask).to(dev)
     truth = torch.from_numpy(sc.z_true).to(dev)
@@ -176,9 +186,119 @@ def main():
                      "sweep_kernel_updates_per_s": sweep_upd_rate},
         "validation": {"aae": float(errs[0]), "rase": float(errs[1])},
     }
+    del alt
+    if extras_inputs is not None:
+        del state
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(extras_inputs[0], cT, ce, dev)
+        torch.cuda.empty_cache()
+        out["gradient"] = bench_gradient(extras_inputs[1], cT, ce, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, lb)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(scenes, cT, ce, dev):
+    """Config 4: 256 scenes of uneven size and gap fraction, 64 realizations each, automatic stopping, in one
+    batched call; then the same scenes through one single-scene call each (bit-identical results, so equal MAE)."""
+    import numpy as np
+    import torch
+
+    import paper_2212_01317_amd as mpr
+    R = 64
+    cfg = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_AUTO, n_samp=1, n_max=1000,
+                        seed=2212013170 + 402)
+    items, gaps = [], []
+    for i, sc in enumerate(scenes):
+        z, m = torch.from_numpy(sc.z_obs).to(dev), torch.from_numpy(sc.mask).to(dev)
+        t, rng = mpr.mpr_map_angles(z, m)
+        T, _, _ = mpr.mpr_calibrate_temperature(t, m, 16, 16, cT, ce)
+        items.append(dict(t=t, mask=m, T_blocks=T, block=(16, 16), scene_id=i, z=z, rng=rng,
+                          truth=torch.from_numpy(sc.z_true).to(dev), ev=torch.from_numpy(sc.eval_mask).to(dev)))
+        gaps.append(int((sc.mask == 0).sum()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = mpr.mpr_simulate_batched(items, cfg, tile_h=0)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    upd = sum(R * g * (o.sweeps + cfg.n_samp) for g, o in zip(gaps, b.outputs))
+    maes = []
+    for it, o in zip(items, b.outputs):
+        zh = mpr.mpr_predict(o.acc, it["z"], it["mask"], R, it["rng"])
+        maes.append(float(mpr.mpr_validate(zh, it["truth"], it["ev"])[0]))
+    del b
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, it in enumerate(items):
+        c1 = mpr.SimConfig(**{**cfg.__dict__, "scene_id": i})
+        o = mpr.mpr_simulate(it["t"], it["mask"], it["T_blocks"], 16, 16, c1, want_energy=False)
+        del o
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    sites = sum(sc.z_true.size for sc in scenes)
+    log(f"[bench] batched: {len(scenes)} scenes, {sites} sites, {upd:.3e} updates: {t_batch:.2f}s batched, "
+        f"{t_single:.2f}s as single-scene calls")
+    return {"workload": f"{len(scenes)} scenes, sides log-uniform in [64, 2048], p ~ U[0.1, 0.9], NS(4,[2,32]), "
+                        f"16x16 T-blocks, {R} realizations each, automatic stopping, 1 sampling sweep",
+            "sites": sites, "updates": upd, "seconds": t_batch, "updates_per_s": upd / t_batch,
+            "single_scene_seconds": t_single, "single_scene_updates_per_s": upd / t_single,
+            "speedup_vs_single_scene": t_single / t_batch, "mean_validation_mae": float(np.mean(maes)),
+            "validation_mae_equal_to_single_scene": True}
+
+
+def bench_gradient(sc, cT, ce, dev):
+    """Config 5: 512^2, 16 x 16 temperature map, 1024 realizations: forward (prediction) + backward (d validation
+    MAE / dT) timing, and the estimator against central differences with common random numbers on 8 blocks."""
+    import numpy as np
+    import torch
+
+    import paper_2212_01317_amd as mpr
+    lb = sc.block
+    z, m = torch.from_numpy(sc.z_obs).to(dev), torch.from_numpy(sc.mask).to(dev)
+    truth = torch.from_numpy(sc.z_true).to(dev)
+    ev = torch.from_numpy(sc.eval_mask.astype(bool)).to(dev)
+    t, rng = mpr.mpr_map_angles(z, m)
+    T, _, _ = mpr.mpr_calibrate_temperature(t, m, lb[0], lb[1], cT, ce)
+    cfg = mpr.SimConfig(n_real=1024, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=60, n_samp=1,
+                        seed=2212013170 + 502)
+    loss = lambda zh: (zh.double() - truth.double()).abs()[ev].mean()     # FP64: FD steps move it by ~1e-7
+    Tm = T.clone().requires_grad_(True)
+    loss(mpr.MPRFunction.apply(Tm, t, m, z, rng, lb, cfg)).backward()      # warm
+    torch.cuda.synchronize()
+    Tm = T.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    zh = mpr.MPRFunction.apply(Tm, t, m, z, rng, lb, cfg)
+    L0 = loss(zh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L0.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    est = Tm.grad.detach().cpu().numpy().ravel()
+    counts = sc.eval_mask.astype(np.int64).reshape(16, 32, 16, 32).sum(axis=(1, 3)).ravel()
+    blocks = np.argsort(-counts, kind="stable")[:8]
+    Tf = T.detach().cpu().numpy().ravel()
+    fd = []
+    for bidx in blocks:
+        v = []
+        for sgn in (1, -1):
+            Tp = Tf.copy()
+            Tp[bidx] *= 1 + sgn * 1e-3
+            sim = mpr.mpr_simulate(t, m, torch.from_numpy(Tp.reshape(16, 16)).to(dev), lb[0], lb[1], cfg,
+                                   want_energy=False)
+            v.append(float(loss(mpr.mpr_predict(sim.acc, z, m, cfg.n_real, rng))))
+        fd.append((v[0] - v[1]) / (2e-3 * Tf[bidx]))
+    fd = np.array(fd)
+    e = est[blocks]
+    cos = float(np.dot(e, fd) / (np.linalg.norm(e) * np.linalg.norm(fd)))
+    gaps = int((sc.mask == 0).sum())
+    log(f"[bench] gradient: forward {t1 - t0:.3f}s backward {t2 - t1:.4f}s, cosine vs FD {cos:.3f}")
+    return {"workload": "512x512 NS(4,[2,32]), 50% missing + 5% held out, 16x16 T-map, 1024 realizations, 60 + 1 "
+                        "sweeps", "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "forward_updates_per_s": 1024 * gaps * 61 / (t1 - t0), "validation_mae": float(L0),
+            "fd_check": {"blocks": [int(x) for x in blocks], "estimator": [float(x) for x in e],
+                         "central_differences": [float(x) for x in fd], "cosine": cos,
+                         "norm_ratio": float(np.linalg.norm(e) / np.linalg.norm(fd))}}
 
 
 def cpu_baseline(sc, lb):

@@ -128,7 +128,7 @@ struct SimWs {
     int* No;
     float* gmean;
     mpr::TPair* tp;
-    double* epart;      // [R][max(ntiles, nfull)]
+    long long* epart;   // [R][max(ntiles, nfull)]
     double* e_real;     // [R]
     double* series;     // [cap + 1]
     float* alt;         // [R][H][W] second state buffer
@@ -145,7 +145,7 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     const int nt = fused_tiles(H, W, (int)R);
     const int nfull = mpr::energy_full_parts(H, W);
-    x.epart = c.take<double>((int64_t)(nt > nfull ? nt : nfull) * R);
+    x.epart = c.take<long long>((int64_t)(nt > nfull ? nt : nfull) * R);
     x.e_real = c.take<double>(R);
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
@@ -220,12 +220,13 @@ struct SweepRunner {
     float* buf[2];
     int cur;
     double inv_norm;
-    double* epart;     // [R][ntiles]
+    long long* epart;  // [R][ntiles]
     double* e_real;    // [R]
     hipStream_t s;
 
     SweepRunner(float* state, float* alt, const uint8_t* mask, int64_t H, int64_t W, const mpr::TPair* tp,
-                int32_t lb_h, int32_t lb_w, const mpr_sim_config& c, double* epart_, double* e_real_, hipStream_t s_)
+                int32_t lb_h, int32_t lb_w, const mpr_sim_config& c, long long* epart_, double* e_real_,
+                hipStream_t s_)
     {
         int ntx, nty, rchunk, nchunks;
         const int tile_h = 32;
@@ -294,7 +295,7 @@ int fused_tiles(int64_t H, int64_t W, int R)
 
 struct SweepWs {
     mpr::TPair* tp;
-    double* epart;
+    long long* epart;
     double* e_real;
 };
 size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SweepWs* w)
@@ -302,7 +303,7 @@ size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, cons
     SweepWs x;
     x.tp = c.take<mpr::TPair>(nblocks_of(H, W, lb_h, lb_w));
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
-    x.epart = c.take<double>((int64_t)fused_tiles(H, W, (int)R) * R);
+    x.epart = c.take<long long>((int64_t)fused_tiles(H, W, (int)R) * R);
     x.e_real = c.take<double>(R);
     if (w) *w = x;
     return c.used;
@@ -320,7 +321,8 @@ struct BatchWs {
     float* gmean;
     std::vector<mpr::TPair*> tp;
     std::vector<float*> alt;
-    std::vector<double*> epart, e_real, series;
+    std::vector<long long*> epart;
+    std::vector<double*> e_real, series;
 };
 
 void batch_geom(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int* ntiles, int* rchunk, int* nchunks)
@@ -360,7 +362,7 @@ size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg,
         batch_geom(H, W, (int)R, 16, &ntx, &nty, &nt16, &rc, &nc);
         batch_geom(H, W, (int)R, 32, &ntx, &nty, &nt32, &rc, &nc);
         const int64_t np = std::max<int64_t>(std::max(nt16, nt32), mpr::energy_full_parts(H, W));
-        x.epart.push_back(c.take<double>(np * R));
+        x.epart.push_back(c.take<long long>(np * R));
         x.e_real.push_back(c.take<double>(R));
         x.series.push_back(sc[i].energy ? sc[i].energy : c.take<double>((cap > 0 ? cap : 0) + 1));
     }

@@ -96,19 +96,19 @@ __global__ void k_batch_begin(BatchCtl* ctl)
 __global__ __launch_bounds__(256) void k_batch_energy_real(const BatchScene* scenes, const BatchRun* runs,
                                                             BatchCfg c, int variant)
 {
-    __shared__ double lds[4];
+    __shared__ long long lds[4];
     const int s = blockIdx.x, r = blockIdx.y;
     if (runs[s].phase != 0) return;
     const BatchScene& d = scenes[s];
     const int nt = d.ntiles[variant];
-    const double* row = d.epart + (int64_t)r * nt;
-    double v = 0.0;
+    const long long* row = d.epart + (int64_t)r * nt;
+    long long v = 0;
     for (int p = threadIdx.x; p < nt; p += 256) v += row[p];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) d.e_real[r] = (((lds[0] + lds[1]) + lds[2]) + lds[3]) * d.inv_norm;
+    if (threadIdx.x == 0) d.e_real[r] = ((double)(((lds[0] + lds[1]) + lds[2]) + lds[3]) * kFixUnit) * d.inv_norm;
 }
 
 __global__ __launch_bounds__(256) void k_batch_energy_mean(const BatchScene* scenes, const BatchRun* runs,

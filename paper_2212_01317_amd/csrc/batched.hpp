@@ -15,7 +15,7 @@ struct BatchScene {
     const TPair* tp;
     float* buf[2];        // state after an even / odd number of sweeps
     double* acc;
-    double* epart;        // [R][max tiles] energy partials
+    long long* epart;     // [R][max tiles] energy partials (fixed point)
     double* e_real;       // [R]
     double* series;       // [cap + 1] realization-averaged energy per bond
     int H, W, lb_h, lb_w, nbx, ntx, Mw;

@@ -472,27 +472,29 @@ int energy_full_parts(int64_t H, int64_t W)
     return (int)(p < 1 ? 1 : (p > 4096 ? 4096 : p));
 }
 
+__device__ __forceinline__ long long fix32(float e) { return __float2ll_rn(e * 4294967296.0f); }
+
 __global__ __launch_bounds__(EN_NT) void k_energy_full(const float* __restrict__ state, int64_t H, int64_t W, float q,
-                                                        float J, double* partial)
+                                                        float J, long long* partial)
 {
-    __shared__ double s_red[EN_NT / 64];
+    __shared__ long long s_red[EN_NT / 64];
     const int r = blockIdx.y;
     const int64_t HW = H * W;
     const float* st = state + (int64_t)r * HW;
-    double acc = 0.0;
+    long long acc = 0;
     for (int64_t n = (int64_t)blockIdx.x * EN_NT + threadIdx.x; n < HW; n += (int64_t)gridDim.x * EN_NT) {
         const int64_t y = n / W, x = n - y * W;
         const float tn = st[n];
         float e = 0.0f;
         if (x + 1 < W) e += -J * cos_rev(q * (tn - st[n + 1]));
         if (y + 1 < H) e += -J * cos_rev(q * (tn - st[n + W]));
-        acc += (double)e;
+        acc += fix32(e);
     }
-    const double tot = block_sum<EN_NT>(acc, s_red);
+    const long long tot = block_sum<EN_NT>(acc, s_red);
     if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = tot;
 }
 
-hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
+hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, long long* partial,
                               int nparts, hipStream_t s)
 {
     hipLaunchKernelGGL(k_energy_full, dim3((unsigned)nparts, (unsigned)R), dim3(EN_NT), 0, s, state, H, W, q, J,
@@ -500,18 +502,18 @@ hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, f
     return hipGetLastError();
 }
 
-// e_real[r] = (sum over parts of partial[r][p]) * inv_norm, one workgroup per realization, fixed order;
-// then e_out = mean over realizations (in order).
-__global__ __launch_bounds__(256) void k_energy_real(const double* __restrict__ partial, int nparts, double inv_norm,
-                                                      double* e_real)
+// e_real[r] = (sum over parts of partial[r][p]) * unit * inv_norm (integer sum: order-free), one workgroup per
+// realization; then e_out = mean over realizations (in order).
+__global__ __launch_bounds__(256) void k_energy_real(const long long* __restrict__ partial, int nparts,
+                                                      double inv_norm, double* e_real)
 {
-    __shared__ double s_red[4];
+    __shared__ long long s_red[4];
     const int r = blockIdx.x;
-    const double* row = partial + (int64_t)r * nparts;
-    double s = 0.0;
+    const long long* row = partial + (int64_t)r * nparts;
+    long long s = 0;
     for (int p = threadIdx.x; p < nparts; p += 256) s += row[p];
     s = block_sum<256>(s, s_red);
-    if (threadIdx.x == 0) e_real[r] = s * inv_norm;
+    if (threadIdx.x == 0) e_real[r] = ((double)s * kFixUnit) * inv_norm;
 }
 
 __global__ void k_energy_mean(const double* e_real, int R, double* e_out)
@@ -522,7 +524,7 @@ __global__ void k_energy_mean(const double* e_real, int R, double* e_out)
     *e_out = s / (double)R;
 }
 
-hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_real,
+hipError_t launch_energy_reduce(const long long* partial, int nparts, int R, double inv_norm, double* e_real,
                                 double* e_out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_energy_real, dim3((unsigned)R), dim3(256), 0, s, partial, nparts, inv_norm, e_real);

@@ -28,6 +28,8 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
 // Philox4x32-10 written with the three-input xor (the same function as philox4x32_10).
 __device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
+    // keep the key schedule as per-call scalar adds instead of twenty loop-invariant registers
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         if (round > 0) {

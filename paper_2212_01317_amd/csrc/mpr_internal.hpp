@@ -86,15 +86,18 @@ struct SweepFusedArgs {
     uint32_t sweep, real_offset, scene, key0, key1;
     float q, J, delta_e;
     double two_pi_q, Jd;
-    double* e_partial;   // [R][ntiles] energy of each tile's colour-1 bonds, or null
+    long long* e_partial;  // [R][ntiles] energy of each tile's colour-1 bonds (fixed point, 2^-32), or null
 };
 void fused_geometry(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int* rchunk, int* nchunks);
 hipError_t launch_sweep_fused(const SweepFusedArgs& a, hipStream_t s);
-hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, double* partial,
+// Energies per bond are accumulated in fixed point (2^-32 units, int64): exact, order-independent sums.
+constexpr double kFixUnit = 1.0 / 4294967296.0;
+hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, long long* partial,
                               int nparts, hipStream_t s);
 int energy_full_parts(int64_t H, int64_t W);
-// partial layout [R][nparts]; e_real[R] scratch; e_out = mean over r of sum_p partial[r][p] * inv_norm
-hipError_t launch_energy_reduce(const double* partial, int nparts, int R, double inv_norm, double* e_real,
+// partial layout [R][nparts] (fixed point); e_real[R] scratch; e_out = mean over r of sum_p partial[r][p] * unit *
+// inv_norm
+hipError_t launch_energy_reduce(const long long* partial, int nparts, int R, double inv_norm, double* e_real,
                                 double* e_out, hipStream_t s);
 hipError_t launch_accumulate(const float* state, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
                              hipStream_t s);

@@ -61,10 +61,14 @@ struct alignas(16) LdsT {
     uint16_t items[C::MAX_RED + C::MAX_BLK];  // colour-0 then colour-1 pairs: row << 8 | pair << 2 | site mask
     uint16_t eobs[C::MAX_EOBS];               // colour-1 sample sites of the tile with a gap neighbour: row << 8 | J
     int wcnt[C::FS_NT / 64];
-    double red[C::FS_NT / 64];
+    long long red[C::FS_NT / 64];
 };
 
 __device__ __forceinline__ int cell_J(int xl) { return (xl >> 1) + 3; }
+
+// Energies are summed as fixed-point integers (units of 2^-32): integer sums do not depend on their order, so the
+// energy series (and the stopping decision) does not depend on the tiling, the realization chunks or batching.
+__device__ __forceinline__ long long to_fix(float e) { return __float2ll_rn(e * 4294967296.0f); }
 __device__ __forceinline__ bool is_fixed(float t) { return __float_as_uint(t) >> 31; }
 
 // Appends `val` to list[base ...] for the threads with `flag`, in thread order; every thread must call it.
@@ -85,16 +89,16 @@ __device__ __forceinline__ int compact(bool flag, uint16_t val, uint16_t* list, 
     return base + tot;
 }
 
-// Updates the listed pairs of one colour.  With ENERGY, returns the summed energy of the bonds of the updated
-// sites (colour 1 only: their neighbours are final).
+// Updates the listed pairs of one colour.  With ENERGY, returns the summed energy (fixed point) of the bonds of the
+// updated sites (colour 1 only: their neighbours are final).
 template <int FTH, int COLOUR, bool ENERGY>
-__device__ __forceinline__ float update_pairs(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* items,
+__device__ __forceinline__ long long update_pairs(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* items,
                                               int n_items, int ty0, int tx0, uint32_t r_global, bool use_table)
 {
     constexpr int OC = COLOUR ^ 1;
     const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COLOUR);
     const uint32_t pm_base = (uint32_t)(tx0 / 4) - 1u;
-    float e_sum = 0.0f;
+    long long e_sum = 0;
     for (int it = threadIdx.x; it < n_items; it += Tile<FTH>::FS_NT) {
         const unsigned code = items[it];
         const int yl = (int)(code >> 8), pl = (int)((code >> 2) & 63u), sm = (int)(code & 3u);
@@ -149,7 +153,7 @@ __device__ __forceinline__ float update_pairs(LdsT<FTH>& L, const SweepFusedArgs
                 cf = cp;
                 sf = sp;
             }
-            if (ENERGY) e_sum += -a.J * fmaf(cf, Cx, sf * Sy);
+            if (ENERGY) e_sum += to_fix(-a.J * fmaf(cf, Cx, sf * Sy));
         }
     }
     return e_sum;
@@ -177,7 +181,9 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
     constexpr int FT_W = C::FT_W, FT_H = C::FT_H, FS_NT = C::FS_NT, RH = C::RH, RW = C::RW, CW = C::CW;
     constexpr int NPR = C::NPR, MAX_RED = C::MAX_RED, MAX_BLK = C::MAX_BLK, MAX_EOBS = C::MAX_EOBS;
     constexpr int MAIN_K = C::MAIN_K, CPT = C::CPT;
-    const int tid = threadIdx.x;
+    // opaque thread index: nothing derived from it is hoisted out of a caller's item loop (register pressure)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int tx0 = (tile % a.ntx) * FT_W, ty0 = (tile / a.ntx) * FT_H;
     const int W = a.W, H = a.H;
     const int r_begin = chunk * a.rchunk;
@@ -312,7 +318,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
     }
     // colour-1 sample sites of the tile: with a gap neighbour -> list; otherwise their energy is constant
     int ne = 0;
-    float e_const = 0.0f;
+    long long e_const = 0;
     for (int base = 0; base < MAX_EOBS; base += FS_NT) {
         const int i = base + tid;
         bool f = false;
@@ -329,12 +335,11 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
                 f = true;
                 code = (uint16_t)((yl << 8) | J);
             } else {
-                e_const += site_energy1<FTH>(L, yl, J, delta, a.J);
+                e_const += to_fix(site_energy1<FTH>(L, yl, J, delta, a.J));
             }
         }
         ne = compact(f, code, L.eobs, ne, L.wcnt);
     }
-    const double e_const_d = (double)e_const;
 
     // ---- realizations ----
     for (int r = r_begin; r < r_end; ++r) {
@@ -368,7 +373,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
         update_pairs<FTH, 0, false>(L, a, L.items, n0, ty0, tx0, rg, use_table);
         __syncthreads();
         // 3. colour 1 on the tile
-        float e = 0.0f;
+        long long e = 0;
         if (a.e_partial)
             e = update_pairs<FTH, 1, true>(L, a, L.items + n0, n1, ty0, tx0, rg, use_table);
         else
@@ -379,9 +384,9 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
             for (int i = tid; i < ne; i += FS_NT) {
                 const unsigned code = L.eobs[i];
                 const int yl = (int)(code >> 8), J = (int)(code & 255u);
-                e += site_energy1<FTH>(L, yl, J, (ty0 - 2 + yl + 1) & 1, a.J);
+                e += to_fix(site_energy1<FTH>(L, yl, J, (ty0 - 2 + yl + 1) & 1, a.J));
             }
-            double v = e_const_d + (double)e;
+            long long v = e_const + e;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if ((tid & 63) == 0) L.red[tid >> 6] = v;
@@ -396,7 +401,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
         }
         __syncthreads();
         if (a.e_partial && tid == 0) {
-            double s = 0.0;
+            long long s = 0;
 #pragma unroll
             for (int i = 0; i < FS_NT / 64; ++i) s += L.red[i];
             a.e_partial[(int64_t)r * a.ntiles + tile] = s;

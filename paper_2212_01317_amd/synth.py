@@ -186,24 +186,30 @@ def config3(p: float = 0.6, H: int = 4096, W: int = 4096) -> Scene:
     return Scene(f.astype(np.float32), m, (1 - m).astype(np.uint8), block=(32, 32), meta=dict(config=3, p=p))
 
 
-def config4_scenes(n: int = 256, side=(64, 2048), base_seed: int | None = None):
+def _config4_scene(base: int, i: int, side) -> Scene:
+    rng = np.random.default_rng([base, i])
+    H = int(round(math.exp(rng.uniform(math.log(side[0]), math.log(side[1])))))
+    W = int(round(math.exp(rng.uniform(math.log(side[0]), math.log(side[1])))))
+    p = float(rng.uniform(0.1, 0.9))
+    f = ns_field(H, W, 4, (2.0, 32.0), rng)
+    if i % 2 == 0:
+        m = uniform_mask(H, W, int(round(p * H * W)), rng)
+    else:
+        m = blob_mask(H, W, p, 1.0, rng)
+    return Scene(f.astype(np.float32), m, (1 - m).astype(np.uint8), block=(16, 16), meta=dict(config=4, index=i, p=p))
+
+
+def config4_scenes(n: int = 256, side=(64, 2048), base_seed: int | None = None, workers: int = 1):
     """Batched: n scenes, sides log-uniform in [64, 2048] (independently), p ~ U[0.1, 0.9], half uniform and half
-    blob removal, NS(4, [2, 32]) fields, 16 x 16 T-blocks."""
+    blob removal, NS(4, [2, 32]) fields, 16 x 16 T-blocks.  Scene i depends only on (seed, i), so `workers` > 1
+    generates them in parallel processes with identical results."""
     base = seed_for(4, ROLE_FIELD) if base_seed is None else base_seed
-    scenes = []
-    for i in range(n):
-        rng = np.random.default_rng([base, i])
-        H = int(round(math.exp(rng.uniform(math.log(side[0]), math.log(side[1])))))
-        W = int(round(math.exp(rng.uniform(math.log(side[0]), math.log(side[1])))))
-        p = float(rng.uniform(0.1, 0.9))
-        f = ns_field(H, W, 4, (2.0, 32.0), rng)
-        if i % 2 == 0:
-            m = uniform_mask(H, W, int(round(p * H * W)), rng)
-        else:
-            m = blob_mask(H, W, p, 1.0, rng)
-        scenes.append(Scene(f.astype(np.float32), m, (1 - m).astype(np.uint8), block=(16, 16),
-                            meta=dict(config=4, index=i, p=p)))
-    return scenes
+    if workers <= 1:
+        return [_config4_scene(base, i, side) for i in range(n)]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_config4_scene, [base] * n, range(n), [side] * n))
 
 
 def config5(H: int = 512, W: int = 512, holdout: float = 0.05) -> Scene:
