@@ -668,6 +668,7 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
     TPair tp;
     tp.T = T;
     tp.nl2T = T > 0.0f ? (float)(-1.4426950408889634074 / (double)T) : 0.0f;
+    const float band = band_of(tp.nl2T, a.delta_e);
     const U4 w = philox_x3((uint32_t)p, a.sweep, (uint32_t)chain, ctr_word3(0u, TAG_REFLAT, a.colour), a.key0,
                                a.key1);
     const int yu = (y + L - 1) % L, yd = (y + 1) % L;
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
         const float u2 = u24(h ? w.w : w.y);
         const float cp = cos_rev(a.q * tpv), sp = sin_rev(a.q * tpv);
         const float dE = -fmaf(cp - co, Cx, (sp - so) * Sy);
-        int dec = filter32(dE, tp, u2, a.delta_e);
+        int dec = filter32(dE, tp.T, tp.nl2T, band, u2, a.delta_e);
         if (dec < 0) dec = exact64(tpv, to, nb[0], nb[1], nb[2], nb[3], 15u, a.two_pi_q, 1.0, T, u2) ? 1 : 0;
         if (dec) st[y * L + x] = tpv;
     }

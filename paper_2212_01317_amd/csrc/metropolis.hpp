@@ -51,15 +51,22 @@ __device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, u
 // FP32 Metropolis filter.  Returns 1 = accept, 0 = reject, -1 = inside the error band (the exact FP64 test decides).
 // dE is the FP32 energy change with |dE - dE_exact| <= delta.  The exact test is u2 < exp(-dE/T) (T > 0) or
 // dE <= 0 (T == 0).  With y = dE * nl2T = log2 of the acceptance ratio, |y - y_exact| <= delta |nl2T| + |y| 2^-22,
-// and the relative error of w = 2^y is ln 2 |y - y_exact| plus the v_exp_f32 error (below 2^-22); the band is that
-// bound with a 25 % margin, plus an absolute 2^-30 for results that flush to zero.
-__device__ __forceinline__ int filter32(float dE, TPair tp, float u2, float delta)
+// and the relative error of w = 2^y is ln 2 |y - y_exact| plus the v_exp_f32 error (below 2^-22).  The band is
+// that bound with a 25 % margin, rel = |y| kBandY + band with band = band_of(nl2T, delta) per temperature, plus an
+// absolute 2^-30 for results that flush to zero.
+constexpr float kBandY = 1.25f * 0.6931472f * 2.3841858e-7f;
+__device__ __forceinline__ float band_of(float nl2T, float delta)
 {
-    if (tp.T > 0.0f) {
-        const float y = dE * tp.nl2T;
+    return fmaf(1.25f * 0.6931472f * delta, fabsf(nl2T), 1.25f * 2.3841858e-7f);
+}
+
+__device__ __forceinline__ int filter32(float dE, float T, float nl2T, float band, float u2, float delta)
+{
+    if (T > 0.0f) {
+        const float y = dE * nl2T;
         if (y >= 1.0f) return 1;
         const float w = exp2_fast(y);
-        const float rel = 1.25f * (0.6931472f * fmaf(delta, fabsf(tp.nl2T), fabsf(y) * 2.3841858e-7f) + 2.3841858e-7f);
+        const float rel = fmaf(fabsf(y), kBandY, band);
         if (fabsf(u2 - w) <= fmaf(w, rel, 9.3132257e-10f)) return -1;
         return u2 < w ? 1 : 0;
     }

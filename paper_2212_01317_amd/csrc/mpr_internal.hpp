@@ -21,6 +21,11 @@ struct TPair {
     float nl2T;    // -log2(e) / T, or 0 when T == 0
 };
 
+// Per-block temperature as the sweep keeps it in LDS: with the error band of its FP32 filter.
+struct alignas(16) TBand {
+    float T, nl2T, band, pad;
+};
+
 // Bump allocator over the caller's workspace (256-byte aligned slices).
 struct Carve {
     char* base;
