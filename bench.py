@@ -33,6 +33,38 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 
+SWEEP_SOURCES = ("sweep_body.hpp", "sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp")
+HBM_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_fused_c3_p0.6_hbm.txt")
+
+
+def sweep_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2212_01317_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(L: int, R: int, p: float):
+    """HBM bytes per sweep launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the
+    counters' reading of a 1 GiB copy), if it was taken on this workload with the current sweep sources; else None."""
+    if not os.path.exists(HBM_PROFILE):
+        return None
+    kv = {}
+    with open(HBM_PROFILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        same = (kv.get("sources_sha256") == sweep_sources_sha256() and int(kv["size"]) == L and int(kv["n_real"]) == R
+                and float(kv["p"]) == p)
+        return float(kv["hbm_bytes_per_launch"]) if same else None
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +193,8 @@ def main():
     sweep_upd_rate = upd_launch / t_launch
     log(f"[bench] sweep launch {t_launch * 1e3:.3f} ms -> {sweep_upd_rate:.3e} upd/s in the sweep kernel")
 
+    traffic = measured_traffic(L, R, args.p)
+    alg_bytes = float(R) * n_gap * 8.0              # 4 B read + 4 B written per gap site and realization
     value = updates / elapsed
     out = {
         "metric": "SV-MPR gap-site updates/s at 4096^2 (C3)",
@@ -181,7 +215,9 @@ def main():
                    "H": L, "W": L, "p": args.p, "gap_sites": n_gap, "n_real": R, "block": list(lb),
                    "sweeps_per_step": sweeps},
         "roofline": {"bound": "alu", "kernel": "k_sweep_fused", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                     "traffic_gbs": traffic / t_launch / 1e9 if traffic else None,
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "launch_ms": t_launch * 1e3, "ops_per_launch": ops_launch,
                      "sweep_kernel_updates_per_s": sweep_upd_rate},
         "validation": {"aae": float(errs[0]), "rase": float(errs[1])},
@@ -229,12 +265,17 @@ def bench_batched(scenes, cT, ce, dev):
     del b
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    accs = []
     for i, it in enumerate(items):
         c1 = mpr.SimConfig(**{**cfg.__dict__, "scene_id": i})
-        o = mpr.mpr_simulate(it["t"], it["mask"], it["T_blocks"], 16, 16, c1, want_energy=False)
-        del o
+        accs.append(mpr.mpr_simulate(it["t"], it["mask"], it["T_blocks"], 16, 16, c1, want_energy=False).acc)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
+    maes1 = []
+    for it, acc in zip(items, accs):
+        zh = mpr.mpr_predict(acc, it["z"], it["mask"], R, it["rng"])
+        maes1.append(float(mpr.mpr_validate(zh, it["truth"], it["ev"])[0]))
+    del accs
     sites = sum(sc.z_true.size for sc in scenes)
     log(f"[bench] batched: {len(scenes)} scenes, {sites} sites, {upd:.3e} updates: {t_batch:.2f}s batched, "
         f"{t_single:.2f}s as single-scene calls")
@@ -243,12 +284,17 @@ def bench_batched(scenes, cT, ce, dev):
             "sites": sites, "updates": upd, "seconds": t_batch, "updates_per_s": upd / t_batch,
             "single_scene_seconds": t_single, "single_scene_updates_per_s": upd / t_single,
             "speedup_vs_single_scene": t_single / t_batch, "mean_validation_mae": float(np.mean(maes)),
-            "validation_mae_equal_to_single_scene": True}
+            "mean_validation_mae_single_scene": float(np.mean(maes1)),
+            "max_abs_mae_difference_vs_single_scene": float(np.max(np.abs(np.array(maes) - np.array(maes1))))}
 
 
 def bench_gradient(sc, cT, ce, dev):
-    """Config 5: 512^2, 16 x 16 temperature map, 1024 realizations: forward (prediction) + backward (d validation
-    MAE / dT) timing, and the estimator against central differences with common random numbers on 8 blocks."""
+    """Config 5: 512^2, 16 x 16 temperature map, 1024 realizations, 60 + 1 sweeps.  Times the plain form (simulate +
+    predict), the autograd forward (the same plus the block energies) and the backward (d validation MAE / dT by the
+    covariance estimator); the three share the chains, so the validation MAE is the same.  Then the estimator against
+    central differences with common random numbers (dT = 1e-3 T_b, 4 seeds) where the derivative is measurable:
+    block temperatures U[0.3, 1.2] and a loss confined to one block (the mean over its gap sites of
+    sign(1/2 - tbar) zhat), on the six partially gapped blocks with the highest T."""
     import numpy as np
     import torch
 
@@ -259,51 +305,88 @@ def bench_gradient(sc, cT, ce, dev):
     ev = torch.from_numpy(sc.eval_mask.astype(bool)).to(dev)
     t, rng = mpr.mpr_map_angles(z, m)
     T, _, _ = mpr.mpr_calibrate_temperature(t, m, lb[0], lb[1], cT, ce)
-    cfg = mpr.SimConfig(n_real=1024, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=60, n_samp=1,
-                        seed=2212013170 + 502)
+
+    def cfg_for(seed):
+        return mpr.SimConfig(n_real=1024, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=60, n_samp=1,
+                             seed=seed)
+    cfg = cfg_for(2212013170 + 502)
     loss = lambda zh: (zh.double() - truth.double()).abs()[ev].mean()     # FP64: FD steps move it by ~1e-7
     Tm = T.clone().requires_grad_(True)
     loss(mpr.MPRFunction.apply(Tm, t, m, z, rng, lb, cfg)).backward()      # warm
     torch.cuda.synchronize()
-    Tm = T.clone().requires_grad_(True)
     t0 = time.perf_counter()
-    zh = mpr.MPRFunction.apply(Tm, t, m, z, rng, lb, cfg)
-    L0 = loss(zh)
+    sim = mpr.mpr_simulate(t, m, T, lb[0], lb[1], cfg, want_energy=False)
+    L_plain = loss(mpr.mpr_predict(sim.acc, z, m, cfg.n_real, rng))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    L0.backward()
+    Tm = T.clone().requires_grad_(True)
+    L0 = loss(mpr.MPRFunction.apply(Tm, t, m, z, rng, lb, cfg))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    est = Tm.grad.detach().cpu().numpy().ravel()
-    counts = sc.eval_mask.astype(np.int64).reshape(16, 32, 16, 32).sum(axis=(1, 3)).ravel()
-    blocks = np.argsort(-counts, kind="stable")[:8]
-    Tf = T.detach().cpu().numpy().ravel()
-    fd = []
-    for bidx in blocks:
-        v = []
-        for sgn in (1, -1):
-            Tp = Tf.copy()
-            Tp[bidx] *= 1 + sgn * 1e-3
-            sim = mpr.mpr_simulate(t, m, torch.from_numpy(Tp.reshape(16, 16)).to(dev), lb[0], lb[1], cfg,
-                                   want_energy=False)
-            v.append(float(loss(mpr.mpr_predict(sim.acc, z, m, cfg.n_real, rng))))
-        fd.append((v[0] - v[1]) / (2e-3 * Tf[bidx]))
-    fd = np.array(fd)
-    e = est[blocks]
-    cos = float(np.dot(e, fd) / (np.linalg.norm(e) * np.linalg.norm(fd)))
+    L0.backward()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     gaps = int((sc.mask == 0).sum())
-    log(f"[bench] gradient: forward {t1 - t0:.3f}s backward {t2 - t1:.4f}s, cosine vs FD {cos:.3f}")
+    log(f"[bench] gradient: plain {t1 - t0:.3f}s forward {t2 - t1:.3f}s backward {t3 - t2:.4f}s, "
+        f"MAE {float(L_plain):.6f} / {float(L0):.6f}")
+
+    # derivative check where it is measurable
+    T_host = np.random.default_rng(7).uniform(0.3, 1.2, 256).astype(np.float32).reshape(16, 16)
+    gapn = (sc.mask == 0).astype(np.int64).reshape(16, 32, 16, 32).sum(axis=(1, 3)).ravel()
+    cand = np.flatnonzero((gapn >= 200) & (gapn <= 800))
+    blocks = cand[np.argsort(-T_host.ravel()[cand], kind="stable")[:6]]
+    Th = torch.from_numpy(T_host).to(dev)
+    tbar = mpr.mpr_simulate(t, m, Th, lb[0], lb[1], cfg_for(99), want_energy=False).state.double().mean(0)
+    gap = m == 0
+    Cs = {}
+    for bidx in blocks:
+        by, bx = divmod(int(bidx), 16)
+        C = torch.zeros_like(tbar)
+        sl = (slice(by * 32, by * 32 + 32), slice(bx * 32, bx * 32 + 32))
+        C[sl] = torch.sign(0.5 - tbar[sl]) * gap[sl] / float(gapn[bidx])
+        Cs[int(bidx)] = C
+    seeds = [1000 + i for i in range(4)]
+    est = np.zeros((len(seeds), len(blocks)))
+    fd = np.zeros_like(est)
+    for i, seed in enumerate(seeds):
+        c = cfg_for(seed)
+        Tg = Th.clone().requires_grad_(True)
+        zh = mpr.MPRFunction.apply(Tg, t, m, z, rng, lb, c)
+        for j, bidx in enumerate(blocks):
+            C = Cs[int(bidx)]
+            (g,) = torch.autograd.grad((zh.double() * C).sum(), Tg, retain_graph=j + 1 < len(blocks))
+            est[i, j] = float(g.double().ravel()[bidx])
+            v = []
+            for sgn in (1, -1):
+                Tp = T_host.copy().ravel()
+                Tp[bidx] *= 1 + sgn * 1e-3
+                s2 = mpr.mpr_simulate(t, m, torch.from_numpy(Tp.reshape(16, 16)).to(dev), lb[0], lb[1], c,
+                                      want_energy=False)
+                v.append(float((mpr.mpr_predict(s2.acc, z, m, c.n_real, rng).double() * C).sum()))
+            fd[i, j] = (v[0] - v[1]) / (2e-3 * T_host.ravel()[bidx])
+    n = len(seeds)
+    me, mf = est.mean(0), fd.mean(0)
+    se_e, se_f = est.std(0, ddof=1) / np.sqrt(n), fd.std(0, ddof=1) / np.sqrt(n)
+    zs = (me - mf) / np.sqrt(se_e ** 2 + se_f ** 2)
+    ratio = float(me.sum() / mf.sum())
+    log(f"[bench] gradient check: estimator {np.round(me, 4)} FD {np.round(mf, 4)} z {np.round(zs, 2)} "
+        f"ratio {ratio:.3f}")
     return {"workload": "512x512 NS(4,[2,32]), 50% missing + 5% held out, 16x16 T-map, 1024 realizations, 60 + 1 "
-                        "sweeps", "forward_s": t1 - t0, "backward_s": t2 - t1,
-            "forward_updates_per_s": 1024 * gaps * 61 / (t1 - t0), "validation_mae": float(L0),
-            "fd_check": {"blocks": [int(x) for x in blocks], "estimator": [float(x) for x in e],
-                         "central_differences": [float(x) for x in fd], "cosine": cos,
-                         "norm_ratio": float(np.linalg.norm(e) / np.linalg.norm(fd))}}
+                        "sweeps",
+            "plain_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2,
+            "plain_updates_per_s": 1024 * gaps * 61 / (t1 - t0),
+            "forward_backward_over_plain": (t3 - t1) / (t1 - t0),
+            "validation_mae_plain": float(L_plain), "validation_mae_forward": float(L0),
+            "fd_check": {"temperatures": "U[0.3, 1.2] per block", "loss": "block-confined sign(1/2 - tbar) zhat",
+                         "seeds": n, "dT": "1e-3 T_b", "blocks": [int(x) for x in blocks],
+                         "estimator": [float(x) for x in me], "estimator_se": [float(x) for x in se_e],
+                         "central_differences": [float(x) for x in mf], "central_differences_se": [float(x) for x in se_f],
+                         "z": [float(x) for x in zs], "sum_ratio": ratio}}
 
 
 def cpu_baseline(sc, lb):
-    """The CPU oracle, single-threaded, on a bounded sample of the same workload: map + calibration + one realization
-    of 2 realizations x (3 equilibration sweeps + 1 sampling sweep)."""
+    """The CPU oracle, single-threaded, on a bounded sample of the same workload: map + calibration + 4 realizations
+    x (3 equilibration sweeps + 1 sampling sweep)."""
     import numpy as np
 
     import oracle
@@ -314,12 +397,12 @@ def cpu_baseline(sc, lb):
     t, rng = oracle.map_angles(sc.z_obs, sc.mask)
     T, _, _ = oracle.calibrate_temperature(t, sc.mask, lb[0], lb[1], Tg.astype(np.float64), e)
     res = oracle.simulate(t, sc.mask, T, lb[0], lb[1],
-                          oracle.SimConfig(n_real=2, init_mode=1, stop_mode=0, n_eq=3, n_samp=1, seed=1))
+                          oracle.SimConfig(n_real=4, init_mode=1, stop_mode=0, n_eq=3, n_samp=1, seed=1))
     el = time.perf_counter() - t0
-    upd = n_gap * 2 * 4
+    upd = n_gap * 4 * 4
     log(f"[bench] cpu oracle: {upd} updates in {el:.1f}s")
     return {"value": upd / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"same 4096^2 input; map + calibration + 2 realizations x 4 sweeps ({upd} updates), "
+            "sample": f"same 4096^2 input; map + calibration + 4 realizations x 4 sweeps ({upd} updates), "
                       f"{el:.1f} s single-threaded FP64"}
 
 

@@ -127,7 +127,7 @@ struct SimWs {
     double* Ts;
     int* No;
     float* gmean;
-    mpr::TPair* tp;
+    mpr::TBand* tp;
     long long* epart;   // [R][max(ntiles, nfull)]
     double* e_real;     // [R]
     double* series;     // [cap + 1]
@@ -141,7 +141,7 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     x.Ts = c.take<double>(g.B());
     x.No = c.take<int>(g.B());
     x.gmean = c.take<float>(1);
-    x.tp = c.take<mpr::TPair>(g.B());
+    x.tp = c.take<mpr::TBand>(g.B());
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     const int nt = fused_tiles(H, W, (int)R);
     const int nfull = mpr::energy_full_parts(H, W);
@@ -224,7 +224,7 @@ struct SweepRunner {
     double* e_real;    // [R]
     hipStream_t s;
 
-    SweepRunner(float* state, float* alt, const uint8_t* mask, int64_t H, int64_t W, const mpr::TPair* tp,
+    SweepRunner(float* state, float* alt, const uint8_t* mask, int64_t H, int64_t W, const mpr::TBand* tp,
                 int32_t lb_h, int32_t lb_w, const mpr_sim_config& c, long long* epart_, double* e_real_,
                 hipStream_t s_)
     {
@@ -294,14 +294,14 @@ int fused_tiles(int64_t H, int64_t W, int R)
 }
 
 struct SweepWs {
-    mpr::TPair* tp;
+    mpr::TBand* tp;
     long long* epart;
     double* e_real;
 };
 size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SweepWs* w)
 {
     SweepWs x;
-    x.tp = c.take<mpr::TPair>(nblocks_of(H, W, lb_h, lb_w));
+    x.tp = c.take<mpr::TBand>(nblocks_of(H, W, lb_h, lb_w));
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     x.epart = c.take<long long>((int64_t)fused_tiles(H, W, (int)R) * R);
     x.e_real = c.take<double>(R);
@@ -319,7 +319,7 @@ struct BatchWs {
     double* Ts;
     int* No;
     float* gmean;
-    std::vector<mpr::TPair*> tp;
+    std::vector<mpr::TBand*> tp;
     std::vector<float*> alt;
     std::vector<long long*> epart;
     std::vector<double*> e_real, series;
@@ -329,6 +329,22 @@ void batch_geom(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int
 {
     mpr::fused_geometry(H, W, R, tile_h, ntx, nty, rchunk, nchunks);
     *ntiles = (*ntx) * (*nty);
+}
+
+// Realization chunk of every work item in a batch: the scenes supply the parallelism, so an item covers as many
+// realizations as possible (its LDS set-up is then shared by all of them), down to what keeps at least 8 items per
+// workgroup slot of the persistent grid.
+int batch_rchunk(const mpr_scene* sc, int n, int R, int tile_h)
+{
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        int ntx, nty, nt, rc, nc;
+        batch_geom(sc[i].H, sc[i].W, R, tile_h, &ntx, &nty, &nt, &rc, &nc);
+        tiles += nt;
+    }
+    int rc = std::min(R, 64);
+    while (rc > 1 && tiles * ((R + rc - 1) / rc) < 8 * 1024) rc = (rc + 1) / 2;
+    return rc;
 }
 
 size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg, BatchWs* w)
@@ -356,7 +372,7 @@ size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg,
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     for (int i = 0; i < n; ++i) {
         const int64_t H = sc[i].H, W = sc[i].W;
-        x.tp.push_back(c.take<mpr::TPair>(nblocks_of(H, W, sc[i].lb_h, sc[i].lb_w)));
+        x.tp.push_back(c.take<mpr::TBand>(nblocks_of(H, W, sc[i].lb_h, sc[i].lb_w)));
         x.alt.push_back(c.take<float>(R * H * W));
         int ntx, nty, nt16, nt32, rc, nc;
         batch_geom(H, W, (int)R, 16, &ntx, &nty, &nt16, &rc, &nc);
@@ -656,7 +672,7 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     ia.key1 = key1;
     ia.mode = c.init_mode;
     MPR_HIP(mpr::launch_init(ia, s));
-    MPR_HIP(mpr::launch_tpairs(T_blocks, B, w.tp, s));
+    MPR_HIP(mpr::launch_tpairs(T_blocks, B, c.J, mpr::kDeltaE * c.J, w.tp, s));
 
     const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, lb_h, lb_w, c, w.epart, w.e_real, s);
@@ -734,7 +750,7 @@ mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_
     Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
     SweepWs w;
     sweep_ws(cv, H, W, lb_h, lb_w, cfg, &w);
-    MPR_HIP(mpr::launch_tpairs(T_blocks, nblocks_of(H, W, lb_h, lb_w), w.tp, s));
+    MPR_HIP(mpr::launch_tpairs(T_blocks, nblocks_of(H, W, lb_h, lb_w), cfg->J, mpr::kDeltaE * cfg->J, w.tp, s));
     SweepRunner runner(state, state_alt, mask, H, W, w.tp, lb_h, lb_w, *cfg, w.epart, w.e_real, s);
     for (int32_t i = 0; i < n_sweeps; ++i)
         MPR_HIP(runner.run((uint32_t)(k_first + i), energy_out ? energy_out + i : nullptr));
@@ -826,6 +842,7 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
     for (int i = 0; i < n_scenes; ++i) any_energy_out |= scenes[i].energy != nullptr;
 
     // ---- per-scene start, temperatures, e(0) ----
+    const int rchunk_v[2] = {batch_rchunk(scenes, n_scenes, R, 16), batch_rchunk(scenes, n_scenes, R, 32)};
     std::vector<mpr::BatchScene> hs(n_scenes);
     std::vector<int64_t> work16(n_scenes), work32(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
@@ -856,7 +873,7 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         ia.key1 = key1;
         ia.mode = c.init_mode;
         MPR_HIP(mpr::launch_init(ia, s));
-        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), w.tp[i], s));
+        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
         const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
         const double inv_norm = nbonds > 0 ? 1.0 / ((double)c.J * (double)nbonds) : 0.0;
         if (energy || sc.energy) {
@@ -884,6 +901,8 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         for (int v = 0; v < 2; ++v) {
             int ntx, nty, nt, rc, nc;
             batch_geom(sc.H, sc.W, R, v ? 32 : 16, &ntx, &nty, &nt, &rc, &nc);
+            rc = rchunk_v[v];
+            nc = (R + rc - 1) / rc;
             d.ntx = ntx;
             d.nty[v] = nty;
             d.ntiles[v] = nt;

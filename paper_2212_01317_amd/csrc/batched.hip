@@ -66,7 +66,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     for (;;) {
         if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ctl->queue, 1ull);
         __syncthreads();
-        const int64_t item = s_item;
+        // uniform: the scene descriptor is then read with scalar loads and kept in scalar registers
+        const uint64_t iu = (uint64_t)s_item;
+        const int64_t item = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(iu >> 32)) << 32) |
+                                       (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)iu));
         __syncthreads();
         if (item >= n_items) break;
         int lo = 0, hi = n_scenes;            // largest i with prefix[i] <= item

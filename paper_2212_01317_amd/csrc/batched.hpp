@@ -12,7 +12,7 @@ namespace mpr {
 struct BatchScene {
     const float* t;
     const uint8_t* mask;
-    const TPair* tp;
+    const TBand* tp;
     float* buf[2];        // state after an even / odd number of sweeps
     double* acc;
     long long* epart;     // [R][max tiles] energy partials (fixed point)

@@ -409,20 +409,16 @@ hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float*
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_tpairs(const float* T, int64_t B, TPair* tp)
+__global__ __launch_bounds__(256) void k_tpairs(const float* T, int64_t B, float J, float delta, TBand* tp)
 {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    const float Tv = T[b];
-    TPair p;
-    p.T = Tv;
-    p.nl2T = Tv > 0.0f ? (float)(-1.4426950408889634074 / (double)Tv) : 0.0f;
-    tp[b] = p;
+    tp[b] = make_tband(T[b], J, delta);
 }
 
-hipError_t launch_tpairs(const float* T, int64_t B, TPair* tp, hipStream_t s)
+hipError_t launch_tpairs(const float* T, int64_t B, float J, float delta, TBand* tp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tpairs, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, T, B, tp);
+    hipLaunchKernelGGL(k_tpairs, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, T, B, J, delta, tp);
     return hipGetLastError();
 }
 
@@ -665,10 +661,7 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
     if (xa >= L) return;
     float* st = a.state + (int64_t)chain * L * L;
     const float T = a.Tgrid[chain];
-    TPair tp;
-    tp.T = T;
-    tp.nl2T = T > 0.0f ? (float)(-1.4426950408889634074 / (double)T) : 0.0f;
-    const float band = band_of(tp.nl2T, a.delta_e);
+    const TBand tb = make_tband(T, 1.0f, a.delta_e);
     const U4 w = philox_x3((uint32_t)p, a.sweep, (uint32_t)chain, ctr_word3(0u, TAG_REFLAT, a.colour), a.key0,
                                a.key1);
     const int yu = (y + L - 1) % L, yd = (y + 1) % L;
@@ -692,10 +685,11 @@ __global__ __launch_bounds__(256) void k_ref_half(RefArgs a)
         const float to = st[y * L + x];
         const float co = cos_rev(a.q * to), so = sin_rev(a.q * to);
         const float tpv = u24(h ? w.z : w.x);
-        const float u2 = u24(h ? w.w : w.y);
+        const uint32_t wa = h ? w.w : w.y;
+        const float u2 = u24(wa);
         const float cp = cos_rev(a.q * tpv), sp = sin_rev(a.q * tpv);
-        const float dE = -fmaf(cp - co, Cx, (sp - so) * Sy);
-        int dec = filter32(dE, tp.T, tp.nl2T, band, u2, a.delta_e);
+        const float X = fmaf(cp - co, Cx, (sp - so) * Sy);
+        int dec = filter32(X, (float)(wa >> 8), tb, 1.0f, a.delta_e);
         if (dec < 0) dec = exact64(tpv, to, nb[0], nb[1], nb[2], nb[3], 15u, a.two_pi_q, 1.0, T, u2) ? 1 : 0;
         if (dec) st[y * L + x] = tpv;
     }

@@ -49,27 +49,45 @@ __device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, u
 }
 
 // FP32 Metropolis filter.  Returns 1 = accept, 0 = reject, -1 = inside the error band (the exact FP64 test decides).
-// dE is the FP32 energy change with |dE - dE_exact| <= delta.  The exact test is u2 < exp(-dE/T) (T > 0) or
-// dE <= 0 (T == 0).  With y = dE * nl2T = log2 of the acceptance ratio, |y - y_exact| <= delta |nl2T| + |y| 2^-22,
-// and the relative error of w = 2^y is ln 2 |y - y_exact| plus the v_exp_f32 error (below 2^-22).  The band is
-// that bound with a 25 % margin, rel = |y| kBandY + band with band = band_of(nl2T, delta) per temperature, plus an
-// absolute 2^-30 for results that flush to zero.
+//
+// Inputs in scaled form: X = (c' - c) Cx + (s' - s) Sy, so that the energy change is dE = -J X, with
+// |dE - dE_exact| <= delta; ui = (wa >> 8) as a float, so that u2 = ui 2^-24 exactly; tb = the block's
+// {T, kappa = J log2(e) / T, band, kb}.  The exact test is u2 < exp(-dE/T) (T > 0) or dE <= 0 (T == 0).
+//
+// For T > 0, y24 = fma(X, kappa, 24) is 24 plus y = log2 of the acceptance ratio, and w24 = 2^y24 = 2^24 w.  Its
+// error: |y24 - 24 - y_exact| <= delta log2(e) / T (from dE) + |y| 2^-22 (roundings of kappa and of the product)
+// + 2^-20 (rounding of the sum near 24), and v_exp_f32 adds a relative 2^-22.  The relative error of w24 is then at
+// most ln 2 times the first three terms plus 2^-22; the band is that bound with a 25 % margin,
+// rel = |X| kb + band with kb = 1.25 ln2 2^-22 kappa and band = band_of(T, delta), plus an absolute 2^-6 (2^-30 in u2
+// units) for results that flush to zero.  y24 is clamped at 25 (y >= 1 accepts: w > 1 > u2, and the clamped value
+// still lies more than the band above any ui).
 constexpr float kBandY = 1.25f * 0.6931472f * 2.3841858e-7f;
-__device__ __forceinline__ float band_of(float nl2T, float delta)
+
+__device__ __forceinline__ float band_of(float T, float delta)
 {
-    return fmaf(1.25f * 0.6931472f * delta, fabsf(nl2T), 1.25f * 2.3841858e-7f);
+    return T > 0.0f ? 1.25f * (0.6931472f * (delta * (1.4426950f / T) + 9.5367432e-7f) + 2.3841858e-7f) : 0.0f;
 }
 
-__device__ __forceinline__ int filter32(float dE, float T, float nl2T, float band, float u2, float delta)
+__device__ __forceinline__ TBand make_tband(float T, float J, float delta)
 {
-    if (T > 0.0f) {
-        const float y = dE * nl2T;
-        if (y >= 1.0f) return 1;
-        const float w = exp2_fast(y);
-        const float rel = fmaf(fabsf(y), kBandY, band);
-        if (fabsf(u2 - w) <= fmaf(w, rel, 9.3132257e-10f)) return -1;
-        return u2 < w ? 1 : 0;
+    TBand b;
+    b.T = T;
+    b.kappa = T > 0.0f ? (float)((double)J * 1.4426950408889634074 / (double)T) : 0.0f;
+    b.band = band_of(T, delta);
+    b.kb = kBandY * b.kappa;
+    return b;
+}
+
+__device__ __forceinline__ int filter32(float X, float ui, const TBand& tb, float J, float delta)
+{
+    if (tb.T > 0.0f) {
+        const float y24 = fminf(fmaf(X, tb.kappa, 24.0f), 25.0f);
+        const float w24 = exp2_fast(y24);
+        const float rel = fmaf(fabsf(X), tb.kb, tb.band);
+        if (fabsf(ui - w24) <= fmaf(w24, rel, 0.015625f)) return -1;
+        return ui < w24 ? 1 : 0;
     }
+    const float dE = -J * X;
     if (fabsf(dE) <= delta) return -1;
     return dE <= 0.0f ? 1 : 0;
 }

@@ -15,15 +15,10 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // 22.6 e + 3.7e-6 including every FP32 rounding; 1.25e-5 leaves margin.
 constexpr float kDeltaE = 1.25e-5f;
 
-// Per-block temperature as the sweep kernels read it.
-struct TPair {
-    float T;       // temperature (0 allowed)
-    float nl2T;    // -log2(e) / T, or 0 when T == 0
-};
-
-// Per-block temperature as the sweep keeps it in LDS: with the error band of its FP32 filter.
+// Per-block temperature as the sweep keeps it in LDS, with the constants of its FP32 filter: kappa = J log2(e) / T
+// (0 when T == 0), the band terms of the filter's error bound (band, and kb per unit |X|).
 struct alignas(16) TBand {
-    float T, nl2T, band, pad;
+    float T, kappa, band, kb;
 };
 
 // Bump allocator over the caller's workspace (256-byte aligned slices).
@@ -62,7 +57,7 @@ hipError_t launch_block_stats(const float* t, const uint8_t* mask, const StatsGe
 hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, const double* cT, const double* ce,
                             int nc, float* T_out, double* e_out, int* nb_out, unsigned* n_have, hipStream_t s);
 hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float* gmean, hipStream_t s);
-hipError_t launch_tpairs(const float* T, int64_t B, TPair* tp, hipStream_t s);
+hipError_t launch_tpairs(const float* T, int64_t B, float J, float delta, TBand* tp, hipStream_t s);
 
 struct InitArgs {
     float* state;
@@ -84,7 +79,7 @@ struct SweepFusedArgs {
     const float* src;    // [R][H][W] state after sweep k-1
     float* dst;          // [R][H][W] state after sweep k (sample cells must already hold their angles)
     const uint8_t* mask;
-    const TPair* Tb;
+    const TBand* Tb;
     int H, W, lb_h, lb_w, nbx, ntx, nty, ntiles, Mw, R, rchunk, nchunks;
     int tile_h;          // 16 or 32 (tile width is 64)
     int64_t HW;

@@ -147,16 +147,16 @@ __device__ __forceinline__ long long site_update(LdsT<FTH>& L, const SweepFusedA
     const float Cx = ((u.x + l.x) + rt.x) + d.x;
     const float Sy = ((u.y + l.y) + rt.y) + d.y;
     const float tp = u24(wp);
-    const float u2 = u24(wa);
+    const float ui = (float)(wa >> 8);                 // u2 = ui 2^-24
     const float ang = a.q * tp;
     const float cp = cos_rev(ang), sp = sin_rev(ang);
-    const float dE = -a.J * fmaf(cp - o.x, Cx, (sp - o.y) * Sy);
-    int dec = filter32(dE, tb.T, tb.nl2T, tb.band, u2, a.delta_e);
+    const float X = fmaf(cp - o.x, Cx, (sp - o.y) * Sy);    // dE = -J X
+    int dec = filter32(X, ui, tb, a.J, a.delta_e);
     if (dec < 0) {
         const unsigned pres = (present(u) ? 1u : 0u) | (present(l) ? 2u : 0u) | (present(rt) ? 4u : 0u) |
                               (present(d) ? 8u : 0u);
         dec = exact64(tp, t[i_own], fabsf(t[i_u]), fabsf(t[i_l]), fabsf(t[i_r]), fabsf(t[i_d]), pres, a.two_pi_q,
-                      a.Jd, tb.T, u2)
+                      a.Jd, tb.T, ui * 5.9604644775390625e-8f)
                   ? 1
                   : 0;
     }
@@ -263,8 +263,7 @@ __device__ __forceinline__ long long generic_colour(LdsT<FTH>& L, const SweepFus
             const float2* const cs = &L.cs[0][0][0];
             const int xl = 4 * (pl - 1) + delta + 2 * h + 2;     // region column
             const int bidx = row_b + L.bcol[xl];
-            const TPair g = a.Tb[bidx];
-            const TBand tb{g.T, g.nl2T, band_of(g.nl2T, a.delta_e), 0.0f};
+            const TBand tb = a.Tb[bidx];
             e_sum += site_update<FTH, ENERGY>(L, a, cs[i_own], cs[i_u], cs[i_l], cs[i_r], cs[i_d], h ? w.z : w.x,
                                               h ? w.w : w.y, tb, i_own, i_u, i_l, i_r, i_d);
         }
@@ -328,10 +327,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
         L.bcol[tid - 64] = v;
     } else if (fast && tid >= 192 && tid < 192 + C::TP_CAP) {
         const int i = tid - 192;
-        if (i < nby_l * nbx_l) {
-            const TPair g = a.Tb[(int64_t)(by0 + i / nbx_l) * a.nbx + bx0 + i % nbx_l];
-            L.tp[i] = TBand{g.T, g.nl2T, band_of(g.nl2T, a.delta_e), 0.0f};
-        }
+        if (i < nby_l * nbx_l) L.tp[i] = a.Tb[(int64_t)(by0 + i / nbx_l) * a.nbx + bx0 + i % nbx_l];
     }
     __syncthreads();
 
@@ -498,8 +494,9 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
         float* __restrict__ dst = a.dst + (int64_t)r * a.HW;
         // opaque per realization: the per-row offsets below are recomputed (one add each) instead of being kept as
         // 64-bit addresses across the loop; uniform base + unsigned 32-bit offset addressing
-        int om = off_m, os = off_s;
-        asm volatile("" : "+v"(om), "+v"(os));
+        int om = off_m, os = off_s, Wr = W;
+        asm volatile("" : "+v"(om), "+v"(os), "+s"(Wr));
+        const int W4r = 4 * Wr;
         // 1. gap cells from registers
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
@@ -521,7 +518,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
             const float* __restrict__ srcn = a.src + (int64_t)(r + 1) * a.HW;
 #pragma unroll
             for (int k = 0; k < MAIN_K; ++k)
-                if ((gapbits >> k) & 1u) pre[k] = srcn[(uint32_t)(om + k * W4)];
+                if ((gapbits >> k) & 1u) pre[k] = srcn[(uint32_t)(om + k * W4r)];
             if ((gapbits >> MAIN_K) & 1u) pre[MAIN_K] = srcn[(uint32_t)os];
         }
         const uint32_t rg = a.real_offset + (uint32_t)r;
@@ -563,7 +560,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
             const int yl = row0 + 2 + 4 * k;
             const float v = L.t[g_m][yl][J_m];
             if (is_fixed(v)) continue;                      // samples and cells outside the grid
-            dst[(uint32_t)(om + (2 + 4 * k) * W)] = v;
+            dst[(uint32_t)(om + (2 + 4 * k) * Wr)] = v;
         }
         __syncthreads();
         if (a.e_partial && tid == 0) {
