@@ -263,7 +263,7 @@ struct SweepRunner {
         buf[1] = alt;
         cur = 0;
         const int64_t nbonds = H * (W - 1) + W * (H - 1);
-        inv_norm = nbonds > 0 ? 1.0 / ((double)c.J * (double)nbonds) : 0.0;
+        inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         epart = epart_;
         e_real = e_real_;
         s = s_;
@@ -875,7 +875,7 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         MPR_HIP(mpr::launch_init(ia, s));
         MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
         const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
-        const double inv_norm = nbonds > 0 ? 1.0 / ((double)c.J * (double)nbonds) : 0.0;
+        const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy || sc.energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
             MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));

@@ -468,12 +468,13 @@ int energy_full_parts(int64_t H, int64_t W)
     return (int)(p < 1 ? 1 : (p > 4096 ? 4096 : p));
 }
 
-__device__ __forceinline__ long long fix32(float e) { return __float2ll_rn(e * 4294967296.0f); }
+__device__ __forceinline__ int fix24(float x) { return __float2int_rn(x * 16777216.0f); }
 
 __global__ __launch_bounds__(EN_NT) void k_energy_full(const float* __restrict__ state, int64_t H, int64_t W, float q,
                                                         float J, long long* partial)
 {
     __shared__ long long s_red[EN_NT / 64];
+    (void)J;
     const int r = blockIdx.y;
     const int64_t HW = H * W;
     const float* st = state + (int64_t)r * HW;
@@ -481,10 +482,10 @@ __global__ __launch_bounds__(EN_NT) void k_energy_full(const float* __restrict__
     for (int64_t n = (int64_t)blockIdx.x * EN_NT + threadIdx.x; n < HW; n += (int64_t)gridDim.x * EN_NT) {
         const int64_t y = n / W, x = n - y * W;
         const float tn = st[n];
-        float e = 0.0f;
-        if (x + 1 < W) e += -J * cos_rev(q * (tn - st[n + 1]));
-        if (y + 1 < H) e += -J * cos_rev(q * (tn - st[n + W]));
-        acc += fix32(e);
+        float e = 0.0f;                                   // energy of the site's right and lower bonds / J
+        if (x + 1 < W) e -= cos_rev(q * (tn - st[n + 1]));
+        if (y + 1 < H) e -= cos_rev(q * (tn - st[n + W]));
+        acc += fix24(e);
     }
     const long long tot = block_sum<EN_NT>(acc, s_red);
     if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = tot;

@@ -90,13 +90,15 @@ struct SweepFusedArgs {
 };
 void fused_geometry(int64_t H, int64_t W, int R, int tile_h, int* ntx, int* nty, int* rchunk, int* nchunks);
 hipError_t launch_sweep_fused(const SweepFusedArgs& a, hipStream_t s);
-// Energies per bond are accumulated in fixed point (2^-32 units, int64): exact, order-independent sums.
-constexpr double kFixUnit = 1.0 / 4294967296.0;
+// Energies are accumulated in fixed point: each site's bond energy divided by J (at most 4 in magnitude) is
+// rounded to a multiple of 2^-24 (an int32), and the integers are summed exactly (int64 beyond a thread), so the
+// sums do not depend on their order.  kFixUnit converts back.
+constexpr double kFixUnit = 1.0 / 16777216.0;
 hipError_t launch_energy_full(const float* state, int64_t H, int64_t W, int R, float q, float J, long long* partial,
                               int nparts, hipStream_t s);
 int energy_full_parts(int64_t H, int64_t W);
 // partial layout [R][nparts] (fixed point); e_real[R] scratch; e_out = mean over r of sum_p partial[r][p] * unit *
-// inv_norm
+// inv_norm, with inv_norm = 1 / (number of bonds): the energy per bond in units of J
 hipError_t launch_energy_reduce(const long long* partial, int nparts, int R, double inv_norm, double* e_real,
                                 double* e_out, hipStream_t s);
 hipError_t launch_accumulate(const float* state, const uint8_t* mask, int64_t HW, int R, int first, double* acc,

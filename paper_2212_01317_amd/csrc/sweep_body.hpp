@@ -79,9 +79,11 @@ struct alignas(16) LdsT {
 
 __device__ __forceinline__ int cell_J(int xl) { return (xl >> 1) + 3; }
 
-// Energies are summed as fixed-point integers (units of 2^-32): integer sums do not depend on their order, so the
-// energy series (and the stopping decision) does not depend on the tiling, the realization chunks or batching.
-__device__ __forceinline__ long long to_fix(float e) { return __float2ll_rn(e * 4294967296.0f); }
+// Energies are summed as fixed-point integers: a site's bond energy / J (at most 4 in magnitude) in units of 2^-24,
+// an int32, summed exactly (a thread's sites stay below 2^30; int64 across threads).  Integer sums do not depend on
+// their order, so the energy series (and the stopping decision) does not depend on the tiling, the realization
+// chunks or batching.
+__device__ __forceinline__ int to_fix(float x) { return __float2int_rn(x * 16777216.0f); }
 __device__ __forceinline__ bool is_fixed(float t) { return __float_as_uint(t) >> 31; }
 __device__ __forceinline__ bool present(float2 cs) { return cs.x != 0.0f || cs.y != 0.0f; }
 
@@ -135,10 +137,10 @@ __device__ __forceinline__ void compact2(int cat, uint16_t val, uint16_t* list, 
 
 // One Metropolis update from the LDS neighbourhood: own (cos, sin) o, neighbours up u, left l, right rt, down d,
 // proposal / acceptance words wp / wa, block temperature tb.  The index arguments are LDS cell indices (the t and
-// cs arrays share them) of the site and of its neighbours, read only on the exact path.  Returns the energy of the
-// site's bonds after the update (fixed point) when ENERGY.
+// cs arrays share them) of the site and of its neighbours, read only on the exact path.  Returns the energy / J of
+// the site's bonds after the update (fixed point) when ENERGY.
 template <int FTH, bool ENERGY>
-__device__ __forceinline__ long long site_update(LdsT<FTH>& L, const SweepFusedArgs& a, float2 o, float2 u, float2 l,
+__device__ __forceinline__ int site_update(LdsT<FTH>& L, const SweepFusedArgs& a, float2 o, float2 u, float2 l,
                                                  float2 rt, float2 d, uint32_t wp, uint32_t wa, const TBand& tb,
                                                  int i_own, int i_u, int i_l, int i_r, int i_d)
 {
@@ -167,7 +169,7 @@ __device__ __forceinline__ long long site_update(LdsT<FTH>& L, const SweepFusedA
         cf = cp;
         sf = sp;
     }
-    return ENERGY ? to_fix(-a.J * fmaf(cf, Cx, sf * Sy)) : 0;
+    return ENERGY ? to_fix(-fmaf(cf, Cx, sf * Sy)) : 0;
 }
 
 // Fast-path offsets, in LDS cells (float2 units) from the lowest cell a colour-COLOUR pair reads: the pair itself,
@@ -184,7 +186,7 @@ struct FastOff {
 // Fast-path update of one colour: full pairs list[0 .. nf), single sites list[cap - nh .. cap).  `ctr_base` is the
 // colour's random-stream counter offset (see the list builder).
 template <int FTH, int COLOUR, bool ENERGY>
-__device__ __forceinline__ long long fast_colour(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* list,
+__device__ __forceinline__ int fast_colour(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* list,
                                                  int cap, int nf, int nh, uint32_t ctr_base, uint32_t r_global,
                                                  int tid)
 {
@@ -192,7 +194,7 @@ __device__ __forceinline__ long long fast_colour(LdsT<FTH>& L, const SweepFusedA
     const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COLOUR);
     const int mw20 = a.Mw - 20;
     const float2* const cs = &L.cs[0][0][0];
-    long long e_sum = 0;
+    int e_sum = 0;
     int v = tid;
     for (; v < nf; v += Tile<FTH>::FS_NT) {
         const unsigned code = list[v];
@@ -236,14 +238,14 @@ __device__ __forceinline__ long long fast_colour(LdsT<FTH>& L, const SweepFusedA
 // Generic update of the listed pairs of one colour (codes row << 8 | pair << 2 | site mask), for the block shapes
 // the fast lists do not cover; block temperatures are read from global memory (brow / bcol hold global offsets).
 template <int FTH, int COLOUR, bool ENERGY>
-__device__ __forceinline__ long long generic_colour(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* items,
+__device__ __forceinline__ int generic_colour(LdsT<FTH>& L, const SweepFusedArgs& a, const uint16_t* items,
                                                     int n_items, int ty0, int tx0, uint32_t r_global, int tid)
 {
     constexpr int OC = COLOUR ^ 1;
     constexpr int CW = Tile<FTH>::CW;
     const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COLOUR);
     const uint32_t pm_base = (uint32_t)(tx0 / 4) - 1u;
-    long long e_sum = 0;
+    int e_sum = 0;
     for (int it = tid; it < n_items; it += Tile<FTH>::FS_NT) {
         const unsigned code = items[it];
         const int yl = (int)(code >> 8), pl = (int)((code >> 2) & 63u), sm = (int)(code & 3u);
@@ -271,16 +273,16 @@ __device__ __forceinline__ long long generic_colour(LdsT<FTH>& L, const SweepFus
     return e_sum;
 }
 
-// Energy of all bonds of a colour-1 site at (yl, J) from the LDS values.
+// Energy / J of all bonds of a colour-1 site at (yl, J) from the LDS values.
 template <int FTH>
-__device__ __forceinline__ float site_energy1(const LdsT<FTH>& L, int yl, int J, int delta, float Jc)
+__device__ __forceinline__ float site_energy1(const LdsT<FTH>& L, int yl, int J, int delta)
 {
     const float2 o = L.cs[1][yl][J];
     const float2 u = L.cs[0][yl - 1][J], d = L.cs[0][yl + 1][J];
     const float2 l = L.cs[0][yl][J - 1 + delta], rt = L.cs[0][yl][J + delta];
     const float Cx = ((u.x + l.x) + rt.x) + d.x;
     const float Sy = ((u.y + l.y) + rt.y) + d.y;
-    return -Jc * fmaf(o.x, Cx, o.y * Sy);
+    return -fmaf(o.x, Cx, o.y * Sy);
 }
 
 // One sweep of tile `tile` (row-major in a.ntx x a.nty tiles) for realizations
@@ -471,7 +473,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
                 f = true;
                 code = (uint16_t)((yl << 8) | J);
             } else {
-                e_const += to_fix(site_energy1<FTH>(L, yl, J, delta, a.J));
+                e_const += to_fix(site_energy1<FTH>(L, yl, J, delta));
             }
         }
         ne = compact(f, code, L.eobs, ne, L.wcnt[0]);
@@ -529,7 +531,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
             generic_colour<FTH, 0, false>(L, a, list0, nf0, ty0, tx0, rg, tid);
         __syncthreads();
         // 3. colour 1 on the tile
-        long long e = 0;
+        int e = 0;
         if (fast) {
             if (a.e_partial)
                 e = fast_colour<FTH, 1, true>(L, a, list1, MAX_BLK, nf1, nh1, ctr1, rg, tid);
@@ -547,7 +549,7 @@ __device__ __forceinline__ void sweep_tile(LdsT<FTH>& L, const SweepFusedArgs& a
             for (int i = tid; i < ne; i += FS_NT) {
                 const unsigned code = L.eobs[i];
                 const int yl = (int)(code >> 8), J = (int)(code & 255u);
-                e += to_fix(site_energy1<FTH>(L, yl, J, (ty0 - 2 + yl + 1) & 1, a.J));
+                e += to_fix(site_energy1<FTH>(L, yl, J, (ty0 - 2 + yl + 1) & 1));
             }
             long long v = e;
 #pragma unroll
