@@ -22,12 +22,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work, in lane-operations (one full-rate VALU lane-instruction = 1; quarter-rate = 4):
-# per gap-site update: half a Philox4x32-10 block (10 rounds x (2 mad_u64_u32 x 4 + 2 xor3)) / 2 = 50, two
-# uniforms 6, proposal angle and its sin/cos 9, local field from 4 neighbours 6, energy change 5, Boltzmann test
-# with exp 6, select/store 2  -> 84;  per site and sweep: sin/cos of its angle as a neighbour 9.
-A_UPD = 84.0
-A_SITE_SWEEP = 9.0
+# Algorithmic VALU work of one gap-site update, in lane-operations priced by the issue cost of each instruction
+# relative to a full-rate 32-bit add, as measured on the device (mpr_probe_instruction_rates):
+#   half a Philox4x32-10 block (the two sites of a pair share one): 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3) / 2
+#   two uniforms: shift + v_cvt_f32_u32 each, plus the scale of the proposal
+#   proposal angle, v_cos_f32, v_sin_f32
+#   local field from four neighbours' (cos, sin): 6 adds;  energy change: 2 sub, mul, fma
+#   Boltzmann test: fma (log2 of the ratio), v_exp_f32, compare;  select / store of t, cos, sin: 3
+# and per site and sweep (every site of a realization, as a neighbour): its angle, v_cos_f32, v_sin_f32.
+def algorithmic_costs(r):
+    parts = {
+        "philox_half_block": 10 * (2 * r["v_mad_u64_u32"] + 2 * r["v_bitop3_b32"]) / 2,
+        "uniforms": 2 * (1 + r["v_cvt_f32_u32"]) + 1,
+        "proposal_sincos": 1 + r["v_sin_f32"] + r["v_cos_f32"],
+        "local_field": 6.0,
+        "energy_change": 4.0,
+        "boltzmann_test": 2 + r["v_exp_f32"],
+        "select_store": 3.0,
+    }
+    return sum(parts.values()), 1 + r["v_sin_f32"] + r["v_cos_f32"], parts
+
+
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
@@ -188,7 +203,10 @@ def main():
     torch.cuda.synchronize()
     t_launch = ev0.elapsed_time(ev1) / 1e3 / ns
     upd_launch = float(R) * n_gap
-    ops_launch = upd_launch * A_UPD + float(R) * L * L * A_SITE_SWEEP
+    rates, add_ns = mpr.mpr_probe_instruction_rates(dev)
+    a_upd, a_site, a_parts = algorithmic_costs(rates)
+    log(f"[bench] instruction costs (v_add_u32 = 1): {rates}; A_update {a_upd:.2f}, A_site {a_site:.2f}")
+    ops_launch = upd_launch * a_upd + float(R) * L * L * a_site
     achieved = ops_launch / t_launch
     sweep_upd_rate = upd_launch / t_launch
     log(f"[bench] sweep launch {t_launch * 1e3:.3f} ms -> {sweep_upd_rate:.3e} upd/s in the sweep kernel")
@@ -219,6 +237,8 @@ def main():
                      "traffic_gbs": traffic / t_launch / 1e9 if traffic else None,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "launch_ms": t_launch * 1e3, "ops_per_launch": ops_launch,
+                     "a_update": a_upd, "a_site": a_site, "a_update_parts": a_parts,
+                     "instruction_cost_vs_add": rates, "add_ns_per_wave_instruction": add_ns,
                      "sweep_kernel_updates_per_s": sweep_upd_rate},
         "validation": {"aae": float(errs[0]), "rase": float(errs[1])},
     }

@@ -209,6 +209,17 @@ mpr_status mpr_temperature_grad(const float* state, const double* H_blocks, cons
                                 const double* range, const float* T_blocks, double* dT_out, void* workspace,
                                 size_t ws_bytes, void* stream);
 
+/* mpr_probe_instruction_rates: measurement support for the ALU roofline of the sweep (the per-update cost is priced
+ * from the device's own instruction rates, not from a data sheet).  Times nine probe kernels, each a fixed number of
+ * wave-instructions of one kind in independent dependency chains over the whole device, and writes to cost_out (host,
+ * n_out >= 9) the issue cost of each relative to v_add_u32 = 1: [0] v_add_u32, [1] v_mad_u64_u32, [2] v_mul_lo_u32,
+ * [3] v_mul_hi_u32, [4] v_bitop3_b32, [5] v_sin_f32, [6] v_cos_f32, [7] v_exp_f32, [8] v_cvt_f32_u32 (2 = half
+ * rate).  add_ns_out (host, nullable): device time per wave-instruction of v_add_u32, in ns.  workspace: device,
+ * mpr_probe_instruction_rates_workspace_bytes() bytes (probe outputs).  Synchronises the stream. */
+size_t mpr_probe_instruction_rates_workspace_bytes(void);
+mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* add_ns_out, void* workspace,
+                                       size_t ws_bytes, void* stream);
+
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* mpr_last_error(void);
 

@@ -104,6 +104,8 @@ _SIGS = {
                              ctypes.c_int),
     "mpr_validate_workspace_bytes": ([_i64], _sz),
     "mpr_validate": ([_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_probe_instruction_rates_workspace_bytes": ([], _sz),
+    "mpr_probe_instruction_rates": ([_vp, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
 }
 
 
@@ -306,6 +308,22 @@ def mpr_validate(zhat, truth, eval_mask):
     ws = _ws(lib().mpr_validate_workspace_bytes(n), zhat.device)
     _check(lib().mpr_validate(_p(zhat), _p(truth), _p(eval_mask), n, _p(out), _p(ws), ws.numel(), _stream()))
     return out
+
+
+PROBE_NAMES = ("v_add_u32", "v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_bitop3_b32", "v_sin_f32", "v_cos_f32",
+               "v_exp_f32", "v_cvt_f32_u32")
+
+
+def mpr_probe_instruction_rates(device=None):
+    """Issue cost of each probed instruction relative to v_add_u32 (dict name -> cost) and the device time per
+    wave-instruction of v_add_u32 in ns."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ws = _ws(lib().mpr_probe_instruction_rates_workspace_bytes(), dev)
+    cost = (ctypes.c_double * len(PROBE_NAMES))()
+    add_ns = ctypes.c_double(0.0)
+    _check(lib().mpr_probe_instruction_rates(cost, len(PROBE_NAMES), ctypes.byref(add_ns), _p(ws), ws.numel(),
+                                             _stream()))
+    return {n: float(c) for n, c in zip(PROBE_NAMES, cost)}, float(add_ns.value)
 
 
 def mpr_block_energy(state, mask, lb_h, lb_w, q=0.5, J=1.0):

@@ -1043,4 +1043,21 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
     return ok();
 }
 
+// ---- instruction-rate probe ----
+size_t mpr_probe_instruction_rates_workspace_bytes(void) { return mpr::probe_out_bytes(); }
+
+mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* add_ns_out, void* workspace,
+                                       size_t ws_bytes, void* stream)
+{
+    if (!cost_out || n_out < mpr::kProbeCount) return fail(MPR_ERR_INVALID_ARG, "cost_out needs %d entries", mpr::kProbeCount);
+    mpr_status st = check_ws(workspace, ws_bytes, mpr::probe_out_bytes());
+    if (st != MPR_OK) return st;
+    double ns[mpr::kProbeCount];
+    MPR_HIP(mpr::time_probes(static_cast<uint32_t*>(workspace), S(stream), ns));
+    for (int i = 0; i < mpr::kProbeCount; ++i) cost_out[i] = ns[i] / ns[0];
+    cost_out[1] -= 1.0;                 // the 64-bit product probe also executes one xor per step
+    if (add_ns_out) *add_ns_out = ns[0] / mpr::probe_wave_instructions();
+    return ok();
+}
+
 }  // extern "C"

@@ -25,17 +25,32 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
     return d;
 }
 
-// Philox4x32-10 written with the three-input xor (the same function as philox4x32_10).
+// Philox4x32-10 written with the three-input xor (the same function as philox4x32_10).  In the sweeps only c0
+// differs between lanes, so in the first two rounds one of the two products and half of the xors are wave-uniform:
+// those rounds are plain C and the compiler keeps the uniform parts on the scalar unit; the other eight use v_bitop3.
 __device__ __forceinline__ U4 philox_x3(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
     // keep the key schedule as per-call scalar adds instead of twenty loop-invariant registers
     asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
-    for (int round = 0; round < 10; ++round) {
+    for (int round = 0; round < 2; ++round) {
         if (round > 0) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+#pragma unroll
+    for (int round = 2; round < 10; ++round) {
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
         const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);

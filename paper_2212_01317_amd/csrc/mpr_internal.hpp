@@ -109,6 +109,15 @@ hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t*
                            int nblocks, double* out, hipStream_t s);
 int validate_blocks(int64_t n);
 
+// ---- instruction-rate probe (rates.hip) ----
+// Probes, in order: v_add_u32, v_mad_u64_u32 (+ one v_xor_b32 per step), v_mul_lo_u32, v_mul_hi_u32, v_bitop3_b32,
+// v_sin_f32, v_cos_f32, v_exp_f32, v_cvt_f32_u32.  ns[i] = kernel time of probe i (same instruction count each).
+constexpr int kProbeCount = 9;
+int probe_grid();
+size_t probe_out_bytes();
+double probe_wave_instructions();
+hipError_t time_probes(uint32_t* out, hipStream_t s, double* ns);
+
 // ---- temperature gradient (grad.hip) ----
 hipError_t launch_block_energy(const float* state, const uint8_t* mask, const StatsGeom& g, double two_pi_q,
                                double J, int R, double* part, double* Hrb, hipStream_t s);

@@ -195,21 +195,27 @@ __device__ __forceinline__ int fast_colour(LdsT<FTH>& L, const SweepFusedArgs& a
     const int mw20 = a.Mw - 20;
     const float2* const cs = &L.cs[0][0][0];
     int e_sum = 0;
+    // Software-pipelined: the next item's code is read one iteration ahead, and the neighbourhood reads are issued
+    // before the Philox rounds (the empty asm keeps them there), so their LDS latency is covered by the rounds.
+    constexpr int NT = Tile<FTH>::FS_NT;
     int v = tid;
-    for (; v < nf; v += Tile<FTH>::FS_NT) {
-        const unsigned code = list[v];
+    unsigned code_next = list[v < nf ? v : 0];
+    for (; v < nf; v += NT) {
+        const unsigned code = code_next;
+        code_next = list[v + NT < nf ? v + NT : 0];         // (a valid index either way: no branch)
         const int a4 = (int)(code & 2047u);
-        const TBand tb = L.tp[code >> 11];
         const int q = (int)(__umul24((unsigned)a4, 3277u) >> 16);     // a4 / 20: the LDS row (minus one for colour 1)
         const int delta = q & 1;
-        const uint32_t c0 = (uint32_t)__mul24(q, mw20) + (uint32_t)a4 + ctr_base;
-        const U4 w = philox_x3(c0, a.sweep, r_global, w3, a.key0, a.key1);
         const int b = 2 * a4;
+        const int hb = b + O::MID + delta;
+        const TBand tb = L.tp[code >> 11];
         const float4 own = *reinterpret_cast<const float4*>(&cs[b + O::OWN]);
         const float4 up = *reinterpret_cast<const float4*>(&cs[b + O::UP]);
         const float4 dn = *reinterpret_cast<const float4*>(&cs[b + O::DN]);
-        const int hb = b + O::MID + delta;
         const float2 x0 = cs[hb - 1], x1 = cs[hb], x2 = cs[hb + 1];
+        asm volatile("" ::: "memory");
+        const uint32_t c0 = (uint32_t)__mul24(q, mw20) + (uint32_t)a4 + ctr_base;
+        const U4 w = philox_x3(c0, a.sweep, r_global, w3, a.key0, a.key1);
         e_sum += site_update<FTH, ENERGY>(L, a, make_float2(own.x, own.y), make_float2(up.x, up.y), x0, x1,
                                           make_float2(dn.x, dn.y), w.x, w.y, tb, b + O::OWN, b + O::UP, hb - 1, hb,
                                           b + O::DN);
@@ -218,19 +224,22 @@ __device__ __forceinline__ int fast_colour(LdsT<FTH>& L, const SweepFusedArgs& a
                                           hb + 1, b + 1 + O::DN);
     }
     const uint16_t* const half = list + (cap - nh);
-    for (; v < nf + nh; v += Tile<FTH>::FS_NT) {
-        const unsigned code = half[v - nf];
+    code_next = half[v < nf + nh ? v - nf : 0];
+    for (; v < nf + nh; v += NT) {
+        const unsigned code = code_next;
+        code_next = half[v + NT < nf + nh ? v + NT - nf : 0];
         const int s2 = (int)(code & 2047u);
-        const TBand tb = L.tp[code >> 11];
         const int a4 = s2 >> 1, h = s2 & 1;
         const int q = (int)(__umul24((unsigned)s2, 3277u) >> 17);     // s2 / 40
         const int delta = q & 1;
+        const int hb = s2 + O::MID + delta;
+        const TBand tb = L.tp[code >> 11];
+        const float2 o = cs[s2 + O::OWN], u = cs[s2 + O::UP], d = cs[s2 + O::DN], l = cs[hb - 1], rt = cs[hb];
+        asm volatile("" ::: "memory");
         const uint32_t c0 = (uint32_t)__mul24(q, mw20) + (uint32_t)a4 + ctr_base;
         const U4 w = philox_x3(c0, a.sweep, r_global, w3, a.key0, a.key1);
-        const int hb = s2 + O::MID + delta;
-        e_sum += site_update<FTH, ENERGY>(L, a, cs[s2 + O::OWN], cs[s2 + O::UP], cs[hb - 1], cs[hb], cs[s2 + O::DN],
-                                          h ? w.z : w.x, h ? w.w : w.y, tb, s2 + O::OWN, s2 + O::UP, hb - 1, hb,
-                                          s2 + O::DN);
+        e_sum += site_update<FTH, ENERGY>(L, a, o, u, l, rt, d, h ? w.z : w.x, h ? w.w : w.y, tb, s2 + O::OWN,
+                                          s2 + O::UP, hb - 1, hb, s2 + O::DN);
     }
     return e_sum;
 }
