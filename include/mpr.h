@@ -51,6 +51,7 @@ typedef enum {
 
 enum { MPR_INIT_RANDOM = 0, MPR_INIT_BLOCK_MEAN = 1 };
 enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
+enum { MPR_T_BLOCK = 0, MPR_T_SITE = 1 };
 
 /* Parameters of one conditional simulation (host struct). */
 typedef struct {
@@ -67,6 +68,10 @@ typedef struct {
     int32_t n_max;        /* AUTO: cap on the equilibration sweeps */
     uint64_t seed;
     uint32_t scene_id;    /* 0 .. 2^28 - 1, separates the random streams of different scenes */
+    int32_t t_mode;       /* MPR_T_BLOCK (0): T_blocks has one temperature per lb_h x lb_w block (BST);
+                             MPR_T_SITE (1): T_blocks has one temperature per site, [H*W] (SST, Sec. 2.2.3), while
+                             lb_h x lb_w still give the blocks of the block-mean start.  Zero-initialised configs are
+                             MPR_T_BLOCK. */
 } mpr_sim_config;
 
 /* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;
@@ -114,7 +119,8 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
                                      void* workspace, size_t ws_bytes, void* stream);
 
 /* Conditional simulation (Sec. 2.1, Sec. 2.2.2, Sec. 3.3, Sec. 3.4).
- *   t[H*W]: mapped angles (samples used); T_blocks[B]: block temperatures (float) with the same lb_h x lb_w layout.
+ *   t[H*W]: mapped angles (samples used); T_blocks[B]: block temperatures (float) with the same lb_h x lb_w layout,
+ *   or, with cfg->t_mode == MPR_T_SITE, T_blocks[H*W]: one temperature per site (the sweeps use T of the site).
  *   Start: gaps take the block mean of the sample angles (a block without samples: the global sample mean), or a
  *   uniform draw (tag 1).  Then sweeps k = 1, 2, ...: all gap sites of colour (x + y) % 2 == 0, then of colour 1,
  *   each an independent-uniform Metropolis proposal t' = u1 accepted iff u2 < exp(-dE / T_b) (T_b = 0: iff
@@ -135,12 +141,22 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
                         double* energy_out, int32_t* sweeps_done_out, void* workspace, size_t ws_bytes,
                         void* stream);
 
+/* Sec. 2.2.3 (SST, site-specific temperatures): from the block temperatures T_blocks[ceil(H/lb_h)*ceil(W/lb_w)]
+ * (every site starts with its block's value), n_s successive passes replace the temperature of every site by the
+ * mean over the (2 r_s + 1) x (2 r_s + 1) square of sites around it, cut at the grid edges (mean over the in-grid
+ * sites; the paper leaves the shape of the area and r_s open).  FP64, each window summed row by row from the top
+ * left, one rounding to FP32: T_site_out[H*W] (float).  0 <= r_s <= 64, 0 <= n_s <= 1000.  Asynchronous.
+ * Workspace: mpr_sst_temperatures_workspace_bytes (two FP64 planes). */
+size_t mpr_sst_temperatures_workspace_bytes(int64_t H, int64_t W);
+mpr_status mpr_sst_temperatures(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
+                                int32_t n_s, float* T_site_out, void* workspace, size_t ws_bytes, void* stream);
+
 /* Continuation of chains: sweeps k_first .. k_first + n_sweeps - 1 (the sweep counter keys the random stream) with
  * exactly the per-sweep arithmetic of mpr_simulate (no start, no stopping rule, no accumulation).  The sweeps
  * alternate between two buffers [n_real*H*W]: sweep k_first reads `state` and writes `state_alt`, the next one reads
  * `state_alt` and writes `state`, and so on, so the result is in `state` when n_sweeps is even and in `state_alt`
  * when it is odd.  Both buffers must hold the same sample angles (e.g. state_alt a copy of state); only gap cells
- * are written.  Uses cfg->q, J, n_real, real_offset, seed, scene_id.  Resuming a saved state with the next sweep
+ * are written.  Uses cfg->q, J, n_real, real_offset, seed, scene_id, t_mode.  Resuming a saved state with the next sweep
  * counter reproduces an uninterrupted run bit for bit.  energy_out[n_sweeps] (optional): the realization-averaged
  * energy per bond after each sweep.  Asynchronous.  Workspace: mpr_sweep_workspace_bytes. */
 size_t mpr_sweep_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg);

@@ -83,9 +83,11 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_stop_check.argtypes = [_f64p, _i32, _i32, _i32]
     L.orc_stop_check.restype = ctypes.c_int
     L.orc_simulate.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _i32, _i32, _i32, _i32,
-                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _f32p, _f64p, _f64p,
+                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _f32p, _f64p, _f64p,
                                ctypes.POINTER(_i32)]
     L.orc_simulate.restype = _i32
+    L.orc_sst_temperatures.argtypes = [_f32p, _i64, _i64, _i32, _i32, _i32, _i32, _f32p]
+    L.orc_sst_temperatures.restype = None
     L.orc_predict.argtypes = [_f64p, _f32p, _u8p, _i64, _i64, _i64, _f64p, _f32p]
     L.orc_predict.restype = None
     L.orc_validate.argtypes = [_f32p, _f32p, _u8p, _i64, _f64p]
@@ -230,6 +232,7 @@ class SimConfig:
     n_max: int = 1000
     seed: int = 0
     scene: int = 0
+    t_mode: int = 0             # 0 block temperatures (BST), 1 one temperature per site (SST)
 
 
 @dataclass
@@ -253,8 +256,16 @@ def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
     conv = _i32(0)
     k = lib().orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
                            cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp, cfg.n_fit, cfg.n_f,
-                           cfg.n_max, cfg.seed, cfg.scene, state, acc, en, ctypes.byref(conv))
+                           cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, state, acc, en, ctypes.byref(conv))
     return SimResult(state=state, acc=acc, energy=en[: k + 1].copy(), k_star=int(k), converged=bool(conv.value))
+
+
+def sst_temperatures(T_blocks, H, W, lb_h, lb_w, r_s=1, n_s=5):
+    """Sec. 2.2.3: site-specific temperatures [H, W] float32 from the block map by n_s passes of the radius-r_s
+    window mean (orc_sst_temperatures)."""
+    out = np.zeros((H, W), np.float32)
+    lib().orc_sst_temperatures(_c(T_blocks, np.float32).ravel(), H, W, lb_h, lb_w, r_s, n_s, out)
+    return out
 
 
 def predict(acc, z, mask, n_samples, rng):

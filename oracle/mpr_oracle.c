@@ -433,8 +433,11 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
                      int32_t lb_h, int32_t lb_w, float q, float J, int32_t R, int32_t real_offset,
                      int32_t init_mode /* 0 random, 1 block mean */, int32_t stop_mode /* 0 fixed, 1 auto */,
                      int32_t n_eq, int32_t n_samp, int32_t n_fit, int32_t n_f, int32_t n_max, uint64_t seed,
-                     uint32_t scene, float* state, double* acc, double* energy, int32_t* converged)
+                     uint32_t scene, int32_t t_per_site /* 0: T_blocks per block, 1: T_blocks[H*W] per site */,
+                     float* state, double* acc, double* energy, int32_t* converged)
 {
+    /* the temperature layout the sweeps read: blocks of lb_h x lb_w, or one temperature per site (SST) */
+    const int32_t tb_h = t_per_site ? 1 : lb_h, tb_w = t_per_site ? 1 : lb_w;
     int64_t HW = H * W;
     int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
     int64_t B = nbx * nby;
@@ -483,7 +486,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
         double ek = 0.0;
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            orc_sweep(s, mask, H, W, T_blocks, lb_h, lb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
+            orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
                       (uint32_t)k);
             ek += orc_energy(s, H, W, q, J);
         }
@@ -495,7 +498,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            orc_sweep(s, mask, H, W, T_blocks, lb_h, lb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
+            orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
                       (uint32_t)(k_star + s_i));
         }
         for (int32_t r = 0; r < R; ++r) {
@@ -509,6 +512,46 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     free(Tsum);
     free(Nobs);
     return k_star;
+}
+
+/* ------------------------------------------------------------------------------------------------------------
+ * Sec. 2.2.3 (SST, site-specific temperatures): starting from the block temperatures (every site takes the value of
+ * its block), the temperature of every site is replaced n_s times in succession by the mean over the surrounding
+ * area of radius r_s.  Readings: the area is the (2 r_s + 1) x (2 r_s + 1) square of sites around the site, cut at
+ * the grid edges (the mean is over the sites inside the grid); each pass reads the previous pass only; FP64, the
+ * window summed row by row from the top left; one rounding to FP32 at the end.
+ * ---------------------------------------------------------------------------------------------------------- */
+void orc_sst_temperatures(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
+                          int32_t n_s, float* T_site)
+{
+    int64_t HW = H * W, nbx = (W + lb_w - 1) / lb_w;
+    double* a = (double*)malloc(sizeof(double) * (size_t)HW);
+    double* b = (double*)malloc(sizeof(double) * (size_t)HW);
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) a[y * W + x] = (double)T_blocks[(y / lb_h) * nbx + (x / lb_w)];
+    for (int32_t pass = 0; pass < n_s; ++pass) {
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = 0; x < W; ++x) {
+                double sum = 0.0;
+                int64_t cnt = 0;
+                for (int64_t yy = y - r_s; yy <= y + r_s; ++yy) {
+                    if (yy < 0 || yy >= H) continue;
+                    for (int64_t xx = x - r_s; xx <= x + r_s; ++xx) {
+                        if (xx < 0 || xx >= W) continue;
+                        sum += a[yy * W + xx];
+                        ++cnt;
+                    }
+                }
+                b[y * W + x] = sum / (double)cnt;
+            }
+        }
+        double* tmp = a;
+        a = b;
+        b = tmp;
+    }
+    for (int64_t n = 0; n < HW; ++n) T_site[n] = (float)a[n];
+    free(a);
+    free(b);
 }
 
 /* ------------------------------------------------------------------------------------------------------------

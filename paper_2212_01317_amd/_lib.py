@@ -21,6 +21,7 @@ _STATUS = {0: "MPR_OK", 1: "MPR_ERR_INVALID_ARG", 2: "MPR_ERR_SHAPE", 3: "MPR_ER
            7: "MPR_ERR_HIP", 8: "MPR_WARN_NOT_CONVERGED"}
 INIT_RANDOM, INIT_BLOCK_MEAN = 0, 1
 STOP_FIXED, STOP_AUTO = 0, 1
+T_BLOCK, T_SITE = 0, 1
 
 
 class MprError(RuntimeError):
@@ -34,7 +35,7 @@ class mpr_sim_config(ctypes.Structure):
                 ("real_offset", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("n_eq", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_fit", ctypes.c_int32),
                 ("n_f", ctypes.c_int32), ("n_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("scene_id", ctypes.c_uint32)]
+                ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32)]
 
 
 @dataclass
@@ -53,10 +54,18 @@ class SimConfig:
     n_max: int = 1000
     seed: int = 0
     scene_id: int = 0
+    t_mode: int = T_BLOCK       # T_BLOCK: one temperature per block; T_SITE: one per site (SST)
 
     def to_c(self) -> mpr_sim_config:
         return mpr_sim_config(self.q, self.J, self.n_real, self.real_offset, self.init_mode, self.stop_mode,
-                              self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id)
+                              self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id,
+                              self.t_mode)
+
+
+def _check_T(T_blocks, H, W, lb_h, lb_w, cfg: "SimConfig"):
+    need = H * W if cfg.t_mode == T_SITE else ((H + lb_h - 1) // lb_h) * ((W + lb_w - 1) // lb_w)
+    if T_blocks.numel() != need:
+        raise ValueError(f"T_blocks has {T_blocks.numel()} entries, the grid and t_mode need {need}")
 
 
 class mpr_scene(ctypes.Structure):
@@ -105,6 +114,8 @@ _SIGS = {
     "mpr_validate_workspace_bytes": ([_i64], _sz),
     "mpr_validate": ([_vp, _vp, _vp, _i64, _vp, _vp, _sz, _vp], ctypes.c_int),
     "mpr_probe_instruction_rates_workspace_bytes": ([], _sz),
+    "mpr_sst_temperatures_workspace_bytes": ([_i64, _i64], _sz),
+    "mpr_sst_temperatures": ([_vp, _i64, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "mpr_probe_instruction_rates": ([_vp, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
 }
 
@@ -238,6 +249,7 @@ def mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, state=None, want
     _dev(mask, torch.uint8, "mask")
     _dev(T_blocks, torch.float32, "T_blocks")
     H, W = _hw(t)
+    _check_T(T_blocks, H, W, lb_h, lb_w, cfg)
     dev = t.device
     c = cfg.to_c()
     if state is None:
@@ -269,6 +281,7 @@ def mpr_sweep(state, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, k_first: int, n
     _dev(mask, torch.uint8, "mask")
     _dev(T_blocks, torch.float32, "T_blocks")
     H, W = _hw(mask)
+    _check_T(T_blocks, H, W, lb_h, lb_w, cfg)
     if tuple(state.shape) != (cfg.n_real, H, W):
         raise ValueError("state must be [n_real, H, W]")
     if state_alt is None:
@@ -307,6 +320,19 @@ def mpr_validate(zhat, truth, eval_mask):
     out = torch.empty(2, dtype=torch.float64, device=zhat.device)
     ws = _ws(lib().mpr_validate_workspace_bytes(n), zhat.device)
     _check(lib().mpr_validate(_p(zhat), _p(truth), _p(eval_mask), n, _p(out), _p(ws), ws.numel(), _stream()))
+    return out
+
+
+def mpr_sst_temperatures(T_blocks, H: int, W: int, lb_h: int, lb_w: int, r_s: int = 1, n_s: int = 5):
+    """Sec. 2.2.3: site temperatures [H, W] float32 from the block map (n_s passes of the radius-r_s window mean)."""
+    _dev(T_blocks, torch.float32, "T_blocks")
+    if T_blocks.numel() != ((H + lb_h - 1) // lb_h) * ((W + lb_w - 1) // lb_w):
+        raise ValueError("T_blocks must hold one temperature per lb_h x lb_w block")
+    dev = T_blocks.device
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = _ws(lib().mpr_sst_temperatures_workspace_bytes(H, W), dev)
+    _check(lib().mpr_sst_temperatures(_p(T_blocks), H, W, lb_h, lb_w, r_s, n_s, _p(out), _p(ws), ws.numel(),
+                                      _stream()))
     return out
 
 
@@ -384,6 +410,7 @@ def mpr_simulate_batched(scenes, cfg: SimConfig, tile_h: int = 0, want_energy: b
         _dev(T, torch.float32, "T_blocks")
         H, W = _hw(t)
         lb_h, lb_w = sc["block"]
+        _check_T(T, int(t.shape[-2]), int(t.shape[-1]), int(lb_h), int(lb_w), cfg)
         state = torch.empty((cfg.n_real, H, W), dtype=torch.float32, device=t.device)
         acc = torch.empty((H, W), dtype=torch.float64, device=t.device)
         en = torch.empty(cap, dtype=torch.float64, device=t.device) if want_energy else None

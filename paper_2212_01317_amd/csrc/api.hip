@@ -68,6 +68,13 @@ int64_t nblocks_of(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w)
     return ((H + lb_h - 1) / lb_h) * ((W + lb_w - 1) / lb_w);
 }
 
+// Temperatures the sweeps read: one per lb_h x lb_w block, or one per site (the 1 x 1 block layout).
+int64_t t_count(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg)
+{
+    return cfg && cfg->t_mode == MPR_T_SITE ? H * W : ((H + lb_h - 1) / lb_h) * ((W + lb_w - 1) / lb_w);
+}
+int32_t t_lb(int32_t lb, const mpr_sim_config& c) { return c.t_mode == MPR_T_SITE ? 1 : lb; }
+
 // ---- workspace layouts (the same code computes the size and carves the pointers) ----
 struct MapWs {
     float *pmin, *pmax;
@@ -141,7 +148,7 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     x.Ts = c.take<double>(g.B());
     x.No = c.take<int>(g.B());
     x.gmean = c.take<float>(1);
-    x.tp = c.take<mpr::TBand>(g.B());
+    x.tp = c.take<mpr::TBand>(t_count(H, W, lb_h, lb_w, cfg));
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     const int nt = fused_tiles(H, W, (int)R);
     const int nfull = mpr::energy_full_parts(H, W);
@@ -211,8 +218,10 @@ mpr_status check_sim_config(const mpr_sim_config& c)
     if (c.n_real < 1 || c.n_real > 65535) return fail(MPR_ERR_INVALID_ARG, "n_real must be in 1 .. 65535");
     if (c.real_offset < 0) return fail(MPR_ERR_INVALID_ARG, "real_offset must be >= 0");
     if (c.scene_id >= (1u << 28)) return fail(MPR_ERR_INVALID_ARG, "scene_id must be < 2^28");
+    if (c.t_mode != MPR_T_BLOCK && c.t_mode != MPR_T_SITE) return fail(MPR_ERR_INVALID_ARG, "unknown t_mode %d", c.t_mode);
     return MPR_OK;
 }
+
 
 // Runs fused sweeps (one launch per sweep) alternating between two state buffers.
 struct SweepRunner {
@@ -301,7 +310,7 @@ struct SweepWs {
 size_t sweep_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SweepWs* w)
 {
     SweepWs x;
-    x.tp = c.take<mpr::TBand>(nblocks_of(H, W, lb_h, lb_w));
+    x.tp = c.take<mpr::TBand>(t_count(H, W, lb_h, lb_w, cfg));
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     x.epart = c.take<long long>((int64_t)fused_tiles(H, W, (int)R) * R);
     x.e_real = c.take<double>(R);
@@ -672,10 +681,10 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     ia.key1 = key1;
     ia.mode = c.init_mode;
     MPR_HIP(mpr::launch_init(ia, s));
-    MPR_HIP(mpr::launch_tpairs(T_blocks, B, c.J, mpr::kDeltaE * c.J, w.tp, s));
+    MPR_HIP(mpr::launch_tpairs(T_blocks, t_count(H, W, lb_h, lb_w, cfg), c.J, mpr::kDeltaE * c.J, w.tp, s));
 
     const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
-    SweepRunner runner(state, w.alt, mask, H, W, w.tp, lb_h, lb_w, c, w.epart, w.e_real, s);
+    SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
     if (need_energy) {
         const int nfull = mpr::energy_full_parts(H, W);
         MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
@@ -750,8 +759,9 @@ mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_
     Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
     SweepWs w;
     sweep_ws(cv, H, W, lb_h, lb_w, cfg, &w);
-    MPR_HIP(mpr::launch_tpairs(T_blocks, nblocks_of(H, W, lb_h, lb_w), cfg->J, mpr::kDeltaE * cfg->J, w.tp, s));
-    SweepRunner runner(state, state_alt, mask, H, W, w.tp, lb_h, lb_w, *cfg, w.epart, w.e_real, s);
+    MPR_HIP(mpr::launch_tpairs(T_blocks, t_count(H, W, lb_h, lb_w, cfg), cfg->J, mpr::kDeltaE * cfg->J, w.tp, s));
+    SweepRunner runner(state, state_alt, mask, H, W, w.tp, t_lb(lb_h, *cfg), t_lb(lb_w, *cfg), *cfg, w.epart,
+                       w.e_real, s);
     for (int32_t i = 0; i < n_sweeps; ++i)
         MPR_HIP(runner.run((uint32_t)(k_first + i), energy_out ? energy_out + i : nullptr));
     return ok();
@@ -821,6 +831,7 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
     if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
     if (tile_h != 0 && tile_h != 16 && tile_h != 32) return fail(MPR_ERR_INVALID_ARG, "tile_h must be 0, 16 or 32");
+    if (c.t_mode != MPR_T_BLOCK) return fail(MPR_ERR_INVALID_ARG, "the batched form takes block temperatures only");
     for (int i = 0; i < n_scenes; ++i) {
         const mpr_scene& sc = scenes[i];
         if ((st = check_grid(sc.H, sc.W)) != MPR_OK) return st;
@@ -1057,6 +1068,33 @@ mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* 
     for (int i = 0; i < mpr::kProbeCount; ++i) cost_out[i] = ns[i] / ns[0];
     cost_out[1] -= 1.0;                 // the 64-bit product probe also executes one xor per step
     if (add_ns_out) *add_ns_out = ns[0] / mpr::probe_wave_instructions();
+    return ok();
+}
+
+// ---- Sec. 2.2.3: site-specific temperatures ----
+size_t mpr_sst_temperatures_workspace_bytes(int64_t H, int64_t W)
+{
+    if (H < 1 || W < 1) return 0;
+    Carve c{nullptr, 0, 0};
+    (void)c.take<double>(H * W);
+    (void)c.take<double>(H * W);
+    return c.used;
+}
+
+mpr_status mpr_sst_temperatures(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
+                                int32_t n_s, float* T_site_out, void* workspace, size_t ws_bytes, void* stream)
+{
+    mpr_status st = check_grid(H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks(H, W, lb_h, lb_w)) != MPR_OK) return st;
+    if (!T_blocks || !T_site_out) return fail(MPR_ERR_INVALID_ARG, "mpr_sst_temperatures: NULL pointer");
+    if (r_s < 0 || r_s > 64 || n_s < 0 || n_s > 1000) return fail(MPR_ERR_INVALID_ARG, "need 0 <= r_s <= 64, 0 <= n_s <= 1000");
+    st = check_ws(workspace, ws_bytes, mpr_sst_temperatures_workspace_bytes(H, W));
+    if (st != MPR_OK) return st;
+    Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
+    double* a = cv.take<double>(H * W);
+    double* b = cv.take<double>(H * W);
+    MPR_HIP(mpr::launch_sst(T_blocks, H, W, lb_h, lb_w, r_s, n_s, a, b, T_site_out, S(stream)));
     return ok();
 }
 

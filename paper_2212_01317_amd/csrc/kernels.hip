@@ -764,4 +764,61 @@ hipError_t launch_ref_finish(const double* e_sum, int nT, double n_meas, double*
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------------------------
+// Sec. 2.2.3 (SST): the block map spread to the sites, then n_s passes of the mean over the (2 r_s + 1)^2 square
+// around each site cut at the grid edges, in FP64 with the window summed row by row from the top left (the oracle's
+// order), one rounding to FP32 at the end.
+__global__ __launch_bounds__(256) void k_sst_spread(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h,
+                                                    int32_t lb_w, double* a)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= H * W) return;
+    const int64_t y = n / W, x = n - y * W, nbx = (W + lb_w - 1) / lb_w;
+    a[n] = (double)T_blocks[(y / lb_h) * nbx + (x / lb_w)];
+}
+
+__global__ __launch_bounds__(256) void k_sst_pass(const double* __restrict__ a, double* __restrict__ b, int64_t H,
+                                                  int64_t W, int32_t r)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= H * W) return;
+    const int64_t y = n / W, x = n - y * W;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int64_t yy = y - r; yy <= y + r; ++yy) {
+        if (yy < 0 || yy >= H) continue;
+        for (int64_t xx = x - r; xx <= x + r; ++xx) {
+            if (xx < 0 || xx >= W) continue;
+            sum += a[yy * W + xx];
+            ++cnt;
+        }
+    }
+    b[n] = sum / (double)cnt;
+}
+
+__global__ __launch_bounds__(256) void k_sst_round(const double* a, int64_t n, float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (float)a[i];
+}
+
+hipError_t launch_sst(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
+                      int32_t n_s, double* a, double* b, float* out, hipStream_t s)
+{
+    const int64_t n = H * W;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_sst_spread, grid, dim3(256), 0, s, T_blocks, H, W, lb_h, lb_w, a);
+    hipError_t e = hipGetLastError();
+    for (int32_t p = 0; p < n_s && e == hipSuccess; ++p) {
+        hipLaunchKernelGGL(k_sst_pass, grid, dim3(256), 0, s, a, b, H, W, r_s);
+        e = hipGetLastError();
+        double* tmp = a;
+        a = b;
+        b = tmp;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sst_round, grid, dim3(256), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
 }  // namespace mpr

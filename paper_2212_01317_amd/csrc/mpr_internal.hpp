@@ -109,6 +109,10 @@ hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t*
                            int nblocks, double* out, hipStream_t s);
 int validate_blocks(int64_t n);
 
+// Sec. 2.2.3: site temperatures from the block map by n_s passes of the radius-r_s window mean (FP64 planes a, b).
+hipError_t launch_sst(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
+                      int32_t n_s, double* a, double* b, float* out, hipStream_t s);
+
 // ---- instruction-rate probe (rates.hip) ----
 // Probes, in order: v_add_u32, v_mad_u64_u32 (+ one v_xor_b32 per step), v_mul_lo_u32, v_mul_hi_u32, v_bitop3_b32,
 // v_sin_f32, v_cos_f32, v_exp_f32, v_cvt_f32_u32.  ns[i] = kernel time of probe i (same instruction count each).
