@@ -1,0 +1,111 @@
+"""Validation of the gap-filling methods in the manner of Sec. 3.2 (Tables 2 and 3, Fig. 10).
+
+For a complete field and each missing-data ratio p, M masks remove round(p H W) pixels uniformly at random; every
+method predicts the removed pixels from the rest; AAE and RASE (Eq. 3, Eq. 4) over the removed pixels are averaged
+over the masks (MAAE, MRASE), next to the mean time of one prediction (map, temperatures, simulation, conditional
+mean) on the device.  Methods: MPR (one global temperature, uniform random start), SV-MPR with block temperatures
+(BST, Sec. 2.2.2) and with site temperatures (SST, Sec. 2.2.3).  Every step runs in the library; this module only
+draws the masks and orders the calls.
+
+    python -m paper_2212_01317_amd.validation --L 256 --M 100 --p 0.1,0.3,0.5,0.7,0.9
+
+prints one JSON object per (p, method).  The paper's data sets are not available; the default field is the seeded
+stand-in `synth.skewed_field`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import INIT_BLOCK_MEAN, INIT_RANDOM, mpr_validate, predict, reference_curve
+from . import synth
+
+METHODS = ("MPR", "BST", "SST")
+
+
+@dataclass
+class Setting:
+    n_real: int = 10            # realizations per prediction
+    n_samp: int = 1             # sampling sweeps per realization
+    block: int = 32             # l_b of BST and SST
+    r_s: int = 1                # SST smoothing radius
+    n_s: int = 5                # SST smoothing passes (the paper's tables use 5)
+    n_max: int = 1000
+    seed: int = 0
+
+
+def masks_for(H: int, W: int, p: float, M: int, seed: int):
+    """M masks (1 = sample) removing round(p H W) pixels uniformly; mask m depends only on (seed, p, m)."""
+    out = []
+    for m in range(M):
+        rng = np.random.default_rng([seed, int(round(p * 1000)), m])
+        out.append(synth.uniform_mask(H, W, int(round(p * H * W)), rng))
+    return out
+
+
+def predict_method(method: str, z: torch.Tensor, mask: torch.Tensor, s: Setting, curve, scene_id: int):
+    H, W = int(z.shape[0]), int(z.shape[1])
+    common = dict(n_real=s.n_real, n_samp=s.n_samp, n_max=s.n_max, seed=s.seed, scene_id=scene_id, curve=curve)
+    if method == "MPR":
+        return predict(z, mask, block=(H, W), init_mode=INIT_RANDOM, **common)
+    if method == "BST":
+        return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, **common)
+    if method == "SST":
+        return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, sst=(s.r_s, s.n_s), **common)
+    raise ValueError(f"unknown method {method}")
+
+
+def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda"):
+    """Rows {p, method, MAAE, MRASE, t_ms, sweeps} for every p and method (the same masks for every method)."""
+    s = setting or Setting()
+    dev = torch.device(device)
+    H, W = field.shape
+    truth = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).to(dev)
+    curve = reference_curve(0.5, dev)
+    rows = []
+    for p in ps:
+        masks = masks_for(H, W, float(p), M, s.seed)
+        for method in methods:
+            aae, rase, times, sweeps = [], [], [], []
+            for m, mk in enumerate(masks):
+                mask = torch.from_numpy(mk).to(dev)
+                ev = (1 - mask).contiguous()
+                z = (truth * mask).contiguous()         # removed values are not read; zeroed for clarity
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pr = predict_method(method, z, mask, s, curve, scene_id=m)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                e = mpr_validate(pr.zhat, truth, ev).cpu().numpy()
+                aae.append(float(e[0]))
+                rase.append(float(e[1]))
+                sweeps.append(pr.sim.sweeps + s.n_samp)
+            rows.append(dict(p=float(p), method=method, MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
+                             t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)), M=M, L=[H, W]))
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--M", type=int, default=100)
+    ap.add_argument("--p", type=str, default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9")
+    ap.add_argument("--methods", type=str, default=",".join(METHODS))
+    ap.add_argument("--n-real", type=int, default=10)
+    ap.add_argument("--field-seed", type=int, default=synth.seed_for(6, synth.ROLE_FIELD))
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    field = synth.skewed_field(a.L, a.field_seed)
+    rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
+               Setting(n_real=a.n_real, seed=a.seed))
+    for r in rows:
+        print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()
