@@ -52,6 +52,7 @@ typedef enum {
 enum { MPR_INIT_RANDOM = 0, MPR_INIT_BLOCK_MEAN = 1 };
 enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
 enum { MPR_T_BLOCK = 0, MPR_T_SITE = 1 };
+enum { MPR_ORDER_SC = 0, MPR_ORDER_DC = 1 };
 
 /* Parameters of one conditional simulation (host struct). */
 typedef struct {
@@ -72,6 +73,10 @@ typedef struct {
                              MPR_T_SITE (1): T_blocks has one temperature per site, [H*W] (SST, Sec. 2.2.3), while
                              lb_h x lb_w still give the blocks of the block-mean start.  Zero-initialised configs are
                              MPR_T_BLOCK. */
+    int32_t order;        /* MPR_ORDER_SC (0): single checkerboard, all gap sites of colour 0 then of colour 1;
+                             MPR_ORDER_DC (1): double checkerboard of Sec. 2.2.2 over the lb_h x lb_w blocks coloured
+                             by (block row + block column) % 2: colour 0 then 1 in the even blocks, then in the odd
+                             blocks (a different chain; mpr_simulate only). */
 } mpr_sim_config;
 
 /* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;

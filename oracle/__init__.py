@@ -83,7 +83,7 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_stop_check.argtypes = [_f64p, _i32, _i32, _i32]
     L.orc_stop_check.restype = ctypes.c_int
     L.orc_simulate.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _i32, _i32, _i32, _i32,
-                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _f32p, _f64p, _f64p,
+                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _i32, _f32p, _f64p, _f64p,
                                ctypes.POINTER(_i32)]
     L.orc_simulate.restype = _i32
     L.orc_sst_temperatures.argtypes = [_f32p, _i64, _i64, _i32, _i32, _i32, _i32, _f32p]
@@ -233,6 +233,7 @@ class SimConfig:
     seed: int = 0
     scene: int = 0
     t_mode: int = 0             # 0 block temperatures (BST), 1 one temperature per site (SST)
+    order: int = 0              # 0 single checkerboard, 1 double checkerboard over the blocks
 
 
 @dataclass
@@ -256,7 +257,7 @@ def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
     conv = _i32(0)
     k = lib().orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
                            cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp, cfg.n_fit, cfg.n_f,
-                           cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, state, acc, en, ctypes.byref(conv))
+                           cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, cfg.order, state, acc, en, ctypes.byref(conv))
     return SimResult(state=state, acc=acc, energy=en[: k + 1].copy(), k_star=int(k), converged=bool(conv.value))
 
 

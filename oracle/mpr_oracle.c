@@ -278,6 +278,33 @@ static void metropolis_site(float* s, int64_t H, int64_t W, int64_t x, int64_t y
     if (accept) s[n] = (float)t_new;
 }
 
+/* Sec. 2.2.2, double checkerboard (DC): the grid is divided into the lb_h x lb_w blocks, coloured like a
+ * checkerboard by (block row + block column) % 2; one sweep = the gap sites of colour 0, then of colour 1, inside
+ * the even blocks, then the same inside the odd blocks.  Sites of one such phase share no bond.  The temperature of
+ * a site is read from T with the tb_h x tb_w layout (the blocks themselves, or 1 x 1 for one temperature per
+ * site).  The random numbers of a site are those of the single-checkerboard order. */
+void orc_sweep_dc(float* s, const uint8_t* mask, int64_t H, int64_t W, const float* T, int32_t tb_h, int32_t tb_w,
+                  int32_t lb_h, int32_t lb_w, float q, float J, uint64_t seed, uint32_t scene, uint32_t real,
+                  uint32_t sweep)
+{
+    int64_t nbx_t = (W + tb_w - 1) / tb_w;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    for (int parity = 0; parity < 2; ++parity) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t y = 0; y < H; ++y) {
+                for (int64_t x = (y + colour) & 1; x < W; x += 2) {
+                    if (mask[y * W + x]) continue;
+                    if ((int)(((y / lb_h) + (x / lb_w)) & 1) != parity) continue;
+                    double Tn = (double)T[(y / tb_h) * nbx_t + (x / tb_w)];
+                    double u1, u2;
+                    site_uniforms(seed, scene, ORC_TAG_SWEEP, sweep, real, W, x, y, &u1, &u2);
+                    metropolis_site(s, H, W, x, y, Tn, tpq, (double)J, u1, u2, 0);
+                }
+            }
+        }
+    }
+}
+
 /* Sec. 2.2.2, single checkerboard: one sweep = all gap sites of colour 0, then all gap sites of colour 1.  Sites
  * of one colour share no bond, so their order inside a half-sweep does not matter.  Each site uses the
  * temperature of its T-block (the same block layout as the energy estimate). */
@@ -434,6 +461,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
                      int32_t init_mode /* 0 random, 1 block mean */, int32_t stop_mode /* 0 fixed, 1 auto */,
                      int32_t n_eq, int32_t n_samp, int32_t n_fit, int32_t n_f, int32_t n_max, uint64_t seed,
                      uint32_t scene, int32_t t_per_site /* 0: T_blocks per block, 1: T_blocks[H*W] per site */,
+                     int32_t order /* 0: single checkerboard, 1: double checkerboard over the lb_h x lb_w blocks */,
                      float* state, double* acc, double* energy, int32_t* converged)
 {
     /* the temperature layout the sweeps read: blocks of lb_h x lb_w, or one temperature per site (SST) */
@@ -486,8 +514,12 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
         double ek = 0.0;
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
-                      (uint32_t)k);
+            if (order == 1)
+                orc_sweep_dc(s, mask, H, W, T_blocks, tb_h, tb_w, lb_h, lb_w, q, J, seed, scene,
+                             (uint32_t)(r + real_offset), (uint32_t)k);
+            else
+                orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
+                          (uint32_t)k);
             ek += orc_energy(s, H, W, q, J);
         }
         energy[k] = ek / (double)R;
@@ -498,8 +530,12 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
-                      (uint32_t)(k_star + s_i));
+            if (order == 1)
+                orc_sweep_dc(s, mask, H, W, T_blocks, tb_h, tb_w, lb_h, lb_w, q, J, seed, scene,
+                             (uint32_t)(r + real_offset), (uint32_t)(k_star + s_i));
+            else
+                orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
+                          (uint32_t)(k_star + s_i));
         }
         for (int32_t r = 0; r < R; ++r) {
             const float* s = state + (int64_t)r * HW;

@@ -22,6 +22,7 @@ _STATUS = {0: "MPR_OK", 1: "MPR_ERR_INVALID_ARG", 2: "MPR_ERR_SHAPE", 3: "MPR_ER
 INIT_RANDOM, INIT_BLOCK_MEAN = 0, 1
 STOP_FIXED, STOP_AUTO = 0, 1
 T_BLOCK, T_SITE = 0, 1
+ORDER_SC, ORDER_DC = 0, 1
 
 
 class MprError(RuntimeError):
@@ -35,7 +36,7 @@ class mpr_sim_config(ctypes.Structure):
                 ("real_offset", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("n_eq", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_fit", ctypes.c_int32),
                 ("n_f", ctypes.c_int32), ("n_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32)]
+                ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 @dataclass
@@ -55,11 +56,12 @@ class SimConfig:
     seed: int = 0
     scene_id: int = 0
     t_mode: int = T_BLOCK       # T_BLOCK: one temperature per block; T_SITE: one per site (SST)
+    order: int = ORDER_SC       # ORDER_SC single checkerboard; ORDER_DC double checkerboard over the blocks
 
     def to_c(self) -> mpr_sim_config:
         return mpr_sim_config(self.q, self.J, self.n_real, self.real_offset, self.init_mode, self.stop_mode,
                               self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id,
-                              self.t_mode)
+                              self.t_mode, self.order)
 
 
 def _check_T(T_blocks, H, W, lb_h, lb_w, cfg: "SimConfig"):

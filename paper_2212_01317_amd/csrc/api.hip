@@ -219,6 +219,7 @@ mpr_status check_sim_config(const mpr_sim_config& c)
     if (c.real_offset < 0) return fail(MPR_ERR_INVALID_ARG, "real_offset must be >= 0");
     if (c.scene_id >= (1u << 28)) return fail(MPR_ERR_INVALID_ARG, "scene_id must be < 2^28");
     if (c.t_mode != MPR_T_BLOCK && c.t_mode != MPR_T_SITE) return fail(MPR_ERR_INVALID_ARG, "unknown t_mode %d", c.t_mode);
+    if (c.order != MPR_ORDER_SC && c.order != MPR_ORDER_DC) return fail(MPR_ERR_INVALID_ARG, "unknown order %d", c.order);
     return MPR_OK;
 }
 
@@ -685,12 +686,44 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
 
     const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
+    const int nfull = mpr::energy_full_parts(H, W);
     if (need_energy) {
-        const int nfull = mpr::energy_full_parts(H, W);
         MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
         MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series, s));
     }
-    auto sweep = [&](uint32_t k, bool energy) -> hipError_t { return runner.run(k, energy ? w.series + k : nullptr); };
+    // double checkerboard: in place in `state`, energy of the whole grid after the sweep
+    const bool dc = c.order == MPR_ORDER_DC;
+    mpr::DcArgs da;
+    da.state = state;
+    da.mask = mask;
+    da.tb = w.tp;
+    da.H = H;
+    da.W = W;
+    da.lb_h = lb_h;
+    da.lb_w = lb_w;
+    da.tb_h = t_lb(lb_h, c);
+    da.tb_w = t_lb(lb_w, c);
+    da.nbx_t = (int)((W + da.tb_w - 1) / da.tb_w);
+    da.Mw = (int)((W + 3) / 4);
+    da.R = R;
+    da.real_offset = (uint32_t)c.real_offset;
+    da.scene = c.scene_id;
+    da.key0 = key0;
+    da.key1 = key1;
+    da.q = c.q;
+    da.J = c.J;
+    da.delta_e = mpr::kDeltaE * c.J;
+    da.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+    da.Jd = (double)c.J;
+    auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
+        if (!dc) return runner.run(k, energy ? w.series + k : nullptr);
+        hipError_t e = mpr::launch_dc_sweep(da, k, s);
+        if (e == hipSuccess && energy) e = mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s);
+        if (e == hipSuccess && energy)
+            e = mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series + k, s);
+        return e;
+    };
+    auto current = [&]() -> float* { return dc ? state : runner.current(); };
 
     const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
     int32_t k = 0;
@@ -720,10 +753,10 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     }
     for (int32_t si = 1; si <= c.n_samp; ++si) {
         MPR_HIP(sweep((uint32_t)(k_star + si), false));
-        MPR_HIP(mpr::launch_accumulate(runner.current(), mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
+        MPR_HIP(mpr::launch_accumulate(current(), mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
     }
-    if (runner.current() != state) {
-        MPR_HIP(hipMemcpyAsync(state, runner.current(), sizeof(float) * (size_t)(R * HW), hipMemcpyDeviceToDevice, s));
+    if (current() != state) {
+        MPR_HIP(hipMemcpyAsync(state, current(), sizeof(float) * (size_t)(R * HW), hipMemcpyDeviceToDevice, s));
     }
     if (energy_out && need_energy) {
         MPR_HIP(hipMemcpyAsync(energy_out, w.series, sizeof(double) * (size_t)(k_star + 1), hipMemcpyDeviceToDevice,
@@ -752,6 +785,7 @@ mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_
     if (!state || !state_alt || !mask || !T_blocks) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: NULL pointer");
     if (state == state_alt) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: state and state_alt must be distinct buffers");
     if ((st = check_sim_config(*cfg)) != MPR_OK) return st;
+    if (cfg->order != MPR_ORDER_SC) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep runs the single-checkerboard order");
     if (k_first < 1 || n_sweeps < 0) return fail(MPR_ERR_INVALID_ARG, "need k_first >= 1 and n_sweeps >= 0");
     st = check_ws(workspace, ws_bytes, mpr_sweep_workspace_bytes(H, W, lb_h, lb_w, cfg));
     if (st != MPR_OK) return st;
@@ -832,6 +866,7 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
     if (tile_h != 0 && tile_h != 16 && tile_h != 32) return fail(MPR_ERR_INVALID_ARG, "tile_h must be 0, 16 or 32");
     if (c.t_mode != MPR_T_BLOCK) return fail(MPR_ERR_INVALID_ARG, "the batched form takes block temperatures only");
+    if (c.order != MPR_ORDER_SC) return fail(MPR_ERR_INVALID_ARG, "the batched form runs the single-checkerboard order");
     for (int i = 0; i < n_scenes; ++i) {
         const mpr_scene& sc = scenes[i];
         if ((st = check_grid(sc.H, sc.W)) != MPR_OK) return st;

@@ -109,6 +109,21 @@ hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t*
                            int nblocks, double* out, hipStream_t s);
 int validate_blocks(int64_t n);
 
+// Sec. 2.2.2 double-checkerboard sweep (dc.hip): four in-place phases per sweep over all realizations.
+struct DcArgs {
+    float* state;        // [R][H][W], updated in place
+    const uint8_t* mask;
+    const TBand* tb;     // temperatures with the tb_h x tb_w layout (blocks, or 1 x 1 per site)
+    int64_t H, W;
+    int lb_h, lb_w;      // the blocks of the checkerboard
+    int tb_h, tb_w, nbx_t;
+    int Mw, R;
+    uint32_t real_offset, scene, key0, key1;
+    float q, J, delta_e;
+    double two_pi_q, Jd;
+};
+hipError_t launch_dc_sweep(const DcArgs& a, uint32_t sweep, hipStream_t s);
+
 // Sec. 2.2.3: site temperatures from the block map by n_s passes of the radius-r_s window mean (FP64 planes a, b).
 hipError_t launch_sst(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, int32_t r_s,
                       int32_t n_s, double* a, double* b, float* out, hipStream_t s);

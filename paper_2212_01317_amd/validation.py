@@ -4,12 +4,14 @@ For a complete field and each missing-data ratio p, M masks remove round(p H W) 
 method predicts the removed pixels from the rest; AAE and RASE (Eq. 3, Eq. 4) over the removed pixels are averaged
 over the masks (MAAE, MRASE), next to the mean time of one prediction (map, temperatures, simulation, conditional
 mean) on the device.  Methods: MPR (one global temperature, uniform random start), SV-MPR with block temperatures
-(BST, Sec. 2.2.2) and with site temperatures (SST, Sec. 2.2.3).  Every step runs in the library; this module only
+(BST, Sec. 2.2.2; BST-DC: the same in the double-checkerboard order) and with site temperatures (SST, Sec. 2.2.3);
+for the SV-MPR methods every block size of `blocks` (the l_b study of Fig. 11).  Every step runs in the library; this module only
 draws the masks and orders the calls.
 
     python -m paper_2212_01317_amd.validation --L 256 --M 100 --p 0.1,0.3,0.5,0.7,0.9
+    python -m paper_2212_01317_amd.validation --L 256 --M 20 --p 0.3,0.8 --methods BST,BST-DC --blocks 8,16,32,64
 
-prints one JSON object per (p, method).  The paper's data sets are not available; the default field is the seeded
+prints one JSON object per (p, method, block).  The paper's data sets are not available; the default field is the seeded
 stand-in `synth.skewed_field`.
 """
 from __future__ import annotations
@@ -22,10 +24,11 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import INIT_BLOCK_MEAN, INIT_RANDOM, mpr_validate, predict, reference_curve
+from . import INIT_BLOCK_MEAN, INIT_RANDOM, ORDER_DC, mpr_validate, predict, reference_curve
 from . import synth
 
 METHODS = ("MPR", "BST", "SST")
+ALL_METHODS = ("MPR", "BST", "SST", "BST-DC")
 
 
 @dataclass
@@ -57,20 +60,27 @@ def predict_method(method: str, z: torch.Tensor, mask: torch.Tensor, s: Setting,
         return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, **common)
     if method == "SST":
         return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, sst=(s.r_s, s.n_s), **common)
+    if method == "BST-DC":
+        return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, order=ORDER_DC, **common)
     raise ValueError(f"unknown method {method}")
 
 
-def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda"):
-    """Rows {p, method, MAAE, MRASE, t_ms, sweeps} for every p and method (the same masks for every method)."""
-    s = setting or Setting()
+def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda",
+        blocks=None):
+    """Rows {p, method, block, MAAE, MRASE, t_ms, sweeps} for every p, method and (SV-MPR) block size; the same masks
+    for every method."""
+    import dataclasses
+    s0 = setting or Setting()
+    blocks = list(blocks) if blocks else [s0.block]
     dev = torch.device(device)
     H, W = field.shape
     truth = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).to(dev)
     curve = reference_curve(0.5, dev)
     rows = []
     for p in ps:
-        masks = masks_for(H, W, float(p), M, s.seed)
-        for method in methods:
+        masks = masks_for(H, W, float(p), M, s0.seed)
+        for method, s in [(mt, dataclasses.replace(s0, block=b)) for mt in methods
+                          for b in ([blocks[0]] if mt == "MPR" else blocks)]:
             aae, rase, times, sweeps = [], [], [], []
             for m, mk in enumerate(masks):
                 mask = torch.from_numpy(mk).to(dev)
@@ -85,7 +95,8 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
                 aae.append(float(e[0]))
                 rase.append(float(e[1]))
                 sweeps.append(pr.sim.sweeps + s.n_samp)
-            rows.append(dict(p=float(p), method=method, MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
+            rows.append(dict(p=float(p), method=method, block=None if method == "MPR" else s.block,
+                             MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
                              t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)), M=M, L=[H, W]))
     return rows
 
@@ -97,12 +108,13 @@ def main():
     ap.add_argument("--p", type=str, default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9")
     ap.add_argument("--methods", type=str, default=",".join(METHODS))
     ap.add_argument("--n-real", type=int, default=10)
+    ap.add_argument("--blocks", type=str, default="32", help="block sizes l_b of the SV-MPR methods")
     ap.add_argument("--field-seed", type=int, default=synth.seed_for(6, synth.ROLE_FIELD))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
     field = synth.skewed_field(a.L, a.field_seed)
     rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
-               Setting(n_real=a.n_real, seed=a.seed))
+               Setting(n_real=a.n_real, seed=a.seed), blocks=[int(b) for b in a.blocks.split(",")])
     for r in rows:
         print(json.dumps(r), flush=True)
 

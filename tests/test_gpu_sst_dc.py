@@ -1,6 +1,7 @@
-"""SST (Sec. 2.2.3, site-specific temperatures) on the GPU against the oracle: the smoothed temperature plane bit for
-bit, and conditional simulations with one temperature per site (same chains, same predictions), on ragged grids
-and on sampled realizations of the 1024^2 configuration."""
+"""SST (Sec. 2.2.3, site-specific temperatures) and the double-checkerboard order (Sec. 2.2.2) on the GPU against the
+oracle: the smoothed temperature plane bit for bit; conditional simulations with one temperature per site and in
+the double-checkerboard order (same chains, same predictions), on ragged grids and on sampled realizations of the
+1024^2 configuration."""
 import numpy as np
 import pytest
 import torch
@@ -98,3 +99,41 @@ def test_sst_error_paths():
     scene = dict(t=t, mask=m, T_blocks=dev(np.full(20 * 24, 0.1, np.float32)), block=(16, 16), scene_id=0)
     with pytest.raises(M.MprError):
         M.mpr_simulate_batched([scene], cfg, tile_h=0)
+
+
+@pytest.mark.parametrize("lb,stop,sst", [((8, 8), "fixed", False), ((16, 12), "auto", False), ((10, 14), "fixed", True)])
+def test_double_checkerboard_matches_oracle(lb, stop, sst):
+    sc = synth.random_small(47, 61, 0.5, seed=37)
+    t, rg = oracle.map_angles(sc.z_obs, sc.mask)
+    nb = ((47 + lb[0] - 1) // lb[0], (61 + lb[1] - 1) // lb[1])
+    T = np.random.default_rng(lb[0]).uniform(0.02, 0.3, nb).astype(np.float32)
+    t_mode = 0
+    if sst:
+        T = oracle.sst_temperatures(T, 47, 61, *lb, r_s=1, n_s=3)
+        t_mode = 1
+    if stop == "fixed":
+        oc = OCfg(n_real=5, init_mode=1, stop_mode=0, n_eq=20, n_samp=2, seed=21, t_mode=t_mode, order=1)
+        cfg = M.SimConfig(n_real=5, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=20, n_samp=2, seed=21,
+                          t_mode=t_mode, order=M.ORDER_DC)
+    else:
+        oc = OCfg(n_real=4, init_mode=1, stop_mode=1, n_samp=1, n_max=150, seed=22, t_mode=t_mode, order=1)
+        cfg = M.SimConfig(n_real=4, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_max=150, seed=22,
+                          t_mode=t_mode, order=M.ORDER_DC)
+    o = oracle.simulate(t, sc.mask, T, *lb, oc)
+    g = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb, cfg)
+    assert g.sweeps == o.k_star
+    assert np.array_equal(host(g.state), o.state)
+    assert np.array_equal(host(g.acc), o.acc)
+    assert np.allclose(host(g.energy), o.energy, rtol=0, atol=1e-5)
+
+
+def test_double_checkerboard_only_where_supported():
+    sc = synth.random_small(20, 24, 0.5, seed=2)
+    t, m = dev(sc.z_obs * 0 + 0.5), dev(sc.mask)
+    T = dev(np.full((2, 2), 0.1, np.float32))
+    cfg = M.SimConfig(n_real=2, stop_mode=M.STOP_FIXED, n_eq=1, order=M.ORDER_DC)
+    state = torch.zeros((2, 20, 24), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MprError):
+        M.mpr_sweep(state, m, T, 16, 16, cfg, 1, 2)
+    with pytest.raises(M.MprError):
+        M.mpr_simulate_batched([dict(t=t, mask=m, T_blocks=T, block=(16, 16), scene_id=0)], cfg, tile_h=0)

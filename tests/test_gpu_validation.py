@@ -21,12 +21,12 @@ def _oracle_errors(field, mask, method, s, cT, ce, scene):
     else:
         lb, init = (s.block, s.block), 1
     T, _, _ = oracle.calibrate_temperature(t, mask, lb[0], lb[1], cT, ce)
-    t_mode = 0
+    t_mode, order = 0, 1 if method == "BST-DC" else 0
     if method == "SST":
         T = oracle.sst_temperatures(T, H, W, lb[0], lb[1], r_s=s.r_s, n_s=s.n_s)
         t_mode = 1
     cfg = OCfg(n_real=s.n_real, init_mode=init, stop_mode=1, n_samp=s.n_samp, n_max=s.n_max, seed=s.seed,
-               scene=scene, t_mode=t_mode)
+               scene=scene, t_mode=t_mode, order=order)
     r = oracle.simulate(t, mask, T, lb[0], lb[1], cfg)
     zhat = oracle.predict(r.acc, z, mask, s.n_real * s.n_samp, rg)
     return oracle.validate(zhat, field, (1 - mask).astype(np.uint8))
@@ -35,7 +35,7 @@ def _oracle_errors(field, mask, method, s, cT, ce, scene):
 def test_harness_matches_oracle():
     field = synth.skewed_field(48, 3)[:48, :40].copy()
     s = V.Setting(n_real=2, n_samp=1, block=16, n_max=80, seed=4)
-    rows = V.run(field, [0.4], 2, V.METHODS, s)
+    rows = V.run(field, [0.4], 2, V.ALL_METHODS, s)
     cT, ce = (x.cpu().numpy() for x in reference_curve(0.5))
     masks = V.masks_for(48, 40, 0.4, 2, s.seed)
     for row in rows:

@@ -1,6 +1,7 @@
-"""Pins of the oracle's site-specific temperatures (Sec. 2.2.3, SST): the smoothing against hand-computed values
-and an independent library box filter, and the per-site simulation against the block simulation when the per-site
-map is the block map."""
+"""Pins of the oracle's SST (Sec. 2.2.3, site-specific temperatures) and double-checkerboard order (Sec. 2.2.2):
+the smoothing against hand-computed values and an independent library box filter, the per-site simulation against
+the block simulation when the per-site map is the block map, and the double-checkerboard sweep against the single
+checkerboard in the two layouts where they visit the sites in the same order."""
 import numpy as np
 import pytest
 from scipy import ndimage
@@ -68,3 +69,43 @@ def test_per_site_simulation_of_the_block_map_is_the_block_simulation():
     Ts5 = oracle.sst_temperatures(T, 40, 56, *lb, r_s=1, n_s=5)
     sm = oracle.simulate(t, sc.mask, Ts5, *lb, SimConfig(**{**cfg.__dict__, "t_mode": 1}))
     assert not np.array_equal(sm.state, blk.state)
+
+
+def _dc_case(lb, seed=5):
+    sc = synth.random_small(30, 42, 0.5, seed=seed)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    nb = ((30 + lb[0] - 1) // lb[0], (42 + lb[1] - 1) // lb[1])
+    T = np.random.default_rng(8).uniform(0.02, 0.4, nb).astype(np.float32)
+    return sc, t, T
+
+
+@pytest.mark.parametrize("lb", [(30, 42), (1, 1)])
+def test_double_checkerboard_reduces_to_single(lb):
+    """Sec. 2.2.2 orders: with one block covering the grid, or with 1 x 1 blocks (block parity = site colour), the
+    double-checkerboard sweep visits the sites in the single-checkerboard order: the chains are identical."""
+    sc, t, T = _dc_case(lb)
+    cfg = SimConfig(n_real=2, init_mode=1, stop_mode=0, n_eq=10, n_samp=1, seed=3)
+    sc_run = oracle.simulate(t, sc.mask, T, *lb, cfg)
+    dc_run = oracle.simulate(t, sc.mask, T, *lb, SimConfig(**{**cfg.__dict__, "order": 1}))
+    assert np.array_equal(dc_run.state, sc_run.state)
+
+
+def test_double_checkerboard_is_another_chain():
+    sc, t, T = _dc_case((8, 8))
+    cfg = SimConfig(n_real=2, init_mode=1, stop_mode=0, n_eq=10, n_samp=1, seed=3)
+    a = oracle.simulate(t, sc.mask, T, 8, 8, cfg)
+    b = oracle.simulate(t, sc.mask, T, 8, 8, SimConfig(**{**cfg.__dict__, "order": 1}))
+    assert not np.array_equal(a.state, b.state)
+    # observed sites untouched and every gap state a proposal value in [0, 1)
+    obs = sc.mask == 1
+    assert np.array_equal(b.state[:, obs], np.broadcast_to(t[obs], b.state[:, obs].shape))
+    assert np.all((b.state[:, ~obs] >= 0) & (b.state[:, ~obs] < 1))
+
+
+def test_double_checkerboard_zero_temperature_energy_never_increases():
+    """At T = 0 every accepted update lowers (or keeps) the energy, in any visiting order."""
+    sc, t, _ = _dc_case((8, 8), seed=9)
+    T0 = np.zeros((4, 6), np.float32)
+    e = [oracle.simulate(t, sc.mask, T0, 8, 8, SimConfig(n_real=1, init_mode=0, stop_mode=0, n_eq=k, n_samp=0,
+                                                            seed=2, order=1)).energy[-1] for k in range(0, 6)]
+    assert all(b <= a + 1e-12 for a, b in zip(e, e[1:]))
