@@ -5,18 +5,19 @@ method predicts the removed pixels from the rest; AAE and RASE (Eq. 3, Eq. 4) ov
 over the masks (MAAE, MRASE), next to the mean time of one prediction (map, temperatures, simulation, conditional
 mean) on the device.  Methods: MPR (one global temperature, uniform random start), SV-MPR with block temperatures
 (BST, Sec. 2.2.2; BST-DC: the same in the double-checkerboard order) and with site temperatures (SST, Sec. 2.2.3);
-for the SV-MPR methods every block size of `blocks` (the l_b study of Fig. 11).  Every step runs in the library; this module only
-draws the masks and orders the calls.
+for the SV-MPR methods every block size of `blocks`, and for SST every smoothing count of `ns` (the l_b and n_s
+studies of Fig. 11).  Every step runs in the library; this module only draws the masks and orders the calls.
 
     python -m paper_2212_01317_amd.validation --L 256 --M 100 --p 0.1,0.3,0.5,0.7,0.9
-    python -m paper_2212_01317_amd.validation --L 256 --M 20 --p 0.3,0.8 --methods BST,BST-DC --blocks 8,16,32,64
+    python -m paper_2212_01317_amd.validation --L 1024 --M 10 --p 0.3,0.8 --field ns --blocks 8,16,32,64
 
-prints one JSON object per (p, method, block).  The paper's data sets are not available; the default field is the seeded
-stand-in `synth.skewed_field`.
+prints one JSON object per (p, method, block, n_s).  The paper's data sets are not available; the fields are seeded
+stand-ins: `synth.skewed_field` (default) or the plain non-stationary field `synth.ns_field` (--field ns).
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import time
 from dataclasses import dataclass
@@ -65,13 +66,26 @@ def predict_method(method: str, z: torch.Tensor, mask: torch.Tensor, s: Setting,
     raise ValueError(f"unknown method {method}")
 
 
+def variants(methods, s0: Setting, blocks, ns):
+    """(method, setting) pairs: MPR once, BST and BST-DC per block size, SST per block size and smoothing count."""
+    out = []
+    for mt in methods:
+        if mt == "MPR":
+            out.append((mt, s0))
+        elif mt == "SST":
+            out += [(mt, dataclasses.replace(s0, block=b, n_s=n)) for b in blocks for n in ns]
+        else:
+            out += [(mt, dataclasses.replace(s0, block=b)) for b in blocks]
+    return out
+
+
 def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda",
-        blocks=None):
-    """Rows {p, method, block, MAAE, MRASE, t_ms, sweeps} for every p, method and (SV-MPR) block size; the same masks
-    for every method."""
-    import dataclasses
+        blocks=None, ns=None):
+    """Rows {p, method, block, n_s, MAAE, MRASE, t_ms, sweeps} for every p and variant; the same masks for every
+    variant."""
     s0 = setting or Setting()
     blocks = list(blocks) if blocks else [s0.block]
+    ns = list(ns) if ns else [s0.n_s]
     dev = torch.device(device)
     H, W = field.shape
     truth = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).to(dev)
@@ -79,8 +93,7 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
     rows = []
     for p in ps:
         masks = masks_for(H, W, float(p), M, s0.seed)
-        for method, s in [(mt, dataclasses.replace(s0, block=b)) for mt in methods
-                          for b in ([blocks[0]] if mt == "MPR" else blocks)]:
+        for method, s in variants(methods, s0, blocks, ns):
             aae, rase, times, sweeps = [], [], [], []
             for m, mk in enumerate(masks):
                 mask = torch.from_numpy(mk).to(dev)
@@ -96,7 +109,7 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
                 rase.append(float(e[1]))
                 sweeps.append(pr.sim.sweeps + s.n_samp)
             rows.append(dict(p=float(p), method=method, block=None if method == "MPR" else s.block,
-                             MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
+                             n_s=s.n_s if method == "SST" else None, MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
                              t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)), M=M, L=[H, W]))
     return rows
 
@@ -109,12 +122,18 @@ def main():
     ap.add_argument("--methods", type=str, default=",".join(METHODS))
     ap.add_argument("--n-real", type=int, default=10)
     ap.add_argument("--blocks", type=str, default="32", help="block sizes l_b of the SV-MPR methods")
+    ap.add_argument("--ns", type=str, default="5", help="smoothing counts n_s of SST")
+    ap.add_argument("--field", choices=("skewed", "ns"), default="skewed")
     ap.add_argument("--field-seed", type=int, default=synth.seed_for(6, synth.ROLE_FIELD))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
-    field = synth.skewed_field(a.L, a.field_seed)
+    if a.field == "skewed":
+        field = synth.skewed_field(a.L, a.field_seed)
+    else:
+        field = synth.ns_field(a.L, a.L, 4, (2.0, 32.0), np.random.default_rng(a.field_seed)).astype(np.float32)
     rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
-               Setting(n_real=a.n_real, seed=a.seed), blocks=[int(b) for b in a.blocks.split(",")])
+               Setting(n_real=a.n_real, seed=a.seed), blocks=[int(b) for b in a.blocks.split(",")],
+               ns=[int(n) for n in a.ns.split(",")])
     for r in rows:
         print(json.dumps(r), flush=True)
 
