@@ -5,8 +5,9 @@ map to angles -> block temperatures (32 x 32 blocks) -> conditional simulation o
 automatic equilibrium test and one sampling sweep -> prediction -> validation error (AAE/RASE) on the removed pixels.
 value = gap-site updates per second = sum over steps of R * (gap sites) * (sweeps) / wall time of the steps.
 
-Prints one JSON line.  --profile-sweeps N runs only N sweeps of the sweep kernel (plus a 1 GiB device copy used to
-calibrate the HBM byte counters) and prints nothing else; it is the command the counter profiles are taken with.
+Prints one JSON line.  --profile-sweeps N runs only the start and N sweeps (energy of each sweep, as in the
+automatic stop) of the simulation, plus a 1 GiB device copy used to calibrate the HBM byte counters, and prints
+nothing else; it is the command the counter profiles are taken with.
 """
 from __future__ import annotations
 
@@ -48,33 +49,46 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 
-SWEEP_SOURCES = ("sweep_body.hpp", "sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp")
-HBM_PROFILE = os.path.join(ROOT, "profiles", "k_sweep_fused_c3_p0.6_hbm.txt")
+# The simulation sweeps with the realization-lane kernel when R >= 64 (one realization per lane), else with the
+# fused tile kernel; the sources each kernel is built from, for matching a committed counter summary.
+SWEEP_SOURCES = {
+    "k_sweep_rl": ("rl_sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp"),
+    "k_sweep_fused": ("sweep_body.hpp", "sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp"),
+}
 
 
-def sweep_sources_sha256() -> str:
+def sweep_kernel(R: int) -> str:
+    return "k_sweep_rl" if R >= 64 else "k_sweep_fused"
+
+
+def hbm_profile(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_c3_p0.6_hbm.txt")
+
+
+def sweep_sources_sha256(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in SWEEP_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2212_01317_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(L: int, R: int, p: float):
+def measured_traffic(kernel: str, L: int, R: int, p: float):
     """HBM bytes per sweep launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the
     counters' reading of a 1 GiB copy), if it was taken on this workload with the current sweep sources; else None."""
-    if not os.path.exists(HBM_PROFILE):
+    path = hbm_profile(kernel)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(HBM_PROFILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     try:
-        same = (kv.get("sources_sha256") == sweep_sources_sha256() and int(kv["size"]) == L and int(kv["n_real"]) == R
-                and float(kv["p"]) == p)
+        same = (kv.get("sources_sha256") == sweep_sources_sha256(kernel) and int(kv["size"]) == L
+                and int(kv["n_real"]) == R and float(kv["p"]) == p)
         return float(kv["hbm_bytes_per_launch"]) if same else None
     except (KeyError, ValueError):
         return None
@@ -146,11 +160,9 @@ def main():
         cT, ce = mpr.reference_curve(0.5, dev, spec=small)
         t, rng = mpr.mpr_map_angles(z, mask)
         T, _, _ = mpr.mpr_calibrate_temperature(t, mask, lb[0], lb[1], cT, ce)
-        mpr.mpr_simulate(t, mask, T, lb[0], lb[1], fixed, state=state, want_energy=False)
-        alt = state.clone()
-        n = args.profile_sweeps + (args.profile_sweeps & 1)
-        mpr.mpr_sweep(state, mask, T, lb[0], lb[1], fixed, 1, n, state_alt=alt)
-        del alt
+        n = args.profile_sweeps
+        prof = mpr.SimConfig(**{**fixed.__dict__, "n_eq": n})
+        mpr.mpr_simulate(t, mask, T, lb[0], lb[1], prof, state=state, want_energy=True)
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.mul(a, 1.0, out=b)
@@ -188,20 +200,28 @@ def main():
     errs = err.cpu().numpy()
     log(f"[bench] {args.steps} steps in {elapsed:.3f}s, sweeps/step {sweeps}, AAE {errs[0]:.5f} RASE {errs[1]:.5f}")
 
-    # roofline of the dominant kernel (one fused sweep over all R realizations), timed with HIP events
-    # on the stream the library launches on (torch's current stream)
-    ns = args.roofline_sweeps + (args.roofline_sweeps & 1)        # even: the result ends in `state`
-    k0 = sim.sweeps + cfg.n_samp + 1
+    # Roofline of the dominant kernel: one sweep of all R realizations as the simulation runs it (with the energy
+    # of the sweep, as under the automatic stop).  HIP events on the stream the library launches on (torch's
+    # current stream) bracket two fixed-length simulations of the same start, n1 and n1 + ns sweeps; their
+    # difference is ns sweeps, each one sweep launch plus the two small launches that reduce its energy.
+    kernel = sweep_kernel(R)
+    ns = args.roofline_sweeps
+    n1 = 4
+
+    def timed_simulation(n):
+        c = mpr.SimConfig(**{**fixed.__dict__, "n_eq": n})
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mpr.mpr_simulate(t, mask, T, lb[0], lb[1], c, state=state, workspace=ws, want_energy=True)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    t, _ = mpr.mpr_map_angles(z, mask)
+    timed_simulation(n1)                                                          # warm
+    t_launch = (timed_simulation(n1 + ns) - timed_simulation(n1)) / ns
     del ws
-    alt = state.clone()
-    mpr.mpr_sweep(state, mask, T, lb[0], lb[1], fixed, k0, 2, state_alt=alt)        # warm
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    mpr.mpr_sweep(state, mask, T, lb[0], lb[1], fixed, k0 + 2, ns, state_alt=alt)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_launch = ev0.elapsed_time(ev1) / 1e3 / ns
     upd_launch = float(R) * n_gap
     rates, add_ns = mpr.mpr_probe_instruction_rates(dev)
     a_upd, a_site, a_parts = algorithmic_costs(rates)
@@ -211,7 +231,7 @@ def main():
     sweep_upd_rate = upd_launch / t_launch
     log(f"[bench] sweep launch {t_launch * 1e3:.3f} ms -> {sweep_upd_rate:.3e} upd/s in the sweep kernel")
 
-    traffic = measured_traffic(L, R, args.p)
+    traffic = measured_traffic(kernel, L, R, args.p)
     alg_bytes = float(R) * n_gap * 8.0              # 4 B read + 4 B written per gap site and realization
     value = updates / elapsed
     out = {
@@ -232,7 +252,7 @@ def main():
                                f"1 sampling sweep; step = map+calibrate+simulate+predict+validate",
                    "H": L, "W": L, "p": args.p, "gap_sites": n_gap, "n_real": R, "block": list(lb),
                    "sweeps_per_step": sweeps},
-        "roofline": {"bound": "alu", "kernel": "k_sweep_fused", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                      "traffic_gbs": traffic / t_launch / 1e9 if traffic else None,
                      "algorithmic_bytes_per_launch": alg_bytes,
@@ -242,7 +262,6 @@ def main():
                      "sweep_kernel_updates_per_s": sweep_upd_rate},
         "validation": {"aae": float(errs[0]), "rase": float(errs[1])},
     }
-    del alt
     if extras_inputs is not None:
         out["sst"] = bench_sst(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
         del state

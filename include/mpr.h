@@ -53,6 +53,7 @@ enum { MPR_INIT_RANDOM = 0, MPR_INIT_BLOCK_MEAN = 1 };
 enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
 enum { MPR_T_BLOCK = 0, MPR_T_SITE = 1 };
 enum { MPR_ORDER_SC = 0, MPR_ORDER_DC = 1 };
+enum { MPR_SWEEP_AUTO = 0, MPR_SWEEP_TILES = 1, MPR_SWEEP_LANES = 2 };
 
 /* Parameters of one conditional simulation (host struct). */
 typedef struct {
@@ -77,6 +78,12 @@ typedef struct {
                              MPR_ORDER_DC (1): double checkerboard of Sec. 2.2.2 over the lb_h x lb_w blocks coloured
                              by (block row + block column) % 2: colour 0 then 1 in the even blocks, then in the odd
                              blocks (a different chain; mpr_simulate only). */
+    int32_t sweep_kernel; /* which kernel mpr_simulate sweeps the single-checkerboard order with; every choice gives
+                             the same chains bit for bit.  MPR_SWEEP_TILES (1): tiles of sites in LDS, lanes =
+                             sites; MPR_SWEEP_LANES (2): state with the realization innermost, lanes = 64
+                             realizations of one site (sides below 65536); MPR_SWEEP_AUTO (0, zero-initialised):
+                             LANES when R >= 64 and the grid gives at least 2048 waves, else TILES.  mpr_sweep and
+                             the batched form use TILES. */
 } mpr_sim_config;
 
 /* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;

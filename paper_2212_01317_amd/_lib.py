@@ -23,6 +23,7 @@ INIT_RANDOM, INIT_BLOCK_MEAN = 0, 1
 STOP_FIXED, STOP_AUTO = 0, 1
 T_BLOCK, T_SITE = 0, 1
 ORDER_SC, ORDER_DC = 0, 1
+SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES = 0, 1, 2
 
 
 class MprError(RuntimeError):
@@ -36,7 +37,8 @@ class mpr_sim_config(ctypes.Structure):
                 ("real_offset", ctypes.c_int32), ("init_mode", ctypes.c_int32), ("stop_mode", ctypes.c_int32),
                 ("n_eq", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_fit", ctypes.c_int32),
                 ("n_f", ctypes.c_int32), ("n_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("sweep_kernel", ctypes.c_int32)]
 
 
 @dataclass
@@ -57,11 +59,12 @@ class SimConfig:
     scene_id: int = 0
     t_mode: int = T_BLOCK       # T_BLOCK: one temperature per block; T_SITE: one per site (SST)
     order: int = ORDER_SC       # ORDER_SC single checkerboard; ORDER_DC double checkerboard over the blocks
+    sweep_kernel: int = SWEEP_AUTO  # SWEEP_TILES / SWEEP_LANES force the sweep kernel (same chains either way)
 
     def to_c(self) -> mpr_sim_config:
         return mpr_sim_config(self.q, self.J, self.n_real, self.real_offset, self.init_mode, self.stop_mode,
                               self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id,
-                              self.t_mode, self.order)
+                              self.t_mode, self.order, self.sweep_kernel)
 
 
 def _check_T(T_blocks, H, W, lb_h, lb_w, cfg: "SimConfig"):

@@ -75,6 +75,17 @@ int64_t t_count(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_
 }
 int32_t t_lb(int32_t lb, const mpr_sim_config& c) { return c.t_mode == MPR_T_SITE ? 1 : lb; }
 
+// mpr_simulate runs the realization-lane sweep (state with the realization innermost, one realization per lane)
+// when the realizations fill the lanes of a wave (R >= 64) and the grid gives enough waves to fill the device,
+// in the single-checkerboard order, with sides below 2^16 (the temperature-column reciprocal is exact there).
+bool use_rl(int64_t H, int64_t W, const mpr_sim_config* cfg)
+{
+    if (!cfg || cfg->order != MPR_ORDER_SC || H >= 65536 || W >= 65536) return false;
+    if (cfg->sweep_kernel == MPR_SWEEP_LANES) return true;
+    if (cfg->sweep_kernel == MPR_SWEEP_TILES || cfg->n_real < 64) return false;
+    return mpr::rl_geometry(H, W, cfg->n_real).n_items >= mpr::kRlMinWaves;
+}
+
 // ---- workspace layouts (the same code computes the size and carves the pointers) ----
 struct MapWs {
     float *pmin, *pmax;
@@ -138,7 +149,9 @@ struct SimWs {
     long long* epart;   // [R][max(ntiles, nfull)]
     double* e_real;     // [R]
     double* series;     // [cap + 1]
-    float* alt;         // [R][H][W] second state buffer
+    float* alt;         // [R][H][W] second state buffer (fused sweep)
+    float* rl[2];       // [HW][Rp] state buffers of the realization-lane sweep
+    uint2* cells;       // its per-row window bits
 };
 size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, SimWs* w)
 {
@@ -152,11 +165,18 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
     const int nt = fused_tiles(H, W, (int)R);
     const int nfull = mpr::energy_full_parts(H, W);
-    x.epart = c.take<long long>((int64_t)(nt > nfull ? nt : nfull) * R);
+    const bool rl = use_rl(H, W, cfg);
+    const mpr::RlGeom rg = mpr::rl_geometry(H, W, (int)R);
+    int64_t np = nt > nfull ? nt : nfull;
+    if (rl && (int64_t)rg.nbands * rg.nseg > np) np = (int64_t)rg.nbands * rg.nseg;
+    x.epart = c.take<long long>(np * R);
     x.e_real = c.take<double>(R);
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
-    x.alt = c.take<float>(R * H * W);
+    x.alt = rl ? nullptr : c.take<float>(R * H * W);
+    x.rl[0] = rl ? c.take<float>(H * W * rg.Rp) : nullptr;
+    x.rl[1] = rl ? c.take<float>(H * W * rg.Rp) : nullptr;
+    x.cells = rl ? c.take<uint2>((H + 4) * rg.nbands) : nullptr;
     if (w) *w = x;
     return c.used;
 }
@@ -220,6 +240,10 @@ mpr_status check_sim_config(const mpr_sim_config& c)
     if (c.scene_id >= (1u << 28)) return fail(MPR_ERR_INVALID_ARG, "scene_id must be < 2^28");
     if (c.t_mode != MPR_T_BLOCK && c.t_mode != MPR_T_SITE) return fail(MPR_ERR_INVALID_ARG, "unknown t_mode %d", c.t_mode);
     if (c.order != MPR_ORDER_SC && c.order != MPR_ORDER_DC) return fail(MPR_ERR_INVALID_ARG, "unknown order %d", c.order);
+    if (c.sweep_kernel < MPR_SWEEP_AUTO || c.sweep_kernel > MPR_SWEEP_LANES)
+        return fail(MPR_ERR_INVALID_ARG, "unknown sweep_kernel %d", c.sweep_kernel);
+    if (c.sweep_kernel == MPR_SWEEP_LANES && c.order != MPR_ORDER_SC)
+        return fail(MPR_ERR_INVALID_ARG, "the realization-lane sweep runs the single-checkerboard order");
     return MPR_OK;
 }
 
@@ -643,6 +667,8 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 0) return fail(MPR_ERR_INVALID_ARG, "n_eq must be >= 0");
     if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
+    if (c.sweep_kernel == MPR_SWEEP_LANES && (H >= 65536 || W >= 65536))
+        return fail(MPR_ERR_SHAPE, "the realization-lane sweep needs sides below 65536");
     st = check_ws(workspace, ws_bytes, mpr_simulate_workspace_bytes(H, W, lb_h, lb_w, cfg));
     if (st != MPR_OK) return st;
 
@@ -715,7 +741,50 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     da.delta_e = mpr::kDeltaE * c.J;
     da.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
     da.Jd = (double)c.J;
+    // realization-lane sweep: the start moves into two [HW][Rp] buffers (both hold the samples), sweeps alternate
+    // between them, and the final state moves back into `state`
+    const bool rl = use_rl(H, W, cfg);
+    mpr::RlArgs ra{};
+    int rl_cur = 0;
+    if (rl) {
+        const mpr::RlGeom rg = mpr::rl_geometry(H, W, R);
+        ra.H = (int)H;
+        ra.W = (int)W;
+        ra.R = R;
+        ra.Rp = rg.Rp;
+        ra.Mw = (int)((W + 3) / 4);
+        ra.nbands = rg.nbands;
+        ra.nseg = rg.nseg;
+        ra.seg_rows = rg.seg_rows;
+        ra.n_items = rg.n_items;
+        ra.tb_h = t_lb(lb_h, c);
+        ra.tb_w = t_lb(lb_w, c);
+        ra.nbx_t = (int)((W + ra.tb_w - 1) / ra.tb_w);
+        ra.nby_t = (int)((H + ra.tb_h - 1) / ra.tb_h);
+        ra.tb_w_inv = ra.tb_w > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)ra.tb_w - 1) / (uint64_t)ra.tb_w) : 0u;
+        ra.real_offset = (uint32_t)c.real_offset;
+        ra.scene = c.scene_id;
+        ra.key0 = key0;
+        ra.key1 = key1;
+        ra.q = c.q;
+        ra.J = c.J;
+        ra.delta_e = mpr::kDeltaE * c.J;
+        ra.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+        ra.Jd = (double)c.J;
+        MPR_HIP(mpr::launch_rl_cells(mask, H, W, w.cells, s));
+        MPR_HIP(mpr::launch_rl_to_lanes(state, HW, R, w.rl[0], w.rl[1], s));
+    }
+    const int rl_parts = rl ? ra.nbands * ra.nseg : 0;
     auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
+        if (rl) {
+            ra.sweep = k;
+            hipError_t e = mpr::launch_sweep_rl(ra, w.cells, w.tp, w.rl[rl_cur], w.rl[rl_cur ^ 1],
+                                                energy ? w.epart : nullptr, s);
+            rl_cur ^= 1;
+            if (e == hipSuccess && energy)
+                e = mpr::launch_energy_reduce(w.epart, rl_parts, R, runner.inv_norm, w.e_real, w.series + k, s);
+            return e;
+        }
         if (!dc) return runner.run(k, energy ? w.series + k : nullptr);
         hipError_t e = mpr::launch_dc_sweep(da, k, s);
         if (e == hipSuccess && energy) e = mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s);
@@ -753,9 +822,12 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     }
     for (int32_t si = 1; si <= c.n_samp; ++si) {
         MPR_HIP(sweep((uint32_t)(k_star + si), false));
-        MPR_HIP(mpr::launch_accumulate(current(), mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
+        if (rl) MPR_HIP(mpr::launch_rl_accumulate(w.rl[rl_cur], mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
+        else MPR_HIP(mpr::launch_accumulate(current(), mask, HW, R, si == 1 ? 1 : 0, acc_out, s));
     }
-    if (current() != state) {
+    if (rl) {
+        MPR_HIP(mpr::launch_rl_from_lanes(w.rl[rl_cur], HW, R, state, s));
+    } else if (current() != state) {
         MPR_HIP(hipMemcpyAsync(state, current(), sizeof(float) * (size_t)(R * HW), hipMemcpyDeviceToDevice, s));
     }
     if (energy_out && need_energy) {

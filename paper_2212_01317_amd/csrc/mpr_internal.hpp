@@ -109,6 +109,41 @@ hipError_t launch_validate(const float* zhat, const float* truth, const uint8_t*
                            int nblocks, double* out, hipStream_t s);
 int validate_blocks(int64_t n);
 
+// Realization-lane sweep (rl_sweep.hip): single-checkerboard order, state layout [H W][Rp] with the realization
+// innermost (Rp = R rounded up to 64); a wave owns kRlBand columns x kRlSegRows rows of 64 realizations.
+constexpr int kRlBand = 12;
+constexpr int kRlSegRows = 256;        // longest row segment (rows are halved for small grids, down to 32)
+constexpr int64_t kRlTargetWaves = 8192; // segments are shortened until a sweep has this many waves
+constexpr int64_t kRlMinWaves = 2048;    // fewer waves than this: the fused tile sweep is used instead
+constexpr int kRlWaves = 2;      // waves per SIMD the kernel is compiled for
+struct RlGeom {
+    int Rp, nbands, nseg, seg_rows;
+    int64_t n_items;     // waves per sweep: nbands * nseg * Rp / 64
+};
+RlGeom rl_geometry(int64_t H, int64_t W, int R);
+struct RlArgs {
+    int H, W, R, Rp, Mw;
+    int nbands, nseg, seg_rows;
+    int64_t n_items;
+    int tb_h, tb_w, nbx_t, nby_t;   // temperature layout (blocks, or 1 x 1 per site)
+    uint32_t tb_w_inv;       // ceil(2^32 / tb_w) for tb_w > 1
+    uint32_t sweep, real_offset, scene, key0, key1;
+    float q, J, delta_e;
+    double two_pi_q, Jd;
+};
+// cells: [(H + 4) * nbands] uint2 (gap bits, sample bits of each wave's window columns, rows -2 .. H + 1)
+hipError_t launch_rl_cells(const uint8_t* mask, int64_t H, int64_t W, uint2* cells, hipStream_t s);
+// [R][HW] -> [HW][Rp] into out (and out2 if not null); pad realizations get 0
+hipError_t launch_rl_to_lanes(const float* in, int64_t HW, int R, float* out, float* out2, hipStream_t s);
+// [HW][Rp] -> [R][HW]
+hipError_t launch_rl_from_lanes(const float* in, int64_t HW, int R, float* out, hipStream_t s);
+hipError_t launch_rl_accumulate(const float* S, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
+                                hipStream_t s);
+// one sweep src -> dst; with epart set, the fixed-point energy of each wave's colour-1 sites goes to
+// epart[r][seg * nbands + band] (layout [R][nbands * nseg])
+hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const float* src, float* dst,
+                           long long* epart, hipStream_t s);
+
 // Sec. 2.2.2 double-checkerboard sweep (dc.hip): four in-place phases per sweep over all realizations.
 struct DcArgs {
     float* state;        // [R][H][W], updated in place

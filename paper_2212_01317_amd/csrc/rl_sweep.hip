@@ -1,0 +1,539 @@
+// Realization-lane sweep: the single-checkerboard Metropolis sweep of Sec. 2.2.2 (block or site temperatures) for
+// runs with many realizations, in a state layout with the realization innermost.
+//
+// Layout: S[g][n][l], n = y W + x, realization r = 64 g + l (R rounded up to a multiple of 64).  Lane l of a wave
+// is realization 64 g + l, so the 64 lanes update the same site in 64 realizations, and the 256 bytes of a site are
+// 256 bytes from those of the next site in the row: whether a site is a sample, its temperature, its random-stream
+// counter and its neighbourhood are the same for the whole wave.  They are scalar data, decided by the scalar
+// unit, and no lane idles on a sample site.
+//
+// A wave owns a band of 16 columns [x0, x0 + 16) and a segment of rows [ys, ye) of one group of 64 realizations,
+// and streams the rows downwards with a window of four rows in registers (angle, cos, sin of each site of columns
+// x0 - 2 .. x0 + 17).  Step y updates colour 0 of row y and then colour 1 of row y - 1, whose colour-0 neighbours
+// (rows y - 2 .. y) are then current, and writes row y - 1.  Colour 0 is also updated one site outside the band
+// (columns x0 - 1, x0 + 16) and one row outside the segment (rows ys - 1, ye): these updates use the same
+// counter-based random numbers and the same inputs as in the wave that owns the site, so they are bit-identical to
+// it, and the two columns beyond (x0 - 2, x0 + 17) are read only.  Sweep k reads `src` and writes `dst`.
+//
+// The update, the decision (FP32 filter, exact FP64 test inside its error band), the random numbers and the
+// fixed-point energy of each colour-1 site are those of the fused sweep, so the chains, the energy series and the
+// stopping sweep are identical.
+#include <hip/hip_runtime.h>
+
+#include "metropolis.hpp"
+#include "mpr_internal.hpp"
+
+namespace mpr {
+
+namespace {
+
+
+__device__ __forceinline__ int fix24(float x) { return __float2int_rn(x * 16777216.0f); }
+
+// Philox4x32-10 when only c2 differs between lanes: the uniform halves of the first three rounds stay on the
+// scalar unit; the remaining rounds use the three-input xor.
+__device__ __forceinline__ U4 philox_rl(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    // keep the key schedule as per-call scalar adds instead of twenty loop-invariant registers
+    asm volatile("" : "+s"(k0), "+s"(k1));
+#pragma unroll
+    for (int round = 0; round < 3; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+#pragma unroll
+    for (int round = 3; round < 10; ++round) {
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+template <int KB, bool ALIGNED, bool ENERGY>
+struct RlWave {
+    static constexpr int kB = KB;          // columns owned by the wave
+    static constexpr int kWC = KB + 4;     // window columns x0 - 2 .. x0 + KB + 1
+    static constexpr uint32_t kAll = (1u << kWC) - 1u;
+    RlArgs a;
+    const uint2* __restrict__ cells;   // [(H + 4) * nbands]: row y + 2 -> {gap bits, sample bits} of the window
+    const TBand* __restrict__ tb;
+    const char* src;                   // this wave's group of realizations in the two state buffers
+    char* dst;
+    int band, x0, ys, ye, lane;
+    uint32_t real;                     // global realization index of this lane
+    uint32_t lane4;                    // byte offset of this lane inside a site's 64 realizations
+    int64_t offy;                      // byte offset of (row y of the current step, window column 0) in the group
+    int64_t wrow;                      // bytes per grid row: W * 256
+    // window of (cos, sin), slot = row & 3
+    float c[4][kWC], s[4][kWC];
+    uint32_t gap[4], smp[4];           // per slot: gap / sample bits of the window columns
+    float pf[kWC];                     // angles of the next row, requested one step ahead
+    float to0[kWC], to1[kWC];          // old angles of the cells updated in the step (colour 0 of row y, colour 1
+                                       // of row y - 1), loaded at its start
+    uint32_t pgap, psmp;
+    int brow, brem;                    // temperature row of the step's row y, and y - brow tb_h
+    const TBand* trow0;                // temperature rows of y and y - 1 (clamped into the grid)
+    const TBand* trow1;
+    int bc, bcl, bcr;                  // ALIGNED: temperature columns of the owned columns and of the two ring columns
+    long long e_acc;
+
+    // the lane's element of window column j of the row at byte offset off (wave-uniform base + lane offset + an
+    // immediate j * 256)
+    __device__ __forceinline__ float ld(const char* b, int64_t off, int j) const
+    {
+        return *reinterpret_cast<const float*>(b + off + j * 256 + lane4);
+    }
+    __device__ __forceinline__ void st(int64_t off, int j, float v) const
+    {
+        *reinterpret_cast<float*>(dst + off + j * 256 + lane4) = v;
+    }
+    // the same load through the device-coherent path (values this wave stored earlier in the launch)
+    __device__ __forceinline__ float ld_coherent(const char* b, int64_t off, int j) const
+    {
+        return __hip_atomic_load(reinterpret_cast<const float*>(b + off + j * 256 + lane4), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // temperature column of window column j (clamped into the grid), by the reciprocal tb_w_inv = ceil(2^32 / tb_w)
+    __device__ __forceinline__ int bcol(int j) const
+    {
+        int x = x0 - 2 + j;
+        x = x < 0 ? 0 : (x >= a.W ? a.W - 1 : x);
+        return a.tb_w == 1 ? x : (int)__umulhi((uint32_t)x, a.tb_w_inv);
+    }
+
+    __device__ __forceinline__ uint2 row_bits(int y) const
+    {
+        return cells[(int64_t)(y + 2) * a.nbands + band];
+    }
+
+    // Requests the angles of the cells of row y that lie inside the grid (gap and sample cells alike: both state
+    // buffers hold the sample angles).
+    __device__ __forceinline__ void request(int y, int64_t off)
+    {
+        const uint2 b = row_bits(y);
+        pgap = b.x;
+        psmp = b.y;
+        const uint32_t in = pgap | psmp;
+        if (in == kAll) {
+#pragma unroll
+            for (int j = 0; j < kWC; ++j) pf[j] = ld(src, off, j);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWC; ++j)
+                if ((in >> j) & 1u) pf[j] = ld(src, off, j);
+        }
+    }
+
+    // Row y enters slot S: (cos, sin) of the requested angles; cells outside the grid get (0, 0).
+    template <int S>
+    __device__ __forceinline__ void arrive()
+    {
+        gap[S] = pgap;
+        smp[S] = psmp;
+        const uint32_t in = pgap | psmp;
+        if (in == kAll) {
+#pragma unroll
+            for (int j = 0; j < kWC; ++j) {
+                const float ang = a.q * pf[j];
+                c[S][j] = cos_rev(ang);
+                s[S][j] = sin_rev(ang);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWC; ++j) {
+                if ((in >> j) & 1u) {
+                    const float ang = a.q * pf[j];
+                    c[S][j] = cos_rev(ang);
+                    s[S][j] = sin_rev(ang);
+                } else {
+                    c[S][j] = 0.0f;
+                    s[S][j] = 0.0f;
+                }
+            }
+        }
+    }
+
+    // Metropolis update of the gap cell at window column j of row y (slot SO; neighbours in slots SU above and SD
+    // below), old angle `to`; writes the cell's angle after the update to dst.  COL = colour of the cell: colour-0
+    // neighbours are read back from dst (this wave wrote them), colour-1 neighbours from src, on the exact path.
+    // Returns the fixed-point energy / J of the site's bonds after the update.
+    template <int COL, int SO, int SU, int SD>
+    __device__ __forceinline__ int update(const TBand& T, int y, int64_t off, int j, float to, uint32_t wp,
+                                          uint32_t wa)
+    {
+        const float Cx = ((c[SU][j] + c[SO][j - 1]) + c[SO][j + 1]) + c[SD][j];
+        const float Sy = ((s[SU][j] + s[SO][j - 1]) + s[SO][j + 1]) + s[SD][j];
+        const float tp = u24(wp);
+        const float ui = (float)(wa >> 8);
+        const float ang = a.q * tp;
+        const float cp = cos_rev(ang), sp = sin_rev(ang);
+        const float co = c[SO][j], so = s[SO][j];
+        const float X = fmaf(cp - co, Cx, (sp - so) * Sy);
+        // The FP32 filter with a wave-uniform temperature, as one comparison of (lhs, rhs) with a tolerance: accept
+        // iff lhs < rhs, exact FP64 test iff |lhs - rhs| <= tol.  T > 0: (ui, w24, the error band of w24);
+        // T = 0: (dE, 0, delta), where dE < 0 and dE <= 0 differ only at dE = 0, which lies inside the band.
+        float lhs, rhs, tol;
+        if (T.T > 0.0f) {
+            const float w24 = exp2_fast(fminf(fmaf(X, T.kappa, 24.0f), 25.0f));
+            lhs = ui;
+            rhs = w24;
+            tol = fmaf(w24, fmaf(fabsf(X), T.kb, T.band), 0.015625f);
+        } else {
+            lhs = -a.J * X;
+            rhs = 0.0f;
+            tol = a.delta_e;
+        }
+        const bool acc = lhs < rhs;
+        float tn = acc ? tp : to;
+        float cf = acc ? cp : co, sf = acc ? sp : so;
+        if (fabsf(lhs - rhs) <= tol) {
+            // rare: the exact decision from the neighbours' angles; an absent neighbour reads the cell itself
+            // (in the grid) and is excluded by `pres`
+            const int x = x0 - 2 + j;
+            const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
+            const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
+            const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
+            float nu, nl, nr, nd;
+            if (COL == 0) {
+                nu = ld(src, ou, j);
+                nl = ld(src, off, jl);
+                nr = ld(src, off, jr);
+                nd = ld(src, od, j);
+            } else {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                nu = ld_coherent(dst, ou, j);
+                nl = ld_coherent(dst, off, jl);
+                nr = ld_coherent(dst, off, jr);
+                nd = ld_coherent(dst, od, j);
+            }
+            const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
+            const bool ex = exact64(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.T, ui * 5.9604644775390625e-8f);
+            tn = ex ? tp : to;
+            cf = ex ? cp : co;
+            sf = ex ? sp : so;
+        }
+        c[SO][j] = cf;
+        s[SO][j] = sf;
+        st(off, j, tn);
+        return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
+    }
+
+    __device__ __forceinline__ TBand tband(const TBand* trow, int j) const
+    {
+        if (ALIGNED) return trow[j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)];
+        return trow[bcol(j)];
+    }
+
+    // Colour COL of the row in slot SO (grid row y): the pairs of groups m0 + MLO .. m0 + MHI, sites restricted to
+    // window columns [JLO, JHI).  PAR = (y + COL) & 1, the column offset of the colour inside a group of four.
+    template <int COL, int PAR, int SO, int SU, int SD, int MLO, int MHI, int JLO, int JHI>
+    __device__ __forceinline__ int colour(const TBand* trow, int y, int64_t off, const float* to)
+    {
+        const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COL);
+        const uint32_t base = (uint32_t)y * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
+        int e = 0;
+#pragma unroll
+        for (int m = MLO; m <= MHI; ++m) {
+            const int j0 = 4 * m + 2 + PAR, j1 = j0 + 2;
+            const bool in0 = j0 >= JLO && j0 < JHI, in1 = j1 >= JLO && j1 < JHI;
+            const int k0 = in0 ? j0 : JLO, k1 = in1 ? j1 : JLO;
+            const bool g0 = in0 && ((gap[SO] >> k0) & 1u);
+            const bool g1 = in1 && ((gap[SO] >> k1) & 1u);
+            if (!(g0 || g1)) continue;
+            // old angles of the pair (a cell outside the grid reads its in-grid partner instead)
+            const TBand T0 = tband(trow, k0), T1 = tband(trow, k1);
+            const U4 w = philox_rl(base + (uint32_t)m, a.sweep, real, w3, a.key0, a.key1);
+            if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, to[k0], w.x, w.y);
+            if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, to[k1], w.z, w.w);
+        }
+        return e;
+    }
+
+    // Old angles of the gap cells of one colour of a row (columns PAR, PAR + 2, ... in [JLO, JHI)): all of them
+    // when the row lies inside the grid, else the gap cells only.
+    template <int PAR, int JLO, int JHI>
+    __device__ __forceinline__ void old_angles(uint32_t g, uint32_t sm, int64_t off, float* to) const
+    {
+        if ((g | sm) == kAll) {
+#pragma unroll
+            for (int j = JLO + ((JLO + PAR) & 1); j < JHI; j += 2) to[j] = ld(src, off, j);
+        } else {
+#pragma unroll
+            for (int j = JLO + ((JLO + PAR) & 1); j < JHI; j += 2)
+                if ((g >> j) & 1u) to[j] = ld(src, off, j);
+        }
+    }
+
+    // Energy / J (fixed point) of the bonds of the colour-1 sample cells of the row in slot SO among the owned
+    // columns (the gap cells' energies come from their updates).
+    template <int PAR, int SO, int SU, int SD>
+    __device__ __forceinline__ int sample_energy()
+    {
+        int e = 0;
+#pragma unroll
+        for (int k = 0; k < kB / 2; ++k) {
+            const int j = 2 + 2 * k + PAR;
+            if (!((smp[SO] >> j) & 1u)) continue;
+            const float Cx = ((c[SU][j] + c[SO][j - 1]) + c[SO][j + 1]) + c[SD][j];
+            const float Sy = ((s[SU][j] + s[SO][j - 1]) + s[SO][j + 1]) + s[SD][j];
+            e += fix24(-fmaf(c[SO][j], Cx, s[SO][j] * Sy));
+        }
+        return e;
+    }
+
+    // One step (P = y & 3): row y + 1 arrives, row y + 2 is requested, colour 0 of row y, colour 1 of row y - 1.
+    template <int P>
+    __device__ __forceinline__ void step(int y)
+    {
+        constexpr int S0 = P, SU = (P + 3) & 3, SD = (P + 1) & 3, S2 = (P + 2) & 3;
+        // temperature rows: trow1 <- row y - 1, trow0 <- row y
+        trow1 = trow0;
+        if (++brem == a.tb_h) {
+            brem = 0;
+            ++brow;
+        }
+        trow0 = tb + (int64_t)(brow < 0 ? 0 : (brow >= a.nby_t ? a.nby_t - 1 : brow)) * a.nbx_t;
+        offy += wrow;
+        // row parity: y & 1 = P & 1, so colour 0 of row y and colour 1 of row y - 1 have column offset P & 1.
+        // The old angles of this step's cells are requested before the next row, so that waiting for them does
+        // not wait for the next row's loads.
+        const int y1 = y - 1;
+        const bool do0 = y >= 0 && y < a.H, do1 = y1 >= ys && y1 < ye;
+        if (do0) old_angles<P & 1, 1, kWC - 1>(gap[S0], smp[S0], offy, to0);
+        if (do1) old_angles<P & 1, 2, kWC - 2>(gap[SU], smp[SU], offy - wrow, to1);
+        arrive<SD>();
+        if (y + 2 <= ye + 1) request(y + 2, offy + 2 * wrow);
+        else pgap = psmp = 0u;
+        if (do0) colour<0, P & 1, S0, SU, SD, -1, kB / 4, 1, kWC - 1>(trow0, y, offy, to0);
+        if (do1) {
+            int e = colour<1, P & 1, SU, S2, S0, 0, kB / 4 - 1, 2, kWC - 2>(trow1, y1, offy - wrow, to1);
+            if (ENERGY) e += sample_energy<P & 1, SU, S2, S0>();
+            e_acc += e;
+        }
+    }
+
+    __device__ __forceinline__ void run()
+    {
+        e_acc = 0;
+        if (ALIGNED) {
+            bc = x0 / a.tb_w;
+            bcl = x0 % a.tb_w == 0 && bc > 0 ? bc - 1 : bc;
+            bcr = (x0 + kB) % a.tb_w == 0 && bc + 1 < a.nbx_t ? bc + 1 : bc;
+        }
+        // the first step is y = ys - 1 (>= -1): start the temperature row one row above it
+        brow = (ys - 2 + a.tb_h) / a.tb_h - 1;
+        brem = (ys - 2 + a.tb_h) % a.tb_h;
+        trow0 = tb;
+        wrow = (int64_t)a.W * 256;
+        offy = ((int64_t)(ys - 2) * a.W + (x0 - 2)) * 256;   // row ys - 2; the first step moves it to ys - 1
+        // rows ys - 2 and ys - 1 into their slots (ys is a multiple of 4: slots 2 and 3), row ys requested
+        request(ys - 2, offy);
+        arrive<2>();
+        request(ys - 1, offy + wrow);
+        arrive<3>();
+        request(ys, offy + 2 * wrow);
+        for (int yb = ys - 1; yb <= ye; yb += 4) {
+            step<3>(yb);
+            if (yb + 1 > ye) break;
+            step<0>(yb + 1);
+            if (yb + 2 > ye) break;
+            step<1>(yb + 2);
+            if (yb + 3 > ye) break;
+            step<2>(yb + 3);
+        }
+    }
+};
+
+template <bool ALIGNED, bool ENERGY>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kRlWaves))) void k_sweep_rl(
+    RlArgs a, const uint2* __restrict__ cells, const TBand* __restrict__ tb, const float* __restrict__ src,
+    float* __restrict__ dst, long long* __restrict__ epart)
+{
+    // XCD-aware order: workgroup g runs on XCD g % 8; consecutive items (adjacent bands) go to the same XCD.
+    const uint32_t N = a.n_items;
+    const uint32_t g = blockIdx.x, xcd = g & 7u, k = g >> 3;
+    const uint32_t per = N >> 3, rem = N & 7u;
+    const uint32_t item = xcd < rem ? xcd * (per + 1u) + k : rem * (per + 1u) + (xcd - rem) * per + k;
+    if (item >= N) return;
+    const int64_t group = (int64_t)(item / ((uint32_t)a.nbands * (uint32_t)a.nseg)) * ((int64_t)a.H * a.W * 256);
+    RlWave<kRlBand, ALIGNED, ENERGY> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
+                                       reinterpret_cast<char*>(dst) + group};
+    w.band = (int)(item % (uint32_t)a.nbands);
+    const uint32_t rest = item / (uint32_t)a.nbands;
+    const int seg = (int)(rest % (uint32_t)a.nseg);
+    const int rg = (int)(rest / (uint32_t)a.nseg);
+    w.lane = (int)(rg * 64 + threadIdx.x);
+    w.lane4 = threadIdx.x * 4u;
+    w.real = a.real_offset + (uint32_t)w.lane;
+    w.x0 = w.band * kRlBand;
+    w.ys = seg * a.seg_rows;
+    w.ye = w.ys + a.seg_rows < a.H ? w.ys + a.seg_rows : a.H;
+    w.run();
+    if (ENERGY && w.lane < a.R) epart[(int64_t)w.lane * (a.nbands * a.nseg) + seg * a.nbands + w.band] = w.e_acc;
+}
+
+// cells[(y + 2) * nbands + band] for y in [-2, H + 2): bit j of .x = (y, x0 - 2 + j) is a gap of the grid, of .y =
+// it is a sample.
+__global__ __launch_bounds__(256) void k_rl_cells(const uint8_t* __restrict__ mask, int H, int W, int nbands,
+                                                   uint2* __restrict__ cells)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)(H + 4) * nbands;
+    if (i >= total) return;
+    const int y = (int)(i / nbands) - 2, band = (int)(i % nbands);
+    uint32_t gb = 0u, sb = 0u;
+    if (y >= 0 && y < H) {
+        for (int j = 0; j < kRlBand + 4; ++j) {
+            const int x = band * kRlBand - 2 + j;
+            if (x < 0 || x >= W) continue;
+            if (mask[(int64_t)y * W + x]) sb |= 1u << j;
+            else gb |= 1u << j;
+        }
+    }
+    cells[i] = make_uint2(gb, sb);
+}
+
+// [R][HW] -> [G][HW][64] (pad realizations get 0) into one or two buffers, 64 sites x 64 realizations per
+// workgroup through LDS.
+__global__ __launch_bounds__(256) void k_rl_to_lanes(const float* __restrict__ in, int64_t HW, int R,
+                                                      float* __restrict__ out, float* __restrict__ out2)
+{
+    __shared__ float tile[64][65];
+    const int64_t n0 = (int64_t)blockIdx.x * 64;
+    const int g = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = g * 64 + i;
+        const int64_t n = n0 + tx;
+        tile[i][tx] = (r < R && n < HW) ? in[(int64_t)r * HW + n] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t n = n0 + i;
+        if (n < HW) {
+            const int64_t o = ((int64_t)g * HW + n) * 64 + tx;
+            out[o] = tile[tx][i];
+            if (out2) out2[o] = tile[tx][i];
+        }
+    }
+}
+
+// [G][HW][64] -> [R][HW]
+__global__ __launch_bounds__(256) void k_rl_from_lanes(const float* __restrict__ in, int64_t HW, int R,
+                                                        float* __restrict__ out)
+{
+    __shared__ float tile[64][65];
+    const int64_t n0 = (int64_t)blockIdx.x * 64;
+    const int g = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t n = n0 + i;
+        tile[i][tx] = n < HW ? in[((int64_t)g * HW + n) * 64 + tx] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int r = g * 64 + i;
+        const int64_t n = n0 + tx;
+        if (r < R && n < HW) out[(int64_t)r * HW + n] = tile[tx][i];
+    }
+}
+
+// acc[n] += sum over realizations (in order) of the gap angle; the first pass starts from 0.
+__global__ __launch_bounds__(256) void k_rl_accumulate(const float* __restrict__ S, const uint8_t* __restrict__ mask,
+                                                        int64_t HW, int R, int first, double* __restrict__ acc)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= HW) return;
+    if (mask[n]) {
+        if (first) acc[n] = 0.0;
+        return;
+    }
+    double v = first ? 0.0 : acc[n];
+    for (int r = 0; r < R; ++r) v += (double)S[((int64_t)(r >> 6) * HW + n) * 64 + (r & 63)];
+    acc[n] = v;
+}
+
+}  // namespace
+
+RlGeom rl_geometry(int64_t H, int64_t W, int R)
+{
+    RlGeom g;
+    g.Rp = (R + 63) / 64 * 64;
+    g.nbands = (int)((W + kRlBand - 1) / kRlBand);
+    // row segments of kRlSegRows rows, halved (down to 32) while the grid has fewer than kRlTargetWaves waves:
+    // each segment adds two ring rows of colour-0 updates
+    const int64_t groups = g.Rp / 64;
+    g.seg_rows = kRlSegRows;
+    while (g.seg_rows > 32 && (int64_t)g.nbands * ((H + g.seg_rows - 1) / g.seg_rows) * groups < kRlTargetWaves)
+        g.seg_rows /= 2;
+    g.nseg = (int)((H + g.seg_rows - 1) / g.seg_rows);
+    g.n_items = (int64_t)g.nbands * g.nseg * groups;
+    return g;
+}
+
+hipError_t launch_rl_cells(const uint8_t* mask, int64_t H, int64_t W, uint2* cells, hipStream_t s)
+{
+    const RlGeom g = rl_geometry(H, W, 64);
+    const int64_t total = (H + 4) * (int64_t)g.nbands;
+    hipLaunchKernelGGL(k_rl_cells, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, mask, (int)H, (int)W,
+                       g.nbands, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_rl_to_lanes(const float* in, int64_t HW, int R, float* out, float* out2, hipStream_t s)
+{
+    const int Rp = (R + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_rl_to_lanes, dim3((unsigned)((HW + 63) / 64), (unsigned)(Rp / 64)), dim3(256), 0, s, in,
+                       HW, R, out, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_rl_from_lanes(const float* in, int64_t HW, int R, float* out, hipStream_t s)
+{
+    const int Rp = (R + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_rl_from_lanes, dim3((unsigned)((HW + 63) / 64), (unsigned)(Rp / 64)), dim3(256), 0, s, in,
+                       HW, R, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rl_accumulate(const float* S, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rl_accumulate, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, S, mask, HW, R, first,
+                       acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const float* src, float* dst,
+                           long long* epart, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const bool aligned = a.tb_w % kRlBand == 0;
+    const dim3 grid((unsigned)a.n_items);
+    if (aligned && epart) hipLaunchKernelGGL((k_sweep_rl<true, true>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
+    else if (aligned) hipLaunchKernelGGL((k_sweep_rl<true, false>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
+    else if (epart) hipLaunchKernelGGL((k_sweep_rl<false, true>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
+    else hipLaunchKernelGGL((k_sweep_rl<false, false>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
+    return hipGetLastError();
+}
+
+}  // namespace mpr

@@ -1,0 +1,136 @@
+"""The realization-lane sweep (sweep_kernel = LANES: one realization per lane, state with the realization innermost)
+against the oracle and against the tile sweep (TILES): the same chains bit for bit, the same energy series and
+stopping sweep, on grids with ragged bands, several and ragged row segments, temperature blocks that straddle the
+bands or line up with them, per-site temperatures, zero-temperature blocks, groups of realizations with idle lanes,
+and the automatic choice at the 4096^2 headline shape."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import SimConfig as OCfg
+from paper_2212_01317_amd import _lib as M
+from paper_2212_01317_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _temps(H, W, lb, seed, zero=False):
+    nb = ((H + lb[0] - 1) // lb[0], (W + lb[1] - 1) // lb[1])
+    T = np.random.default_rng(seed).uniform(0.02, 0.4, nb).astype(np.float32)
+    if zero:
+        T.ravel()[::3] = 0.0
+    return T
+
+
+def _run_both(sc, T, lb, oc, cfg):
+    t, rg = oracle.map_angles(sc.z_obs, sc.mask)
+    o = oracle.simulate(t, sc.mask, T, *lb, oc)
+    g = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb, cfg)
+    return t, rg, o, g
+
+
+@pytest.mark.parametrize("H,W,lb,R,p,zero", [
+    (300, 52, (16, 12), 70, 0.6, False),     # ten row segments (the last ragged), ragged band, ragged lanes
+    (40, 37, (8, 8), 64, 0.5, True),         # zero-temperature blocks
+    (70, 50, (24, 24), 20, 0.55, False),     # blocks lined up with the bands, 44 idle lanes
+    (9, 1, (4, 1), 64, 0.5, False),          # one column
+    (1, 29, (1, 5), 65, 0.4, False),         # one row
+    (3, 5, (3, 5), 64, 0.7, False),          # one block smaller than a band
+])
+def test_rl_fixed_matches_oracle(H, W, lb, R, p, zero):
+    sc = synth.random_small(H, W, p, seed=H * 31 + W)
+    T = _temps(H, W, lb, seed=H + W, zero=zero)
+    oc = OCfg(n_real=R, init_mode=1, stop_mode=0, n_eq=6, n_samp=2, seed=21)
+    cfg = M.SimConfig(n_real=R, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=6, n_samp=2, seed=21,
+                      sweep_kernel=M.SWEEP_LANES)
+    print(f"[rl] fixed H={H} W={W} lb={lb} R={R}", flush=True)
+    _, _, o, g = _run_both(sc, T, lb, oc, cfg)
+    assert g.sweeps == o.k_star
+    assert np.array_equal(host(g.state), o.state)
+    assert np.array_equal(host(g.acc), o.acc)
+    assert np.allclose(host(g.energy), o.energy, rtol=0, atol=1e-5)
+
+
+def test_rl_auto_matches_oracle():
+    sc = synth.random_small(45, 70, 0.55, seed=7)
+    lb = (16, 16)
+    T = _temps(45, 70, lb, seed=5)
+    oc = OCfg(n_real=64, init_mode=0, stop_mode=1, n_samp=1, n_max=150, seed=4)
+    cfg = M.SimConfig(n_real=64, init_mode=M.INIT_RANDOM, stop_mode=M.STOP_AUTO, n_samp=1, n_max=150, seed=4,
+                      sweep_kernel=M.SWEEP_LANES)
+    print("[rl] auto 45x70 R=64", flush=True)
+    t, rg, o, g = _run_both(sc, T, lb, oc, cfg)
+    assert g.sweeps == o.k_star
+    assert np.array_equal(host(g.state), o.state)
+    assert np.array_equal(host(g.acc), o.acc)
+    assert np.allclose(host(g.energy), o.energy, rtol=0, atol=1e-5)
+    n = cfg.n_real * cfg.n_samp
+    zo = oracle.predict(o.acc, sc.z_obs, sc.mask, n, rg)
+    zg = host(M.mpr_predict(g.acc, dev(sc.z_obs), dev(sc.mask), n, dev(rg)))
+    assert np.array_equal(zg, zo)
+
+
+def test_rl_site_temperatures_match_oracle():
+    sc = synth.random_small(37, 45, 0.6, seed=17)
+    lb = (8, 8)
+    T = _temps(37, 45, lb, seed=2)
+    Ts = oracle.sst_temperatures(T, 37, 45, *lb, r_s=1, n_s=3)
+    oc = OCfg(n_real=64, init_mode=1, stop_mode=0, n_eq=8, n_samp=1, seed=8, t_mode=1)
+    cfg = M.SimConfig(n_real=64, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=8, n_samp=1, seed=8,
+                      t_mode=M.T_SITE, sweep_kernel=M.SWEEP_LANES)
+    print("[rl] site temperatures 37x45 R=64", flush=True)
+    _, _, o, g = _run_both(sc, Ts, lb, oc, cfg)
+    assert np.array_equal(host(g.state), o.state)
+    assert np.array_equal(host(g.acc), o.acc)
+
+
+def test_rl_matches_fused_sweep():
+    """The two kernels run the same chains: R = 72 with LANES equals R = 72 with TILES bit for bit (states, sums,
+    energy series), and realizations 40..71 alone (real_offset = 40) equal the last 32 of either."""
+    H, W, lb = 130, 100, (32, 32)
+    sc = synth.random_small(H, W, 0.6, seed=3)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T = _temps(H, W, lb, seed=9)
+    base = dict(init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=12, n_samp=2, seed=77)
+    print("[rl] lanes vs tiles 130x100", flush=True)
+    lanes = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb, M.SimConfig(n_real=72, sweep_kernel=M.SWEEP_LANES, **base))
+    tiles = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb, M.SimConfig(n_real=72, sweep_kernel=M.SWEEP_TILES, **base))
+    part = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb,
+                          M.SimConfig(n_real=32, real_offset=40, sweep_kernel=M.SWEEP_LANES, **base))
+    s = host(lanes.state)
+    assert np.array_equal(s, host(tiles.state))
+    assert np.array_equal(host(lanes.acc), host(tiles.acc))
+    assert np.array_equal(host(lanes.energy), host(tiles.energy))
+    assert np.array_equal(s[40:], host(part.state))
+
+
+def test_auto_choice_and_errors():
+    """AUTO takes the realization-lane sweep at the 4096^2, R = 256 headline shape and the tile sweep where the grid
+    gives too few waves; LANES is refused with the double-checkerboard order."""
+    L = M.lib()
+    import ctypes
+    big = M.SimConfig(n_real=256, stop_mode=M.STOP_FIXED, n_eq=1).to_c()
+    lanes_ws = L.mpr_simulate_workspace_bytes(4096, 4096, 32, 32, ctypes.byref(big))
+    tiles = M.SimConfig(n_real=256, stop_mode=M.STOP_FIXED, n_eq=1, sweep_kernel=M.SWEEP_TILES).to_c()
+    tiles_ws = L.mpr_simulate_workspace_bytes(4096, 4096, 32, 32, ctypes.byref(tiles))
+    assert lanes_ws != tiles_ws              # the two kernels carve different state buffers
+    small_auto = M.SimConfig(n_real=64, stop_mode=M.STOP_FIXED, n_eq=1).to_c()
+    small_tiles = M.SimConfig(n_real=64, stop_mode=M.STOP_FIXED, n_eq=1, sweep_kernel=M.SWEEP_TILES).to_c()
+    assert (L.mpr_simulate_workspace_bytes(128, 128, 16, 16, ctypes.byref(small_auto))
+            == L.mpr_simulate_workspace_bytes(128, 128, 16, 16, ctypes.byref(small_tiles)))
+    sc = synth.random_small(20, 24, 0.5, seed=1)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T = _temps(20, 24, (8, 8), seed=1)
+    with pytest.raises(M.MprError):
+        M.mpr_simulate(dev(t), dev(sc.mask), dev(T), 8, 8,
+                       M.SimConfig(n_real=64, order=M.ORDER_DC, sweep_kernel=M.SWEEP_LANES))
