@@ -57,7 +57,13 @@ SWEEP_SOURCES = {
 }
 
 
-def sweep_kernel(R: int) -> str:
+def sweep_kernel(R: int, choice: str = "auto") -> str:
+    """The kernel mpr_simulate sweeps with (at the 4096^2 workload the automatic choice is the realization-lane
+    kernel exactly when R >= 64)."""
+    if choice == "tiles":
+        return "k_sweep_fused"
+    if choice == "lanes":
+        return "k_sweep_rl"
     return "k_sweep_rl" if R >= 64 else "k_sweep_fused"
 
 
@@ -107,6 +113,8 @@ def parse():
     ap.add_argument("--profile-sweeps", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and gradient measurements")
     ap.add_argument("--batch-scenes", type=int, default=256)
+    ap.add_argument("--sweep-kernel", choices=("auto", "tiles", "lanes"), default="auto",
+                    help="sweep kernel of the simulation (auto: the library's choice)")
     return ap.parse_args()
 
 
@@ -148,10 +156,11 @@ def main():
     evm = torch.from_numpy(sc.eval_mask).to(dev)
     n_gap = int((sc.mask == 0).sum())
     state = torch.empty((R, L, L), dtype=torch.float32, device=dev)
+    kchoice = {"auto": mpr.SWEEP_AUTO, "tiles": mpr.SWEEP_TILES, "lanes": mpr.SWEEP_LANES}[args.sweep_kernel]
     cfg = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_AUTO, n_samp=1, n_fit=20,
-                        n_f=5, n_max=1000, seed=synth.seed_for(3, synth.ROLE_PHILOX))
+                        n_f=5, n_max=1000, seed=synth.seed_for(3, synth.ROLE_PHILOX), sweep_kernel=kchoice)
     fixed = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=0, n_samp=0,
-                          seed=cfg.seed)
+                          seed=cfg.seed, sweep_kernel=kchoice)
 
     if args.profile_sweeps > 0:
         # counter runs: a small matching curve (T values do not change the traffic), the start, an even number of
@@ -204,7 +213,7 @@ def main():
     # of the sweep, as under the automatic stop).  HIP events on the stream the library launches on (torch's
     # current stream) bracket two fixed-length simulations of the same start, n1 and n1 + ns sweeps; their
     # difference is ns sweeps, each one sweep launch plus the two small launches that reduce its energy.
-    kernel = sweep_kernel(R)
+    kernel = sweep_kernel(R, args.sweep_kernel)
     ns = args.roofline_sweeps
     n1 = 4
 
@@ -251,6 +260,7 @@ def main():
                                f"32x32 T-blocks, {R} realizations, automatic equilibrium test (n_fit=20, n_f=5), "
                                f"1 sampling sweep; step = map+calibrate+simulate+predict+validate",
                    "H": L, "W": L, "p": args.p, "gap_sites": n_gap, "n_real": R, "block": list(lb),
+                   "sweep_kernel": kernel,
                    "sweeps_per_step": sweeps},
         "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
