@@ -83,8 +83,14 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_stop_check.argtypes = [_f64p, _i32, _i32, _i32]
     L.orc_stop_check.restype = ctypes.c_int
     L.orc_simulate.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _i32, _i32, _i32, _i32,
-                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _i32, _f32p, _f64p, _f64p,
+                               _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _i32, _i32, _f32p, _f64p, _f64p,
                                ctypes.POINTER(_i32)]
+    L.orc_block_stats_directional.argtypes = [_f32p, _u8p, _i64, _i64, _i32, _i32, _flt, _flt, _f64p, _i32p, _f64p,
+                                              _i32p]
+    L.orc_block_stats_directional.restype = None
+    L.orc_sweep_directional.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _u64, _u32, _u32,
+                                        _u32]
+    L.orc_sweep_directional.restype = None
     L.orc_simulate.restype = _i32
     L.orc_sst_temperatures.argtypes = [_f32p, _i64, _i64, _i32, _i32, _i32, _i32, _f32p]
     L.orc_sst_temperatures.restype = None
@@ -153,6 +159,44 @@ def block_stats(t, mask, lb_h, lb_w, q=0.5, J=1.0):
     No = np.zeros(B, np.int32)
     lib().orc_block_stats(t, mask, H, W, lb_h, lb_w, q, J, S, N, Ts, No)
     return S, N, Ts, No
+
+
+def block_stats_directional(t, mask, lb_h, lb_w, q=0.5, J=1.0):
+    """Eq. (2) per block split by bond direction: (Sh, Nh) horizontal bonds, (Sv, Nv) vertical bonds."""
+    t = _c(t, np.float32)
+    mask = _c(mask, np.uint8)
+    H, W = t.shape
+    nby, nbx = n_blocks(H, W, lb_h, lb_w)
+    B = nby * nbx
+    Sh, Sv = np.zeros(B, np.float64), np.zeros(B, np.float64)
+    Nh, Nv = np.zeros(B, np.int32), np.zeros(B, np.int32)
+    lib().orc_block_stats_directional(t, mask, H, W, lb_h, lb_w, q, J, Sh, Nh, Sv, Nv)
+    return Sh, Nh, Sv, Nv
+
+
+# Directional coupling: the lowest temperature a direction may take, in units of J (keeps both temperatures > 0, so
+# the ratio of the two couplings is finite).
+T_MIN_DIRECTIONAL = 1e-3
+
+
+def calibrate_directional(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    """Directional coupling (the extension suggested in Sec. 4): each block gets Tx from its horizontal sample bonds
+    and Ty from its vertical ones, each by the energy matching and median fill of Sec. 2.2.2 with the (isotropic)
+    matching curve, then raised to at least fl32(T_MIN_DIRECTIONAL * J).  Returns (Tx, Ty) as [nby, nbx] float32."""
+    H, W = np.shape(t)
+    Sh, Nh, Sv, Nv = block_stats_directional(t, mask, lb_h, lb_w, q, J)
+    floor = np.float32(T_MIN_DIRECTIONAL * float(J))
+    Tx = np.maximum(calibrate_blocks(Sh, Nh, curve_T, curve_e, J), floor)
+    Ty = np.maximum(calibrate_blocks(Sv, Nv, curve_T, curve_e, J), floor)
+    nby, nbx = n_blocks(H, W, lb_h, lb_w)
+    return Tx.reshape(nby, nbx), Ty.reshape(nby, nbx)
+
+
+def sweep_directional(state, mask, Tx, Ty, lb_h, lb_w, k, q=0.5, J=1.0, seed=0, scene=0, real=0):
+    assert state.dtype == np.float32 and state.flags["C_CONTIGUOUS"]
+    H, W = state.shape
+    T = np.concatenate([_c(Tx, np.float32).ravel(), _c(Ty, np.float32).ravel()])
+    lib().orc_sweep_directional(state, _c(mask, np.uint8), H, W, T, lb_h, lb_w, q, J, seed, scene, real, k)
 
 
 def curve_inverse(e, curve_T, curve_e) -> float:
@@ -234,6 +278,7 @@ class SimConfig:
     scene: int = 0
     t_mode: int = 0             # 0 block temperatures (BST), 1 one temperature per site (SST)
     order: int = 0              # 0 single checkerboard, 1 double checkerboard over the blocks
+    directional: int = 0        # 1: T_blocks holds Tx of every block, then Ty (directional coupling, SC order)
 
 
 @dataclass
@@ -257,7 +302,8 @@ def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
     conv = _i32(0)
     k = lib().orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
                            cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp, cfg.n_fit, cfg.n_f,
-                           cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, cfg.order, state, acc, en, ctypes.byref(conv))
+                           cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, cfg.order, cfg.directional, state, acc, en,
+                           ctypes.byref(conv))
     return SimResult(state=state, acc=acc, energy=en[: k + 1].copy(), k_star=int(k), converged=bool(conv.value))
 
 

@@ -170,6 +170,38 @@ void orc_block_stats(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     }
 }
 
+/* Directional form of the block statistics for the directional-coupling extension (Sec. 4 suggests distinguishing
+ * the exchange interaction by direction, keeping the parameters local to blocks): the sample-bond energies of Eq. (2)
+ * split by the direction of the bond, horizontal (a site and its right neighbour) into Sh, Nh and vertical (a site
+ * and its lower neighbour) into Sv, Nv; a bond belongs to the block of its owner as above. */
+void orc_block_stats_directional(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h,
+                                 int32_t lb_w, float q, float J, double* Sh, int32_t* Nh, double* Sv, int32_t* Nv)
+{
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    for (int64_t b = 0; b < nbx * nby; ++b) {
+        Sh[b] = 0.0;
+        Nh[b] = 0;
+        Sv[b] = 0.0;
+        Nv[b] = 0;
+    }
+    for (int64_t y = 0; y < H; ++y) {
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t n = y * W + x;
+            if (!mask[n]) continue;
+            int64_t b = (y / lb_h) * nbx + (x / lb_w);
+            if (x + 1 < W && mask[n + 1]) {
+                Sh[b] += bond_energy(t[n], t[n + 1], tpq, J);
+                Nh[b] += 1;
+            }
+            if (y + 1 < H && mask[n + W]) {
+                Sv[b] += bond_energy(t[n], t[n + W], tpq, J);
+                Nv[b] += 1;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------------------------------------------
  * Temperature by specific-energy matching (Sec. 2.1; per block in Sec. 2.2.2).
  * Reading: the matching curve e_ref(T) is the equilibrium energy per bond of the unconditional MPR model at
@@ -276,6 +308,59 @@ static void metropolis_site(float* s, int64_t H, int64_t W, int64_t x, int64_t y
         accept = dE <= 0.0;
     }
     if (accept) s[n] = (float)t_new;
+}
+
+/* Directional coupling (the extension of Sec. 4): every site carries two temperatures, Tx for its horizontal bonds
+ * and Ty for its vertical bonds, so the Boltzmann factor of an update is exp(-dEh/Tx - dEv/Ty) with
+ * dEh = -J * [left and right terms] and dEv = -J * [up and down terms] of the sum of metropolis_site (equivalently
+ * couplings J and J Tx/Ty at temperature Tx).  Both temperatures are > 0.  Accept iff u2 < exp(w) with
+ * w = J ah / Tx + J av / Ty, ah = left + right, av = up + down, each term cos 2 pi q (t' - t_j) - cos 2 pi q (t - t_j). */
+static void metropolis_site_directional(float* s, int64_t H, int64_t W, int64_t x, int64_t y, double Tx, double Ty,
+                                        double two_pi_q, double J, double u1, double u2)
+{
+    int64_t n = y * W + x;
+    double t_old = (double)s[n];
+    double t_new = (double)(float)u1;
+    double ah = 0.0, av = 0.0;
+    if (y > 0) {
+        double tj = (double)s[n - W];
+        av += cos(two_pi_q * (t_new - tj)) - cos(two_pi_q * (t_old - tj));
+    }
+    if (x > 0) {
+        double tj = (double)s[n - 1];
+        ah += cos(two_pi_q * (t_new - tj)) - cos(two_pi_q * (t_old - tj));
+    }
+    if (x + 1 < W) {
+        double tj = (double)s[n + 1];
+        ah += cos(two_pi_q * (t_new - tj)) - cos(two_pi_q * (t_old - tj));
+    }
+    if (y + 1 < H) {
+        double tj = (double)s[n + W];
+        av += cos(two_pi_q * (t_new - tj)) - cos(two_pi_q * (t_old - tj));
+    }
+    double w = J * ah / Tx + J * av / Ty;
+    if (u2 < exp(w)) s[n] = (float)t_new;
+}
+
+/* Single-checkerboard sweep with directional block temperatures: Tx[b] = T[b], Ty[b] = T[B + b]. */
+void orc_sweep_directional(float* s, const uint8_t* mask, int64_t H, int64_t W, const float* T, int32_t lb_h,
+                           int32_t lb_w, float q, float J, uint64_t seed, uint32_t scene, uint32_t real,
+                           uint32_t sweep)
+{
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
+    int64_t B = nbx * nby;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = (y + colour) & 1; x < W; x += 2) {
+                if (mask[y * W + x]) continue;
+                int64_t b = (y / lb_h) * nbx + (x / lb_w);
+                double u1, u2;
+                site_uniforms(seed, scene, ORC_TAG_SWEEP, sweep, real, W, x, y, &u1, &u2);
+                metropolis_site_directional(s, H, W, x, y, (double)T[b], (double)T[B + b], tpq, (double)J, u1, u2);
+            }
+        }
+    }
 }
 
 /* Sec. 2.2.2, double checkerboard (DC): the grid is divided into the lb_h x lb_w blocks, coloured like a
@@ -462,6 +547,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
                      int32_t n_eq, int32_t n_samp, int32_t n_fit, int32_t n_f, int32_t n_max, uint64_t seed,
                      uint32_t scene, int32_t t_per_site /* 0: T_blocks per block, 1: T_blocks[H*W] per site */,
                      int32_t order /* 0: single checkerboard, 1: double checkerboard over the lb_h x lb_w blocks */,
+                     int32_t directional /* 1: T_blocks = [Tx of the B blocks, Ty of the B blocks], SC order */,
                      float* state, double* acc, double* energy, int32_t* converged)
 {
     /* the temperature layout the sweeps read: blocks of lb_h x lb_w, or one temperature per site (SST) */
@@ -514,7 +600,10 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
         double ek = 0.0;
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            if (order == 1)
+            if (directional)
+                orc_sweep_directional(s, mask, H, W, T_blocks, lb_h, lb_w, q, J, seed, scene,
+                                      (uint32_t)(r + real_offset), (uint32_t)k);
+            else if (order == 1)
                 orc_sweep_dc(s, mask, H, W, T_blocks, tb_h, tb_w, lb_h, lb_w, q, J, seed, scene,
                              (uint32_t)(r + real_offset), (uint32_t)k);
             else
@@ -530,7 +619,10 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
-            if (order == 1)
+            if (directional)
+                orc_sweep_directional(s, mask, H, W, T_blocks, lb_h, lb_w, q, J, seed, scene,
+                                      (uint32_t)(r + real_offset), (uint32_t)(k_star + s_i));
+            else if (order == 1)
                 orc_sweep_dc(s, mask, H, W, T_blocks, tb_h, tb_w, lb_h, lb_w, q, J, seed, scene,
                              (uint32_t)(r + real_offset), (uint32_t)(k_star + s_i));
             else

@@ -43,6 +43,18 @@ def _torus_grf(M0: int, M1: int, xi: float, rng: np.random.Generator) -> np.ndar
     return f
 
 
+def grf_aniso(H: int, W: int, xi_x: float, xi_y: float, rng: np.random.Generator) -> np.ndarray:
+    """Standardised stationary GRF with geometric anisotropy: covariance exp(-sqrt((dx/xi_x)^2 + (dy/xi_y)^2)),
+    circulant embedding on a 2H x 2W torus (negative eigenvalues clipped)."""
+    M0, M1 = 2 * H, 2 * W
+    d0 = np.minimum(np.arange(M0), M0 - np.arange(M0)).astype(np.float64) / xi_y
+    d1 = np.minimum(np.arange(M1), M1 - np.arange(M1)).astype(np.float64) / xi_x
+    cov = np.exp(-np.sqrt(d0[:, None] ** 2 + d1[None, :] ** 2))
+    lam = np.clip(np.fft.rfft2(cov).real, 0.0, None)
+    f = np.fft.irfft2(np.sqrt(lam) * np.fft.rfft2(rng.standard_normal((M0, M1))), s=(M0, M1))[:H, :W]
+    return (f - f.mean()) / max(f.std(), 1e-300)
+
+
 def grf(H: int, W: int, xi: float, rng: np.random.Generator) -> np.ndarray:
     """Standardised stationary GRF on H x W, embedded in a 2H x 2W torus."""
     f = _torus_grf(2 * H, 2 * W, xi, rng)[:H, :W]
