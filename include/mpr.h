@@ -54,6 +54,7 @@ enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
 enum { MPR_T_BLOCK = 0, MPR_T_SITE = 1 };
 enum { MPR_ORDER_SC = 0, MPR_ORDER_DC = 1 };
 enum { MPR_SWEEP_AUTO = 0, MPR_SWEEP_TILES = 1, MPR_SWEEP_LANES = 2 };
+enum { MPR_COUPLING_ISOTROPIC = 0, MPR_COUPLING_DIRECTIONAL = 1 };
 
 /* Parameters of one conditional simulation (host struct). */
 typedef struct {
@@ -84,6 +85,16 @@ typedef struct {
                              realizations of one site (sides below 65536); MPR_SWEEP_AUTO (0, zero-initialised):
                              LANES when R >= 64 and the grid gives at least 2048 waves, else TILES.  mpr_sweep and
                              the batched form use TILES. */
+    int32_t coupling;     /* MPR_COUPLING_ISOTROPIC (0, zero-initialised): one temperature per block.
+                             MPR_COUPLING_DIRECTIONAL (1): the directional exchange interaction suggested in Sec. 4,
+                             kept local to blocks: T_blocks[2*B] holds Tx of every block (its horizontal bonds) and
+                             then Ty (its vertical bonds); an update is accepted iff
+                             u2 < exp(J ah / Tx + J av / Ty), ah and av the sums of cos 2 pi q (t' - t_j) -
+                             cos 2 pi q (t - t_j) over the left/right and up/down neighbours (couplings J and J Tx/Ty
+                             at temperature Tx); temperatures below 1e-3 J are raised to fl32(1e-3 J).  Runs in the
+                             single-checkerboard order with block temperatures on the realization-lane kernel (AUTO
+                             selects it; TILES is refused); the energy series stays the unweighted Eq. (1) energy per
+                             bond.  mpr_simulate only. */
 } mpr_sim_config;
 
 /* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;
@@ -129,6 +140,17 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
                                      int32_t lb_w, float q, float J, const double* curve_T, const double* curve_e,
                                      int32_t n_curve, float* T_out, double* e_blocks_out, int32_t* nbonds_out,
                                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Directional-coupling extension (Sec. 4 suggests an exchange interaction that depends on the direction, with the
+ * parameters kept local to blocks): per block, Tx by the energy matching of mpr_calibrate_temperature applied to its
+ * horizontal sample bonds only (a sample and its right neighbour) and Ty to its vertical ones (a sample and its
+ * lower neighbour), each with its own median fill, then both raised to at least fl32(1e-3 J).  The same matching
+ * curve is used for both directions (exact when Tx = Ty).  Tx_out[B], Ty_out[B] (float).  Synchronises the stream;
+ * MPR_ERR_NO_SAMPLE_BONDS when a direction has no sample bond at all.  Workspace: mpr_calibrate_workspace_bytes. */
+mpr_status mpr_calibrate_directional(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h,
+                                     int32_t lb_w, float q, float J, const double* curve_T, const double* curve_e,
+                                     int32_t n_curve, float* Tx_out, float* Ty_out, void* workspace, size_t ws_bytes,
+                                     void* stream);
 
 /* Conditional simulation (Sec. 2.1, Sec. 2.2.2, Sec. 3.3, Sec. 3.4).
  *   t[H*W]: mapped angles (samples used); T_blocks[B]: block temperatures (float) with the same lb_h x lb_w layout,

@@ -552,6 +552,15 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
 {
     /* the temperature layout the sweeps read: blocks of lb_h x lb_w, or one temperature per site (SST) */
     const int32_t tb_h = t_per_site ? 1 : lb_h, tb_w = t_per_site ? 1 : lb_w;
+    /* directional coupling: both temperatures raised to at least fl32(1e-3 J) */
+    float* T_dir = NULL;
+    if (directional) {
+        int64_t nb = ((W + lb_w - 1) / lb_w) * ((H + lb_h - 1) / lb_h);
+        float floor_T = (float)(1e-3 * (double)J);
+        T_dir = (float*)malloc(sizeof(float) * (size_t)(2 * nb));
+        for (int64_t i = 0; i < 2 * nb; ++i) T_dir[i] = T_blocks[i] > floor_T ? T_blocks[i] : floor_T;
+        T_blocks = T_dir;
+    }
     int64_t HW = H * W;
     int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
     int64_t B = nbx * nby;
@@ -639,6 +648,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     free(N);
     free(Tsum);
     free(Nobs);
+    free(T_dir);
     return k_star;
 }
 

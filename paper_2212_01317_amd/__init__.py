@@ -11,13 +11,14 @@ from dataclasses import dataclass
 import torch
 
 from .autograd import MPRFunction
-from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, MprError, SimConfig, SimOutput, lib,
-                   mpr_block_stats, mpr_calibrate_temperature, mpr_map_angles, mpr_predict, mpr_reference_curve,
+from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL, MprError, SimConfig, SimOutput, lib,
+                   mpr_block_stats, mpr_calibrate_temperature, mpr_calibrate_directional, mpr_map_angles, mpr_predict, mpr_reference_curve,
                    mpr_simulate, mpr_sweep, mpr_validate, mpr_block_energy, mpr_temperature_grad,
                    mpr_simulate_batched, BatchOutput, mpr_probe_instruction_rates, mpr_sst_temperatures)
 
-__all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "MprError", "SimConfig", "SimOutput",
-           "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_map_angles", "mpr_predict",
+__all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "COUPLING_ISOTROPIC", "COUPLING_DIRECTIONAL", "MprError", "SimConfig", "SimOutput",
+           "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_calibrate_directional", "mpr_map_angles",
+           "mpr_predict",
            "mpr_reference_curve", "mpr_simulate", "mpr_sweep", "mpr_validate", "default_T_grid", "reference_curve", "predict",
            "Prediction", "CURVE_SPEC", "MPRFunction", "mpr_block_energy", "mpr_temperature_grad",
            "mpr_simulate_batched", "BatchOutput", "mpr_probe_instruction_rates", "mpr_sst_temperatures"]
@@ -59,24 +60,30 @@ def predict(z: torch.Tensor, mask: torch.Tensor, block=(32, 32), n_real: int = 1
             J: float = 1.0, init_mode: int = INIT_BLOCK_MEAN, stop_mode: int = STOP_AUTO, n_eq: int = 50,
             n_samp: int = 1, n_fit: int = 20, n_f: int = 5, n_max: int = 1000, seed: int = 0, scene_id: int = 0,
             curve=None, T_blocks: torch.Tensor | None = None, sst: tuple | None = None,
-            order: int = ORDER_SC) -> Prediction:
+            order: int = ORDER_SC, directional: bool = False) -> Prediction:
     """Fill the gaps (mask == 0) of z: Sec. 2.1 map, Sec. 2.2.2 block temperatures (block = (lb_h, lb_w); a block
     as large as the grid gives the plain MPR method), conditional simulation with the Sec. 3.4 stopping rule, and
     the conditional mean over n_real realizations x n_samp sampling sweeps.  sst = (r_s, n_s) gives the SST variant
     (Sec. 2.2.3): the block temperatures smoothed into one temperature per site; `T` is then that [H, W] map.
-    order = ORDER_DC sweeps in the double-checkerboard order over the blocks (Sec. 2.2.2)."""
+    order = ORDER_DC sweeps in the double-checkerboard order over the blocks (Sec. 2.2.2).  directional = True uses
+    the directional coupling (one temperature per bond direction and block, the extension suggested in Sec. 4);
+    `T` is then the [2, nby, nbx] stack (Tx, Ty)."""
     lb_h, lb_w = int(block[0]), int(block[1])
     t, rng = mpr_map_angles(z, mask)
     if T_blocks is None:
         cT, ce = reference_curve(q, z.device) if curve is None else curve
-        T_blocks, _, _ = mpr_calibrate_temperature(t, mask, lb_h, lb_w, cT, ce, q, J)
+        if directional:
+            T_blocks = torch.stack(mpr_calibrate_directional(t, mask, lb_h, lb_w, cT, ce, q, J))
+        else:
+            T_blocks, _, _ = mpr_calibrate_temperature(t, mask, lb_h, lb_w, cT, ce, q, J)
     t_mode = T_BLOCK
     if sst is not None:
         H, W = int(z.shape[-2]), int(z.shape[-1])
         T_blocks = mpr_sst_temperatures(T_blocks, H, W, lb_h, lb_w, int(sst[0]), int(sst[1]))
         t_mode = T_SITE
     cfg = SimConfig(q=q, J=J, n_real=n_real, init_mode=init_mode, stop_mode=stop_mode, n_eq=n_eq, n_samp=n_samp,
-                    n_fit=n_fit, n_f=n_f, n_max=n_max, seed=seed, scene_id=scene_id, t_mode=t_mode, order=order)
+                    n_fit=n_fit, n_f=n_f, n_max=n_max, seed=seed, scene_id=scene_id, t_mode=t_mode, order=order,
+                    coupling=COUPLING_DIRECTIONAL if directional else COUPLING_ISOTROPIC)
     sim = mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg)
     zhat = mpr_predict(sim.acc, z, mask, n_real * n_samp, rng)
     return Prediction(zhat=zhat, T=T_blocks, sim=sim, range=rng)

@@ -24,6 +24,7 @@ STOP_FIXED, STOP_AUTO = 0, 1
 T_BLOCK, T_SITE = 0, 1
 ORDER_SC, ORDER_DC = 0, 1
 SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES = 0, 1, 2
+COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL = 0, 1
 
 
 class MprError(RuntimeError):
@@ -38,7 +39,7 @@ class mpr_sim_config(ctypes.Structure):
                 ("n_eq", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_fit", ctypes.c_int32),
                 ("n_f", ctypes.c_int32), ("n_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("scene_id", ctypes.c_uint32), ("t_mode", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("sweep_kernel", ctypes.c_int32)]
+                ("sweep_kernel", ctypes.c_int32), ("coupling", ctypes.c_int32)]
 
 
 @dataclass
@@ -60,15 +61,18 @@ class SimConfig:
     t_mode: int = T_BLOCK       # T_BLOCK: one temperature per block; T_SITE: one per site (SST)
     order: int = ORDER_SC       # ORDER_SC single checkerboard; ORDER_DC double checkerboard over the blocks
     sweep_kernel: int = SWEEP_AUTO  # SWEEP_TILES / SWEEP_LANES force the sweep kernel (same chains either way)
+    coupling: int = COUPLING_ISOTROPIC  # COUPLING_DIRECTIONAL: T_blocks = [Tx of the blocks, Ty of the blocks]
 
     def to_c(self) -> mpr_sim_config:
         return mpr_sim_config(self.q, self.J, self.n_real, self.real_offset, self.init_mode, self.stop_mode,
                               self.n_eq, self.n_samp, self.n_fit, self.n_f, self.n_max, self.seed, self.scene_id,
-                              self.t_mode, self.order, self.sweep_kernel)
+                              self.t_mode, self.order, self.sweep_kernel, self.coupling)
 
 
 def _check_T(T_blocks, H, W, lb_h, lb_w, cfg: "SimConfig"):
     need = H * W if cfg.t_mode == T_SITE else ((H + lb_h - 1) // lb_h) * ((W + lb_w - 1) // lb_w)
+    if cfg.coupling == COUPLING_DIRECTIONAL:
+        need *= 2
     if T_blocks.numel() != need:
         raise ValueError(f"T_blocks has {T_blocks.numel()} entries, the grid and t_mode need {need}")
 
@@ -101,6 +105,8 @@ _SIGS = {
     "mpr_calibrate_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "mpr_calibrate_temperature": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
                                    _sz, _vp], ctypes.c_int),
+    "mpr_calibrate_directional": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp, _vp, _sz,
+                                   _vp], ctypes.c_int),
     "mpr_simulate_workspace_bytes": ([_i64, _i64, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
     "mpr_simulate": ([_vp, _vp, _i64, _i64, _vp, _i32, _i32, ctypes.POINTER(mpr_sim_config), _vp, _vp, _vp,
                       ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
@@ -237,6 +243,23 @@ def mpr_calibrate_temperature(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.
                                            int(curve_T.numel()), _p(T), _p(eb), _p(nb), _p(ws), ws.numel(),
                                            _stream()))
     return T, eb, nb
+
+
+def mpr_calibrate_directional(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    """Per-block temperatures of the horizontal and of the vertical sample bonds, (Tx, Ty) each [nby, nbx]."""
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(curve_T, torch.float64, "curve_T")
+    _dev(curve_e, torch.float64, "curve_e")
+    H, W = _hw(t)
+    nby, nbx = -(-H // lb_h), -(-W // lb_w)
+    dev = t.device
+    Tx = torch.empty((nby, nbx), dtype=torch.float32, device=dev)
+    Ty = torch.empty((nby, nbx), dtype=torch.float32, device=dev)
+    ws = _ws(lib().mpr_calibrate_workspace_bytes(H, W, lb_h, lb_w), dev)
+    _check(lib().mpr_calibrate_directional(_p(t), _p(mask), H, W, lb_h, lb_w, q, J, _p(curve_T), _p(curve_e),
+                                           int(curve_T.numel()), _p(Tx), _p(Ty), _p(ws), ws.numel(), _stream()))
+    return Tx, Ty
 
 
 @dataclass

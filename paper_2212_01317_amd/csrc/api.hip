@@ -81,7 +81,7 @@ int32_t t_lb(int32_t lb, const mpr_sim_config& c) { return c.t_mode == MPR_T_SIT
 bool use_rl(int64_t H, int64_t W, const mpr_sim_config* cfg)
 {
     if (!cfg || cfg->order != MPR_ORDER_SC || H >= 65536 || W >= 65536) return false;
-    if (cfg->sweep_kernel == MPR_SWEEP_LANES) return true;
+    if (cfg->sweep_kernel == MPR_SWEEP_LANES || cfg->coupling == MPR_COUPLING_DIRECTIONAL) return true;
     if (cfg->sweep_kernel == MPR_SWEEP_TILES || cfg->n_real < 64) return false;
     return mpr::rl_geometry(H, W, cfg->n_real).n_items >= mpr::kRlMinWaves;
 }
@@ -150,6 +150,7 @@ struct SimWs {
     double* e_real;     // [R]
     double* series;     // [cap + 1]
     float* alt;         // [R][H][W] second state buffer (fused sweep)
+    mpr::TBandDir* tpd; // directional coupling: per-block table
     float* rl[2];       // [HW][Rp] state buffers of the realization-lane sweep
     uint2* cells;       // its per-row window bits
 };
@@ -174,6 +175,7 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
     x.alt = rl ? nullptr : c.take<float>(R * H * W);
+    x.tpd = cfg->coupling == MPR_COUPLING_DIRECTIONAL ? c.take<mpr::TBandDir>(nblocks_of(H, W, lb_h, lb_w)) : nullptr;
     x.rl[0] = rl ? c.take<float>(H * W * rg.Rp) : nullptr;
     x.rl[1] = rl ? c.take<float>(H * W * rg.Rp) : nullptr;
     x.cells = rl ? c.take<uint2>((H + 4) * rg.nbands) : nullptr;
@@ -244,6 +246,13 @@ mpr_status check_sim_config(const mpr_sim_config& c)
         return fail(MPR_ERR_INVALID_ARG, "unknown sweep_kernel %d", c.sweep_kernel);
     if (c.sweep_kernel == MPR_SWEEP_LANES && c.order != MPR_ORDER_SC)
         return fail(MPR_ERR_INVALID_ARG, "the realization-lane sweep runs the single-checkerboard order");
+    if (c.coupling != MPR_COUPLING_ISOTROPIC && c.coupling != MPR_COUPLING_DIRECTIONAL)
+        return fail(MPR_ERR_INVALID_ARG, "unknown coupling %d", c.coupling);
+    if (c.coupling == MPR_COUPLING_DIRECTIONAL &&
+        (c.order != MPR_ORDER_SC || c.t_mode != MPR_T_BLOCK || c.sweep_kernel == MPR_SWEEP_TILES))
+        return fail(MPR_ERR_INVALID_ARG,
+                    "directional coupling runs the single-checkerboard order with block temperatures on the "
+                    "realization-lane sweep");
     return MPR_OK;
 }
 
@@ -641,6 +650,44 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
     return ok();
 }
 
+mpr_status mpr_calibrate_directional(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h,
+                                     int32_t lb_w, float q, float J, const double* curve_T, const double* curve_e,
+                                     int32_t n_curve, float* Tx_out, float* Ty_out, void* workspace, size_t ws_bytes,
+                                     void* stream)
+{
+    mpr_status st = check_grid(H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks(H, W, lb_h, lb_w)) != MPR_OK) return st;
+    if (!t || !mask || !curve_T || !curve_e || !Tx_out || !Ty_out)
+        return fail(MPR_ERR_INVALID_ARG, "mpr_calibrate_directional: NULL pointer");
+    if (n_curve < 1) return fail(MPR_ERR_INVALID_ARG, "n_curve must be >= 1");
+    if (!(q > 0.0f && q <= 0.5f) || !(J > 0.0f)) return fail(MPR_ERR_INVALID_ARG, "need 0 < q <= 1/2 and J > 0");
+    st = check_ws(workspace, ws_bytes, mpr_calibrate_workspace_bytes(H, W, lb_h, lb_w));
+    if (st != MPR_OK) return st;
+    mpr::StatsGeom g = mpr::stats_geom(H, W, lb_h, lb_w);
+    Carve c{static_cast<char*>(workspace), 0, ws_bytes};
+    CalWs w;
+    cal_ws(c, g, &w);
+    hipStream_t s = S(stream);
+    const float floor_T = (float)(mpr::kTMinDirectional * (double)J);
+    float* outs[2] = {Tx_out, Ty_out};
+    for (int d = 0; d < 2; ++d) {
+        // bonds 1: horizontal (a sample and its right neighbour), 2: vertical (a sample and its lower neighbour)
+        MPR_HIP(mpr::launch_block_stats(t, mask, g, 2.0 * mpr::kPi * (double)q, (double)J, w.st.pS, w.st.pN,
+                                        w.st.pTs, w.st.pNo, w.S, w.N, nullptr, nullptr, s, d + 1));
+        MPR_HIP(mpr::launch_calibrate(w.S, w.N, g.B(), (double)J, curve_T, curve_e, n_curve, outs[d], nullptr,
+                                      nullptr, w.n_have, s));
+        unsigned n_have = 0;
+        MPR_HIP(hipMemcpyAsync(&n_have, w.n_have, sizeof n_have, hipMemcpyDeviceToHost, s));
+        MPR_HIP(hipStreamSynchronize(s));
+        if (n_have == 0)
+            return fail(MPR_ERR_NO_SAMPLE_BONDS, "no %s pair of neighbouring samples: T%s cannot be estimated",
+                        d == 0 ? "horizontal" : "vertical", d == 0 ? "x" : "y");
+        MPR_HIP(mpr::launch_floor(outs[d], g.B(), floor_T, s));
+    }
+    return ok();
+}
+
 size_t mpr_simulate_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg)
 {
     if (!cfg || H < 1 || W < 1 || lb_h < 1 || lb_w < 1) return 0;
@@ -708,7 +755,13 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     ia.key1 = key1;
     ia.mode = c.init_mode;
     MPR_HIP(mpr::launch_init(ia, s));
-    MPR_HIP(mpr::launch_tpairs(T_blocks, t_count(H, W, lb_h, lb_w, cfg), c.J, mpr::kDeltaE * c.J, w.tp, s));
+    const bool directional = c.coupling == MPR_COUPLING_DIRECTIONAL;
+    if (directional) {
+        MPR_HIP(mpr::launch_tpairs_directional(T_blocks, nblocks_of(H, W, lb_h, lb_w), c.J, mpr::kDeltaE * c.J,
+                                               (float)(mpr::kTMinDirectional * (double)c.J), w.tpd, s));
+    } else {
+        MPR_HIP(mpr::launch_tpairs(T_blocks, t_count(H, W, lb_h, lb_w, cfg), c.J, mpr::kDeltaE * c.J, w.tp, s));
+    }
 
     const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
@@ -778,8 +831,8 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
         if (rl) {
             ra.sweep = k;
-            hipError_t e = mpr::launch_sweep_rl(ra, w.cells, w.tp, w.rl[rl_cur], w.rl[rl_cur ^ 1],
-                                                energy ? w.epart : nullptr, s);
+            hipError_t e = mpr::launch_sweep_rl(ra, w.cells, w.tp, directional ? w.tpd : nullptr, w.rl[rl_cur],
+                                                w.rl[rl_cur ^ 1], energy ? w.epart : nullptr, s);
             rl_cur ^= 1;
             if (e == hipSuccess && energy)
                 e = mpr::launch_energy_reduce(w.epart, rl_parts, R, runner.inv_norm, w.e_real, w.series + k, s);
@@ -858,6 +911,8 @@ mpr_status mpr_sweep(float* state, float* state_alt, const uint8_t* mask, int64_
     if (state == state_alt) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep: state and state_alt must be distinct buffers");
     if ((st = check_sim_config(*cfg)) != MPR_OK) return st;
     if (cfg->order != MPR_ORDER_SC) return fail(MPR_ERR_INVALID_ARG, "mpr_sweep runs the single-checkerboard order");
+    if (cfg->coupling != MPR_COUPLING_ISOTROPIC)
+        return fail(MPR_ERR_INVALID_ARG, "mpr_sweep runs one temperature per block (isotropic coupling)");
     if (k_first < 1 || n_sweeps < 0) return fail(MPR_ERR_INVALID_ARG, "need k_first >= 1 and n_sweeps >= 0");
     st = check_ws(workspace, ws_bytes, mpr_sweep_workspace_bytes(H, W, lb_h, lb_w, cfg));
     if (st != MPR_OK) return st;
@@ -928,6 +983,8 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
     mpr_status st = check_sim_config(*cfg);
     if (st != MPR_OK) return st;
     const mpr_sim_config& c = *cfg;
+    if (c.coupling != MPR_COUPLING_ISOTROPIC)
+        return fail(MPR_ERR_INVALID_ARG, "the batched form runs one temperature per block (isotropic coupling)");
     if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
         return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
     if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)

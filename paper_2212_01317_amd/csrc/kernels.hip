@@ -195,8 +195,8 @@ StatsGeom stats_geom(int64_t H, int64_t W, int lb_h, int lb_w)
 
 __global__ __launch_bounds__(STATS_NT) void k_block_stats(const float* __restrict__ t,
                                                            const uint8_t* __restrict__ mask, StatsGeom g,
-                                                           double two_pi_q, double J, double* pS, int* pN,
-                                                           double* pTs, int* pNo)
+                                                           double two_pi_q, double J, int bonds, double* pS,
+                                                           int* pN, double* pTs, int* pNo)
 {
     __shared__ double lds_d[STATS_NT / 64];
     __shared__ int lds_i[STATS_NT / 64];
@@ -221,11 +221,11 @@ __global__ __launch_bounds__(STATS_NT) void k_block_stats(const float* __restric
             const double tn = (double)t[n];
             Ts += tn;
             ++No;
-            if (x + 1 < g.W && mask[n + 1]) {
+            if ((bonds & 1) && x + 1 < g.W && mask[n + 1]) {
                 S += -J * cos(two_pi_q * (tn - (double)t[n + 1]));
                 ++N;
             }
-            if (y + 1 < g.H && mask[n + g.W]) {
+            if ((bonds & 2) && y + 1 < g.H && mask[n + g.W]) {
                 S += -J * cos(two_pi_q * (tn - (double)t[n + g.W]));
                 ++N;
             }
@@ -266,12 +266,12 @@ __global__ __launch_bounds__(256) void k_block_stats_final(const double* pS, con
 
 hipError_t launch_block_stats(const float* t, const uint8_t* mask, const StatsGeom& g, double two_pi_q, double J,
                               double* pS, int* pN, double* pTs, int* pNo, double* S, int* N, double* Ts, int* No,
-                              hipStream_t s)
+                              hipStream_t s, int bonds)
 {
     const int64_t B = g.B();
     const int64_t nwg = B * g.nchunk;
-    hipLaunchKernelGGL(k_block_stats, dim3((unsigned)nwg), dim3(STATS_NT), 0, s, t, mask, g, two_pi_q, J, pS, pN,
-                       pTs, pNo);
+    hipLaunchKernelGGL(k_block_stats, dim3((unsigned)nwg), dim3(STATS_NT), 0, s, t, mask, g, two_pi_q, J, bonds, pS,
+                       pN, pTs, pNo);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_block_stats_final, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, pS, pN, pTs, pNo, B,
@@ -419,6 +419,37 @@ __global__ __launch_bounds__(256) void k_tpairs(const float* T, int64_t B, float
 hipError_t launch_tpairs(const float* T, int64_t B, float J, float delta, TBand* tp, hipStream_t s)
 {
     hipLaunchKernelGGL(k_tpairs, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, T, B, J, delta, tp);
+    return hipGetLastError();
+}
+
+// Directional coupling: per block {Tx, Ty} from T[b], T[B + b] raised to at least `floor`, the scales
+// kx = J log2(e) / Tx, ky = J log2(e) / Ty of the two field components and the error band of the filter.
+__global__ __launch_bounds__(256) void k_tpairs_directional(const float* __restrict__ T, int64_t B, float J,
+                                                             float delta, float floor_T, TBandDir* __restrict__ out)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    out[b] = make_tband_directional(fmaxf(T[b], floor_T), fmaxf(T[B + b], floor_T), J, delta);
+}
+
+hipError_t launch_tpairs_directional(const float* T, int64_t B, float J, float delta, float floor_T, TBandDir* out,
+                                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tpairs_directional, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, T, B, J, delta,
+                       floor_T, out);
+    return hipGetLastError();
+}
+
+// out[i] = max(T[i], floor_T)
+__global__ __launch_bounds__(256) void k_floor(float* __restrict__ T, int64_t n, float floor_T)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) T[i] = fmaxf(T[i], floor_T);
+}
+
+hipError_t launch_floor(float* T, int64_t n, float floor_T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_floor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, n, floor_T);
     return hipGetLastError();
 }
 

@@ -93,6 +93,25 @@ __device__ __forceinline__ TBand make_tband(float T, float J, float delta)
     return b;
 }
 
+// Directional coupling: y24 = fma(X_h, kx, fma(X_v, ky, 24)) with the horizontal and vertical parts X_h, X_v of the
+// field change (each within delta / J of exact).  Its error: delta log2(e) (1/Tx + 1/Ty) from the fields, two
+// roundings near 24 (2^-19 together), and the roundings of kx, ky and of large intermediate sums (at most
+// (|X_h| kx + |X_v| ky) 2^-22); v_exp_f32 adds a relative 2^-22.  The band is that bound with a 25 % margin, as for
+// one temperature.  Both temperatures are > 0.
+__device__ __forceinline__ TBandDir make_tband_directional(float Tx, float Ty, float J, float delta)
+{
+    TBandDir b;
+    b.Tx = Tx;
+    b.Ty = Ty;
+    b.kx = (float)((double)J * 1.4426950408889634074 / (double)Tx);
+    b.ky = (float)((double)J * 1.4426950408889634074 / (double)Ty);
+    b.kbx = kBandY * b.kx;
+    b.kby = kBandY * b.ky;
+    b.band = 1.25f * (0.6931472f * (delta * 1.4426950f * (1.0f / Tx + 1.0f / Ty) + 1.9073486e-6f) + 2.3841858e-7f);
+    b.pad = 0.0f;
+    return b;
+}
+
 __device__ __forceinline__ int filter32(float X, float ui, const TBand& tb, float J, float delta)
 {
     if (tb.T > 0.0f) {
@@ -121,6 +140,23 @@ __device__ __noinline__ bool exact64(float tp, float to, float nu, float nl, flo
     const double dE = -J * acc;
     if ((double)T > 0.0) return (double)u2 < exp(-dE / (double)T);
     return dE <= 0.0;
+}
+
+// The exact directional decision, evaluated as the definition writes it: ah over the left and right neighbours, av
+// over the up and down neighbours (each term cos 2 pi q (t' - t_j) - cos 2 pi q (t - t_j), in the order up, left,
+// right, down), accept iff u2 < exp(J ah / Tx + J av / Ty).
+__device__ __noinline__ bool exact64_directional(float tp, float to, float nu, float nl, float nr, float nd,
+                                                 unsigned present, double two_pi_q, double J, float Tx, float Ty,
+                                                 float u2)
+{
+    double ah = 0.0, av = 0.0;
+    const double dtp = (double)tp, dto = (double)to;
+    if (present & 1u) av += cos(two_pi_q * (dtp - (double)nu)) - cos(two_pi_q * (dto - (double)nu));
+    if (present & 2u) ah += cos(two_pi_q * (dtp - (double)nl)) - cos(two_pi_q * (dto - (double)nl));
+    if (present & 4u) ah += cos(two_pi_q * (dtp - (double)nr)) - cos(two_pi_q * (dto - (double)nr));
+    if (present & 8u) av += cos(two_pi_q * (dtp - (double)nd)) - cos(two_pi_q * (dto - (double)nd));
+    const double w = J * ah / (double)Tx + J * av / (double)Ty;
+    return (double)u2 < exp(w);
 }
 
 }  // namespace mpr

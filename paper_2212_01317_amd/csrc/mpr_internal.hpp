@@ -20,6 +20,16 @@ constexpr float kDeltaE = 1.25e-5f;
 struct alignas(16) TBand {
     float T, kappa, band, kb;
 };
+// Directional coupling (one temperature per bond direction): the filter's y = log2 of the acceptance ratio is
+// X_h kx + X_v ky with kx = J log2(e) / Tx, ky = J log2(e) / Ty; its error band is band + |X_h| kbx + |X_v| kby.
+struct alignas(16) TBandDir {
+    float Tx, Ty, kx, ky, kbx, kby, band, pad;
+};
+// The lowest directional temperature, in units of J.
+constexpr double kTMinDirectional = 1e-3;
+hipError_t launch_tpairs_directional(const float* T, int64_t B, float J, float delta, float floor_T, TBandDir* out,
+                                     hipStream_t s);
+hipError_t launch_floor(float* T, int64_t n, float floor_T, hipStream_t s);
 
 // Bump allocator over the caller's workspace (256-byte aligned slices).
 struct Carve {
@@ -51,9 +61,10 @@ struct StatsGeom {
     int64_t B() const { return (int64_t)nbx * nby; }
 };
 StatsGeom stats_geom(int64_t H, int64_t W, int lb_h, int lb_w);
+// bonds: 1 = horizontal bonds only, 2 = vertical only, 3 = both
 hipError_t launch_block_stats(const float* t, const uint8_t* mask, const StatsGeom& g, double two_pi_q, double J,
                               double* pS, int* pN, double* pTs, int* pNo, double* S, int* N, double* Ts, int* No,
-                              hipStream_t s);
+                              hipStream_t s, int bonds = 3);
 hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, const double* cT, const double* ce,
                             int nc, float* T_out, double* e_out, int* nb_out, unsigned* n_have, hipStream_t s);
 hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float* gmean, hipStream_t s);
@@ -141,8 +152,9 @@ hipError_t launch_rl_accumulate(const float* S, const uint8_t* mask, int64_t HW,
                                 hipStream_t s);
 // one sweep src -> dst; with epart set, the fixed-point energy of each wave's colour-1 sites goes to
 // epart[r][seg * nbands + band] (layout [R][nbands * nseg])
-hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const float* src, float* dst,
-                           long long* epart, hipStream_t s);
+// tbd != nullptr: directional coupling with the per-block table tbd (tb is then unused)
+hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const TBandDir* tbd, const float* src,
+                           float* dst, long long* epart, hipStream_t s);
 
 // Sec. 2.2.2 double-checkerboard sweep (dc.hip): four in-place phases per sweep over all realizations.
 struct DcArgs {

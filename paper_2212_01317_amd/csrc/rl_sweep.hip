@@ -20,6 +20,8 @@
 // stopping sweep are identical.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "metropolis.hpp"
 #include "mpr_internal.hpp"
 
@@ -67,14 +69,16 @@ __device__ __forceinline__ U4 philox_rl(uint32_t c0, uint32_t c1, uint32_t c2, u
     return U4{c0, c1, c2, c3};
 }
 
-template <int KB, bool ALIGNED, bool ENERGY>
+// DIR: directional coupling (a temperature per bond direction, table TBandDir); else one temperature (TBand).
+template <int KB, bool ALIGNED, bool ENERGY, bool DIR>
 struct RlWave {
     static constexpr int kB = KB;          // columns owned by the wave
     static constexpr int kWC = KB + 4;     // window columns x0 - 2 .. x0 + KB + 1
     static constexpr uint32_t kAll = (1u << kWC) - 1u;
+    using TB = typename std::conditional<DIR, TBandDir, TBand>::type;
     RlArgs a;
     const uint2* __restrict__ cells;   // [(H + 4) * nbands]: row y + 2 -> {gap bits, sample bits} of the window
-    const TBand* __restrict__ tb;
+    const TB* __restrict__ tb;
     const char* src;                   // this wave's group of realizations in the two state buffers
     char* dst;
     int band, x0, ys, ye, lane;
@@ -90,8 +94,8 @@ struct RlWave {
                                        // of row y - 1), loaded at its start
     uint32_t pgap, psmp;
     int brow, brem;                    // temperature row of the step's row y, and y - brow tb_h
-    const TBand* trow0;                // temperature rows of y and y - 1 (clamped into the grid)
-    const TBand* trow1;
+    const TB* trow0;                   // temperature rows of y and y - 1 (clamped into the grid)
+    const TB* trow1;
     int bc, bcl, bcr;                  // ALIGNED: temperature columns of the owned columns and of the two ring columns
     long long e_acc;
 
@@ -177,7 +181,7 @@ struct RlWave {
     // neighbours are read back from dst (this wave wrote them), colour-1 neighbours from src, on the exact path.
     // Returns the fixed-point energy / J of the site's bonds after the update.
     template <int COL, int SO, int SU, int SD>
-    __device__ __forceinline__ int update(const TBand& T, int y, int64_t off, int j, float to, uint32_t wp,
+    __device__ __forceinline__ int update(const TB& T, int y, int64_t off, int j, float to, uint32_t wp,
                                           uint32_t wa)
     {
         const float Cx = ((c[SU][j] + c[SO][j - 1]) + c[SO][j + 1]) + c[SD][j];
@@ -187,6 +191,8 @@ struct RlWave {
         const float ang = a.q * tp;
         const float cp = cos_rev(ang), sp = sin_rev(ang);
         const float co = c[SO][j], so = s[SO][j];
+        if constexpr (DIR) return update_directional<COL, SO, SU, SD>(T, y, off, j, to, tp, ui, cp, sp, co, so, Cx, Sy);
+        else {
         const float X = fmaf(cp - co, Cx, (sp - so) * Sy);
         // The FP32 filter with a wave-uniform temperature, as one comparison of (lhs, rhs) with a tolerance: accept
         // iff lhs < rhs, exact FP64 test iff |lhs - rhs| <= tol.  T > 0: (ui, w24, the error band of w24);
@@ -235,9 +241,57 @@ struct RlWave {
         s[SO][j] = sf;
         st(off, j, tn);
         return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
+        }
     }
 
-    __device__ __forceinline__ TBand tband(const TBand* trow, int j) const
+    // The directional update: X_h from the left and right neighbours, X_v from the up and down neighbours,
+    // y24 = fma(X_h, kx, fma(X_v, ky, 24)); the energy term is the unweighted bond energy, as for one temperature.
+    template <int COL, int SO, int SU, int SD>
+    __device__ __forceinline__ int update_directional(const TB& T, int y, int64_t off, int j, float to, float tp,
+                                                      float ui, float cp, float sp, float co, float so, float Cx,
+                                                      float Sy)
+    {
+        const float Ch = c[SO][j - 1] + c[SO][j + 1], Sh = s[SO][j - 1] + s[SO][j + 1];
+        const float Cv = c[SU][j] + c[SD][j], Sv = s[SU][j] + s[SD][j];
+        const float Xh = fmaf(cp - co, Ch, (sp - so) * Sh);
+        const float Xv = fmaf(cp - co, Cv, (sp - so) * Sv);
+        const float w24 = exp2_fast(fminf(fmaf(Xh, T.kx, fmaf(Xv, T.ky, 24.0f)), 25.0f));
+        const float tol = fmaf(w24, fmaf(fabsf(Xh), T.kbx, fmaf(fabsf(Xv), T.kby, T.band)), 0.015625f);
+        const bool acc = ui < w24;
+        float tn = acc ? tp : to;
+        float cf = acc ? cp : co, sf = acc ? sp : so;
+        if (fabsf(ui - w24) <= tol) {
+            const int x = x0 - 2 + j;
+            const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
+            const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
+            const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
+            float nu, nl, nr, nd;
+            if (COL == 0) {
+                nu = ld(src, ou, j);
+                nl = ld(src, off, jl);
+                nr = ld(src, off, jr);
+                nd = ld(src, od, j);
+            } else {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                nu = ld_coherent(dst, ou, j);
+                nl = ld_coherent(dst, off, jl);
+                nr = ld_coherent(dst, off, jr);
+                nd = ld_coherent(dst, od, j);
+            }
+            const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
+            const bool ex = exact64_directional(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.Tx, T.Ty,
+                                                ui * 5.9604644775390625e-8f);
+            tn = ex ? tp : to;
+            cf = ex ? cp : co;
+            sf = ex ? sp : so;
+        }
+        c[SO][j] = cf;
+        s[SO][j] = sf;
+        st(off, j, tn);
+        return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
+    }
+
+    __device__ __forceinline__ TB tband(const TB* trow, int j) const
     {
         if (ALIGNED) return trow[j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)];
         return trow[bcol(j)];
@@ -246,7 +300,7 @@ struct RlWave {
     // Colour COL of the row in slot SO (grid row y): the pairs of groups m0 + MLO .. m0 + MHI, sites restricted to
     // window columns [JLO, JHI).  PAR = (y + COL) & 1, the column offset of the colour inside a group of four.
     template <int COL, int PAR, int SO, int SU, int SD, int MLO, int MHI, int JLO, int JHI>
-    __device__ __forceinline__ int colour(const TBand* trow, int y, int64_t off, const float* to)
+    __device__ __forceinline__ int colour(const TB* trow, int y, int64_t off, const float* to)
     {
         const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COL);
         const uint32_t base = (uint32_t)y * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
@@ -260,7 +314,7 @@ struct RlWave {
             const bool g1 = in1 && ((gap[SO] >> k1) & 1u);
             if (!(g0 || g1)) continue;
             // old angles of the pair (a cell outside the grid reads its in-grid partner instead)
-            const TBand T0 = tband(trow, k0), T1 = tband(trow, k1);
+            const TB T0 = tband(trow, k0), T1 = tband(trow, k1);
             const U4 w = philox_rl(base + (uint32_t)m, a.sweep, real, w3, a.key0, a.key1);
             if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, to[k0], w.x, w.y);
             if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, to[k1], w.z, w.w);
@@ -363,9 +417,9 @@ struct RlWave {
     }
 };
 
-template <bool ALIGNED, bool ENERGY>
+template <bool ALIGNED, bool ENERGY, bool DIR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kRlWaves))) void k_sweep_rl(
-    RlArgs a, const uint2* __restrict__ cells, const TBand* __restrict__ tb, const float* __restrict__ src,
+    RlArgs a, const uint2* __restrict__ cells, const void* __restrict__ tbv, const float* __restrict__ src,
     float* __restrict__ dst, long long* __restrict__ epart)
 {
     // XCD-aware order: workgroup g runs on XCD g % 8; consecutive items (adjacent bands) go to the same XCD.
@@ -375,7 +429,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
     const uint32_t item = xcd < rem ? xcd * (per + 1u) + k : rem * (per + 1u) + (xcd - rem) * per + k;
     if (item >= N) return;
     const int64_t group = (int64_t)(item / ((uint32_t)a.nbands * (uint32_t)a.nseg)) * ((int64_t)a.H * a.W * 256);
-    RlWave<kRlBand, ALIGNED, ENERGY> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
+    using TB = typename RlWave<kRlBand, ALIGNED, ENERGY, DIR>::TB;
+    const TB* tb = static_cast<const TB*>(tbv);
+    RlWave<kRlBand, ALIGNED, ENERGY, DIR> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
                                        reinterpret_cast<char*>(dst) + group};
     w.band = (int)(item % (uint32_t)a.nbands);
     const uint32_t rest = item / (uint32_t)a.nbands;
@@ -523,16 +579,27 @@ hipError_t launch_rl_accumulate(const float* S, const uint8_t* mask, int64_t HW,
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const float* src, float* dst,
-                           long long* epart, hipStream_t s)
+hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb, const TBandDir* tbd, const float* src,
+                           float* dst, long long* epart, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
     const bool aligned = a.tb_w % kRlBand == 0;
     const dim3 grid((unsigned)a.n_items);
-    if (aligned && epart) hipLaunchKernelGGL((k_sweep_rl<true, true>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
-    else if (aligned) hipLaunchKernelGGL((k_sweep_rl<true, false>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
-    else if (epart) hipLaunchKernelGGL((k_sweep_rl<false, true>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
-    else hipLaunchKernelGGL((k_sweep_rl<false, false>), grid, dim3(64), 0, s, a, cells, tb, src, dst, epart);
+    const void* t = tbd ? static_cast<const void*>(tbd) : static_cast<const void*>(tb);
+#define MPR_RL_LAUNCH(AL, EN, DI) \
+    hipLaunchKernelGGL((k_sweep_rl<AL, EN, DI>), grid, dim3(64), 0, s, a, cells, t, src, dst, epart)
+    if (tbd) {
+        if (aligned && epart) MPR_RL_LAUNCH(true, true, true);
+        else if (aligned) MPR_RL_LAUNCH(true, false, true);
+        else if (epart) MPR_RL_LAUNCH(false, true, true);
+        else MPR_RL_LAUNCH(false, false, true);
+    } else {
+        if (aligned && epart) MPR_RL_LAUNCH(true, true, false);
+        else if (aligned) MPR_RL_LAUNCH(true, false, false);
+        else if (epart) MPR_RL_LAUNCH(false, true, false);
+        else MPR_RL_LAUNCH(false, false, false);
+    }
+#undef MPR_RL_LAUNCH
     return hipGetLastError();
 }
 
