@@ -274,6 +274,7 @@ def main():
     }
     if extras_inputs is not None:
         out["sst"] = bench_sst(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
+        out["directional"] = bench_directional(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
         del state
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(extras_inputs[0], cT, ce, dev)
@@ -282,6 +283,46 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, lb)
     print(json.dumps(out), flush=True)
+
+
+def bench_directional(sc, cT, ce, dev, state, R, lb, cfg, n_gap, bst_errs):
+    """The directional coupling (the extension suggested in Sec. 4) on the headline input: per block a temperature
+    for the horizontal and one for the vertical sample bonds, the same simulation otherwise (AUTO, 1 sampling sweep);
+    one warm-up and one timed step (map, directional calibration, simulate, predict, validate)."""
+    import dataclasses
+
+    import torch
+
+    import paper_2212_01317_amd as mpr
+    L = sc.z_obs.shape[0]
+    z = torch.from_numpy(sc.z_obs).to(dev)
+    mask = torch.from_numpy(sc.mask).to(dev)
+    truth = torch.from_numpy(sc.z_true).to(dev)
+    evm = torch.from_numpy(sc.eval_mask).to(dev)
+    c_dir = dataclasses.replace(cfg, coupling=mpr.COUPLING_DIRECTIONAL, sweep_kernel=mpr.SWEEP_AUTO)
+    ws = torch.empty(mpr.lib().mpr_simulate_workspace_bytes(L, L, lb[0], lb[1], ctypes.byref(c_dir.to_c())),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        t, rng = mpr.mpr_map_angles(z, mask)
+        Tx, Ty = mpr.mpr_calibrate_directional(t, mask, lb[0], lb[1], cT, ce)
+        sim = mpr.mpr_simulate(t, mask, torch.stack([Tx, Ty]), lb[0], lb[1], c_dir, state=state, workspace=ws)
+        zhat = mpr.mpr_predict(sim.acc, z, mask, R * c_dir.n_samp, rng)
+        return sim, mpr.mpr_validate(zhat, truth, evm)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim, err = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    e = err.cpu().numpy()
+    upd = R * n_gap * (sim.sweeps + c_dir.n_samp)
+    log(f"[bench] directional: {sim.sweeps} + 1 sweeps in {el:.3f}s ({upd / el:.3e} upd/s), AAE {e[0]:.5f} "
+        f"RASE {e[1]:.5f} (BST {bst_errs[0]:.5f} / {bst_errs[1]:.5f})")
+    return {"workload": "headline input, directional coupling (Tx, Ty per block), AUTO, 1 sampling sweep",
+            "seconds_per_step": el, "sweeps": sim.sweeps + c_dir.n_samp, "updates_per_s": upd / el,
+            "aae": float(e[0]), "rase": float(e[1]), "bst_aae": float(bst_errs[0]), "bst_rase": float(bst_errs[1])}
 
 
 def bench_sst(sc, cT, ce, dev, state, R, lb, cfg, n_gap, bst_errs):

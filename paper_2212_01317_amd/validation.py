@@ -4,7 +4,8 @@ For a complete field and each missing-data ratio p, M masks remove round(p H W) 
 method predicts the removed pixels from the rest; AAE and RASE (Eq. 3, Eq. 4) over the removed pixels are averaged
 over the masks (MAAE, MRASE), next to the mean time of one prediction (map, temperatures, simulation, conditional
 mean) on the device.  Methods: MPR (one global temperature, uniform random start), SV-MPR with block temperatures
-(BST, Sec. 2.2.2; BST-DC: the same in the double-checkerboard order) and with site temperatures (SST, Sec. 2.2.3);
+(BST, Sec. 2.2.2; BST-DC: the same in the double-checkerboard order; BST-DIR: one temperature per bond direction
+and block, the directional coupling suggested in Sec. 4) and with site temperatures (SST, Sec. 2.2.3);
 for the SV-MPR methods every block size of `blocks`, and for SST every smoothing count of `ns` (the l_b and n_s
 studies of Fig. 11).  Every step runs in the library; this module only draws the masks and orders the calls.
 
@@ -12,7 +13,8 @@ studies of Fig. 11).  Every step runs in the library; this module only draws the
     python -m paper_2212_01317_amd.validation --L 1024 --M 10 --p 0.3,0.8 --field ns --blocks 8,16,32,64
 
 prints one JSON object per (p, method, block, n_s).  The paper's data sets are not available; the fields are seeded
-stand-ins: `synth.skewed_field` (default) or the plain non-stationary field `synth.ns_field` (--field ns).
+stand-ins: `synth.skewed_field` (default), the plain non-stationary field `synth.ns_field` (--field ns), or a field
+with geometric anisotropy `synth.grf_aniso` (--field aniso: correlation lengths 16 along x and 2 along y).
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ from . import INIT_BLOCK_MEAN, INIT_RANDOM, ORDER_DC, mpr_validate, predict, ref
 from . import synth
 
 METHODS = ("MPR", "BST", "SST")
-ALL_METHODS = ("MPR", "BST", "SST", "BST-DC")
+ALL_METHODS = ("MPR", "BST", "SST", "BST-DC", "BST-DIR")
 
 
 @dataclass
@@ -63,6 +65,8 @@ def predict_method(method: str, z: torch.Tensor, mask: torch.Tensor, s: Setting,
         return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, sst=(s.r_s, s.n_s), **common)
     if method == "BST-DC":
         return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, order=ORDER_DC, **common)
+    if method == "BST-DIR":
+        return predict(z, mask, block=(s.block, s.block), init_mode=INIT_BLOCK_MEAN, directional=True, **common)
     raise ValueError(f"unknown method {method}")
 
 
@@ -123,12 +127,14 @@ def main():
     ap.add_argument("--n-real", type=int, default=10)
     ap.add_argument("--blocks", type=str, default="32", help="block sizes l_b of the SV-MPR methods")
     ap.add_argument("--ns", type=str, default="5", help="smoothing counts n_s of SST")
-    ap.add_argument("--field", choices=("skewed", "ns"), default="skewed")
+    ap.add_argument("--field", choices=("skewed", "ns", "aniso"), default="skewed")
     ap.add_argument("--field-seed", type=int, default=synth.seed_for(6, synth.ROLE_FIELD))
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
     if a.field == "skewed":
         field = synth.skewed_field(a.L, a.field_seed)
+    elif a.field == "aniso":
+        field = synth.grf_aniso(a.L, a.L, 16.0, 2.0, np.random.default_rng(a.field_seed)).astype(np.float32)
     else:
         field = synth.ns_field(a.L, a.L, 4, (2.0, 32.0), np.random.default_rng(a.field_seed)).astype(np.float32)
     rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),

@@ -21,12 +21,15 @@ def _oracle_errors(field, mask, method, s, cT, ce, scene):
     else:
         lb, init = (s.block, s.block), 1
     T, _, _ = oracle.calibrate_temperature(t, mask, lb[0], lb[1], cT, ce)
-    t_mode, order = 0, 1 if method == "BST-DC" else 0
+    t_mode, order, directional = 0, 1 if method == "BST-DC" else 0, 0
+    if method == "BST-DIR":
+        T = np.concatenate([x.ravel() for x in oracle.calibrate_directional(t, mask, lb[0], lb[1], cT, ce)])
+        directional = 1
     if method == "SST":
         T = oracle.sst_temperatures(T, H, W, lb[0], lb[1], r_s=s.r_s, n_s=s.n_s)
         t_mode = 1
     cfg = OCfg(n_real=s.n_real, init_mode=init, stop_mode=1, n_samp=s.n_samp, n_max=s.n_max, seed=s.seed,
-               scene=scene, t_mode=t_mode, order=order)
+               scene=scene, t_mode=t_mode, order=order, directional=directional)
     r = oracle.simulate(t, mask, T, lb[0], lb[1], cfg)
     zhat = oracle.predict(r.acc, z, mask, s.n_real * s.n_samp, rg)
     return oracle.validate(zhat, field, (1 - mask).astype(np.uint8))
