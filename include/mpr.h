@@ -94,7 +94,7 @@ typedef struct {
                              at temperature Tx); temperatures below 1e-3 J are raised to fl32(1e-3 J).  Runs in the
                              single-checkerboard order with block temperatures on the realization-lane kernel (AUTO
                              selects it; TILES is refused); the energy series stays the unweighted Eq. (1) energy per
-                             bond.  mpr_simulate only. */
+                             bond.  mpr_simulate only; sides below 65536 (MPR_ERR_SHAPE otherwise). */
 } mpr_sim_config;
 
 /* Sec. 2.1, first step: linear map of the samples onto spin angles.  zmin and zmax are taken over the samples;

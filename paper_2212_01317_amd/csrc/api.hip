@@ -714,8 +714,8 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 0) return fail(MPR_ERR_INVALID_ARG, "n_eq must be >= 0");
     if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
-    if (c.sweep_kernel == MPR_SWEEP_LANES && (H >= 65536 || W >= 65536))
-        return fail(MPR_ERR_SHAPE, "the realization-lane sweep needs sides below 65536");
+    if ((c.sweep_kernel == MPR_SWEEP_LANES || c.coupling == MPR_COUPLING_DIRECTIONAL) && (H >= 65536 || W >= 65536))
+        return fail(MPR_ERR_SHAPE, "the realization-lane sweep (and the directional coupling) needs sides below 65536");
     st = check_ws(workspace, ws_bytes, mpr_simulate_workspace_bytes(H, W, lb_h, lb_w, cfg));
     if (st != MPR_OK) return st;
 
