@@ -71,12 +71,21 @@ def hbm_profile(kernel: str) -> str:
     return os.path.join(ROOT, "profiles", f"{kernel}_c3_p0.6_hbm.txt")
 
 
+def code_text(src: str) -> str:
+    """C++ source without comments, trailing blanks and blank lines (what a counter summary's hash covers, so that
+    editing a comment does not invalidate a measurement)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def sweep_sources_sha256(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
     for name in SWEEP_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2212_01317_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2212_01317_amd", "csrc", name)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()
 
 

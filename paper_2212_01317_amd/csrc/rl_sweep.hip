@@ -7,13 +7,16 @@
 // counter and its neighbourhood are the same for the whole wave.  They are scalar data, decided by the scalar
 // unit, and no lane idles on a sample site.
 //
-// A wave owns a band of 16 columns [x0, x0 + 16) and a segment of rows [ys, ye) of one group of 64 realizations,
-// and streams the rows downwards with a window of four rows in registers (angle, cos, sin of each site of columns
-// x0 - 2 .. x0 + 17).  Step y updates colour 0 of row y and then colour 1 of row y - 1, whose colour-0 neighbours
-// (rows y - 2 .. y) are then current, and writes row y - 1.  Colour 0 is also updated one site outside the band
-// (columns x0 - 1, x0 + 16) and one row outside the segment (rows ys - 1, ye): these updates use the same
-// counter-based random numbers and the same inputs as in the wave that owns the site, so they are bit-identical to
-// it, and the two columns beyond (x0 - 2, x0 + 17) are read only.  Sweep k reads `src` and writes `dst`.
+// A wave owns a band of B = kRlBand columns [x0, x0 + B) and a segment of rows [ys, ye) of one group of 64
+// realizations, and streams the rows downwards with a window of four rows in registers: (cos, sin) of each site of
+// columns x0 - 2 .. x0 + B + 1.  Step y updates colour 0 of row y and then colour 1 of row y - 1, whose colour-0
+// neighbours (rows y - 2 .. y) are then current; every update writes its cell at once.  Colour 0 is also updated
+// one site outside the band (columns x0 - 1, x0 + B) and one row outside the segment (rows ys - 1, ye): these
+// updates use the same counter-based random numbers and the same inputs as in the wave that owns the site, so they
+// are bit-identical to it (and so are the duplicate writes), and the two columns beyond (x0 - 2, x0 + B + 1) are
+// read only.  Sweep k reads `src` and writes `dst`; both hold the sample angles at the sample sites.  The old angle of
+// a cell comes from `src` when the cell is updated; the rare exact decision reads the neighbours' angles from memory
+// (colour-1 neighbours from `src`, colour-0 neighbours, already updated, from `dst`).
 //
 // The update, the decision (FP32 filter, exact FP64 test inside its error band), the random numbers and the
 // fixed-point energy of each colour-1 site are those of the fused sweep, so the chains, the energy series and the
@@ -313,7 +316,6 @@ struct RlWave {
             const bool g0 = in0 && ((gap[SO] >> k0) & 1u);
             const bool g1 = in1 && ((gap[SO] >> k1) & 1u);
             if (!(g0 || g1)) continue;
-            // old angles of the pair (a cell outside the grid reads its in-grid partner instead)
             const TB T0 = tband(trow, k0), T1 = tband(trow, k1);
             const U4 w = philox_rl(base + (uint32_t)m, a.sweep, real, w3, a.key0, a.key1);
             if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, to[k0], w.x, w.y);
