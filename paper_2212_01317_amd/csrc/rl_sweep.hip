@@ -8,15 +8,16 @@
 // unit, and no lane idles on a sample site.
 //
 // A wave owns a band of B = kRlBand columns [x0, x0 + B) and a segment of rows [ys, ye) of one group of 64
-// realizations, and streams the rows downwards with a window of four rows in registers: (cos, sin) of each site of
-// columns x0 - 2 .. x0 + B + 1.  Step y updates colour 0 of row y and then colour 1 of row y - 1, whose colour-0
-// neighbours (rows y - 2 .. y) are then current; every update writes its cell at once.  Colour 0 is also updated
-// one site outside the band (columns x0 - 1, x0 + B) and one row outside the segment (rows ys - 1, ye): these
-// updates use the same counter-based random numbers and the same inputs as in the wave that owns the site, so they
-// are bit-identical to it (and so are the duplicate writes), and the two columns beyond (x0 - 2, x0 + B + 1) are
-// read only.  Sweep k reads `src` and writes `dst`; both hold the sample angles at the sample sites.  The old angle of
-// a cell comes from `src` when the cell is updated; the rare exact decision reads the neighbours' angles from memory
-// (colour-1 neighbours from `src`, colour-0 neighbours, already updated, from `dst`).
+// realizations, and streams the rows downwards with a window of four rows in registers: the angle as loaded and
+// (cos, sin) of each site of columns x0 - 2 .. x0 + B + 1.  Step y updates colour 0 of row y and then colour 1 of
+// row y - 1, whose colour-0 neighbours (rows y - 2 .. y) are then current; every update writes its cell at once.
+// A row is requested two steps before it is updated, into the slot it then occupies, and its loaded angles are the
+// old angles of its updates, so nothing is read twice.  Colour 0 is also updated one site outside the band
+// (columns x0 - 1, x0 + B) and one row outside the segment (rows ys - 1, ye): these updates use the same
+// counter-based random numbers and the same inputs as in the wave that owns the site, so they are bit-identical to
+// it (and so are the duplicate writes), and the two columns beyond (x0 - 2, x0 + B + 1) are read only.  Sweep k reads `src` and writes `dst`; both hold the sample angles at the sample sites.  The rare exact
+// decision reads the neighbours' angles from memory (colour-1 neighbours from `src`, colour-0 neighbours, already
+// updated, from `dst`).
 //
 // The update, the decision (FP32 filter, exact FP64 test inside its error band), the random numbers and the
 // fixed-point energy of each colour-1 site are those of the fused sweep, so the chains, the energy series and the
@@ -72,8 +73,14 @@ __device__ __forceinline__ U4 philox_rl(uint32_t c0, uint32_t c1, uint32_t c2, u
     return U4{c0, c1, c2, c3};
 }
 
+// How a window column finds its temperature column: TM_ALIGNED when the blocks are a multiple of the band wide
+// (the owned columns share one temperature column, each ring column may have its own), TM_TWO when the blocks are
+// at least kRlBand + 3 wide (the window spans at most two temperature columns: those below `jsplit` take `bca`, the
+// others `bcb`), TM_ANY otherwise (one division per column).
+enum { TM_ANY = 0, TM_ALIGNED = 1, TM_TWO = 2 };
+
 // DIR: directional coupling (a temperature per bond direction, table TBandDir); else one temperature (TBand).
-template <int KB, bool ALIGNED, bool ENERGY, bool DIR>
+template <int KB, int TM, bool ENERGY, bool DIR>
 struct RlWave {
     static constexpr int kB = KB;          // columns owned by the wave
     static constexpr int kWC = KB + 4;     // window columns x0 - 2 .. x0 + KB + 1
@@ -92,14 +99,14 @@ struct RlWave {
     // window of (cos, sin), slot = row & 3
     float c[4][kWC], s[4][kWC];
     uint32_t gap[4], smp[4];           // per slot: gap / sample bits of the window columns
-    float pf[kWC];                     // angles of the next row, requested one step ahead
-    float to0[kWC], to1[kWC];          // old angles of the cells updated in the step (colour 0 of row y, colour 1
-                                       // of row y - 1), loaded at its start
+    float ang[4][kWC];                 // per slot: the angles of the row as loaded (requested two steps ahead);
+                                       // they are the old angles of the row's updates
     uint32_t pgap, psmp;
     int brow, brem;                    // temperature row of the step's row y, and y - brow tb_h
     const TB* trow0;                   // temperature rows of y and y - 1 (clamped into the grid)
     const TB* trow1;
-    int bc, bcl, bcr;                  // ALIGNED: temperature columns of the owned columns and of the two ring columns
+    int bc, bcl, bcr;                  // TM_ALIGNED: temperature columns of the owned columns and of the two ring columns
+    int bca, bcb, jsplit;              // TM_TWO: the two temperature columns and the first window column of bcb
     long long e_acc;
 
     // the lane's element of window column j of the row at byte offset off (wave-uniform base + lane offset + an
@@ -133,7 +140,8 @@ struct RlWave {
     }
 
     // Requests the angles of the cells of row y that lie inside the grid (gap and sample cells alike: both state
-    // buffers hold the sample angles).
+    // buffers hold the sample angles) into slot S.
+    template <int S>
     __device__ __forceinline__ void request(int y, int64_t off)
     {
         const uint2 b = row_bits(y);
@@ -142,40 +150,36 @@ struct RlWave {
         const uint32_t in = pgap | psmp;
         if (in == kAll) {
 #pragma unroll
-            for (int j = 0; j < kWC; ++j) pf[j] = ld(src, off, j);
+            for (int j = 0; j < kWC; ++j) ang[S][j] = ld(src, off, j);
         } else {
 #pragma unroll
             for (int j = 0; j < kWC; ++j)
-                if ((in >> j) & 1u) pf[j] = ld(src, off, j);
+                if ((in >> j) & 1u) ang[S][j] = ld(src, off, j);
         }
     }
 
-    // Row y enters slot S: (cos, sin) of the requested angles; cells outside the grid get (0, 0).
+    // Row y enters slot S: (cos, sin) of the requested angles; cells outside the grid get (0, 0).  The (cos, sin)
+    // of every window column are computed from whatever the slot holds and then cleared outside the grid, so that
+    // the common case writes the slot once.
     template <int S>
     __device__ __forceinline__ void arrive()
     {
         gap[S] = pgap;
         smp[S] = psmp;
+#pragma unroll
+        for (int j = 0; j < kWC; ++j) {
+            const float t = a.q * ang[S][j];
+            c[S][j] = cos_rev(t);
+            s[S][j] = sin_rev(t);
+        }
         const uint32_t in = pgap | psmp;
-        if (in == kAll) {
+        if (in != kAll) {
 #pragma unroll
-            for (int j = 0; j < kWC; ++j) {
-                const float ang = a.q * pf[j];
-                c[S][j] = cos_rev(ang);
-                s[S][j] = sin_rev(ang);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kWC; ++j) {
-                if ((in >> j) & 1u) {
-                    const float ang = a.q * pf[j];
-                    c[S][j] = cos_rev(ang);
-                    s[S][j] = sin_rev(ang);
-                } else {
+            for (int j = 0; j < kWC; ++j)
+                if (!((in >> j) & 1u)) {
                     c[S][j] = 0.0f;
                     s[S][j] = 0.0f;
                 }
-            }
         }
     }
 
@@ -197,53 +201,20 @@ struct RlWave {
         if constexpr (DIR) return update_directional<COL, SO, SU, SD>(T, y, off, j, to, tp, ui, cp, sp, co, so, Cx, Sy);
         else {
         const float X = fmaf(cp - co, Cx, (sp - so) * Sy);
-        // The FP32 filter with a wave-uniform temperature, as one comparison of (lhs, rhs) with a tolerance: accept
-        // iff lhs < rhs, exact FP64 test iff |lhs - rhs| <= tol.  T > 0: (ui, w24, the error band of w24);
-        // T = 0: (dE, 0, delta), where dE < 0 and dE <= 0 differ only at dE = 0, which lies inside the band.
-        float lhs, rhs, tol;
+        // The FP32 filter with a wave-uniform temperature as a signed margin r and a tolerance: accept iff r < 0,
+        // exact FP64 test iff |r| <= tol.  T > 0: r = ui - w24 (its sign is that of the exact difference, and it is
+        // 0 only when ui = w24) within the error band of w24; T = 0: r = dE within delta (dE < 0 and dE <= 0 differ
+        // only at dE = 0, which lies inside the band).
+        float r, tol;
         if (T.T > 0.0f) {
             const float w24 = exp2_fast(fminf(fmaf(X, T.kappa, 24.0f), 25.0f));
-            lhs = ui;
-            rhs = w24;
+            r = ui - w24;
             tol = fmaf(w24, fmaf(fabsf(X), T.kb, T.band), 0.015625f);
         } else {
-            lhs = -a.J * X;
-            rhs = 0.0f;
+            r = -a.J * X;
             tol = a.delta_e;
         }
-        const bool acc = lhs < rhs;
-        float tn = acc ? tp : to;
-        float cf = acc ? cp : co, sf = acc ? sp : so;
-        if (fabsf(lhs - rhs) <= tol) {
-            // rare: the exact decision from the neighbours' angles; an absent neighbour reads the cell itself
-            // (in the grid) and is excluded by `pres`
-            const int x = x0 - 2 + j;
-            const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
-            const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
-            const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
-            float nu, nl, nr, nd;
-            if (COL == 0) {
-                nu = ld(src, ou, j);
-                nl = ld(src, off, jl);
-                nr = ld(src, off, jr);
-                nd = ld(src, od, j);
-            } else {
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                nu = ld_coherent(dst, ou, j);
-                nl = ld_coherent(dst, off, jl);
-                nr = ld_coherent(dst, off, jr);
-                nd = ld_coherent(dst, od, j);
-            }
-            const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
-            const bool ex = exact64(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.T, ui * 5.9604644775390625e-8f);
-            tn = ex ? tp : to;
-            cf = ex ? cp : co;
-            sf = ex ? sp : so;
-        }
-        c[SO][j] = cf;
-        s[SO][j] = sf;
-        st(off, j, tn);
-        return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
+        return decide<COL, SO>(r, tol, T, y, off, j, to, tp, ui, cp, sp, Cx, Sy);
         }
     }
 
@@ -260,50 +231,72 @@ struct RlWave {
         const float Xv = fmaf(cp - co, Cv, (sp - so) * Sv);
         const float w24 = exp2_fast(fminf(fmaf(Xh, T.kx, fmaf(Xv, T.ky, 24.0f)), 25.0f));
         const float tol = fmaf(w24, fmaf(fabsf(Xh), T.kbx, fmaf(fabsf(Xv), T.kby, T.band)), 0.015625f);
-        const bool acc = ui < w24;
-        float tn = acc ? tp : to;
-        float cf = acc ? cp : co, sf = acc ? sp : so;
-        if (fabsf(ui - w24) <= tol) {
-            const int x = x0 - 2 + j;
-            const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
-            const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
-            const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
-            float nu, nl, nr, nd;
-            if (COL == 0) {
-                nu = ld(src, ou, j);
-                nl = ld(src, off, jl);
-                nr = ld(src, off, jr);
-                nd = ld(src, od, j);
-            } else {
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                nu = ld_coherent(dst, ou, j);
-                nl = ld_coherent(dst, off, jl);
-                nr = ld_coherent(dst, off, jr);
-                nd = ld_coherent(dst, od, j);
-            }
-            const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
-            const bool ex = exact64_directional(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.Tx, T.Ty,
-                                                ui * 5.9604644775390625e-8f);
-            tn = ex ? tp : to;
-            cf = ex ? cp : co;
-            sf = ex ? sp : so;
+        return decide<COL, SO>(ui - w24, tol, T, y, off, j, to, tp, ui, cp, sp, Cx, Sy);
+    }
+
+    // Completes the update of window column j of row y (slot SO) from the filter's margin r (accept iff r < 0)
+    // and tolerance: where a lane has |r| <= tol, the whole wave reads the neighbours' angles and runs the exact
+    // test, and those lanes take its decision (r = -1 or 1).  Then the window cell, the stored angle and the
+    // fixed-point energy of the site's bonds.
+    template <int COL, int SO>
+    __device__ __forceinline__ int decide(float r, float tol, const TB& T, int y, int64_t off, int j, float to,
+                                          float tp, float ui, float cp, float sp, float Cx, float Sy)
+    {
+        const bool need = fabsf(r) <= tol;
+        if (__builtin_amdgcn_ballot_w64(need) != 0) {
+            const bool ex = exact_at<COL>(T, y, off, j, tp, to, ui);
+            r = need ? (ex ? -1.0f : 1.0f) : r;
         }
+        const bool acc = r < 0.0f;
+        const float cf = acc ? cp : c[SO][j], sf = acc ? sp : s[SO][j];
         c[SO][j] = cf;
         s[SO][j] = sf;
-        st(off, j, tn);
+        st(off, j, acc ? tp : to);
         return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
+    }
+
+    // The exact decision of the update of window column j of row y: the neighbours' angles from memory (colour-0
+    // cells: colour-1 neighbours from src; colour-1 cells: colour-0 neighbours, written earlier in this launch,
+    // from dst through the device-coherent path), then the FP64 test.  An absent neighbour reads the cell itself
+    // (in the grid) and is excluded by `pres`.
+    template <int COL>
+    __device__ __forceinline__ bool exact_at(const TB& T, int y, int64_t off, int j, float tp, float to,
+                                             float ui) const
+    {
+        const int x = x0 - 2 + j;
+        const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
+        const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
+        const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
+        float nu, nl, nr, nd;
+        if (COL == 0) {
+            nu = ld(src, ou, j);
+            nl = ld(src, off, jl);
+            nr = ld(src, off, jr);
+            nd = ld(src, od, j);
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            nu = ld_coherent(dst, ou, j);
+            nl = ld_coherent(dst, off, jl);
+            nr = ld_coherent(dst, off, jr);
+            nd = ld_coherent(dst, od, j);
+        }
+        const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
+        const float u = ui * 5.9604644775390625e-8f;
+        if constexpr (DIR) return exact64_directional(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.Tx, T.Ty, u);
+        else return exact64(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.T, u);
     }
 
     __device__ __forceinline__ TB tband(const TB* trow, int j) const
     {
-        if (ALIGNED) return trow[j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)];
+        if (TM == TM_ALIGNED) return trow[j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)];
+        if (TM == TM_TWO) return j < jsplit ? trow[bca] : trow[bcb];
         return trow[bcol(j)];
     }
 
     // Colour COL of the row in slot SO (grid row y): the pairs of groups m0 + MLO .. m0 + MHI, sites restricted to
     // window columns [JLO, JHI).  PAR = (y + COL) & 1, the column offset of the colour inside a group of four.
     template <int COL, int PAR, int SO, int SU, int SD, int MLO, int MHI, int JLO, int JHI>
-    __device__ __forceinline__ int colour(const TB* trow, int y, int64_t off, const float* to)
+    __device__ __forceinline__ int colour(const TB* trow, int y, int64_t off)
     {
         const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COL);
         const uint32_t base = (uint32_t)y * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
@@ -318,25 +311,10 @@ struct RlWave {
             if (!(g0 || g1)) continue;
             const TB T0 = tband(trow, k0), T1 = tband(trow, k1);
             const U4 w = philox_rl(base + (uint32_t)m, a.sweep, real, w3, a.key0, a.key1);
-            if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, to[k0], w.x, w.y);
-            if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, to[k1], w.z, w.w);
+            if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, ang[SO][k0], w.x, w.y);
+            if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, ang[SO][k1], w.z, w.w);
         }
         return e;
-    }
-
-    // Old angles of the gap cells of one colour of a row (columns PAR, PAR + 2, ... in [JLO, JHI)): all of them
-    // when the row lies inside the grid, else the gap cells only.
-    template <int PAR, int JLO, int JHI>
-    __device__ __forceinline__ void old_angles(uint32_t g, uint32_t sm, int64_t off, float* to) const
-    {
-        if ((g | sm) == kAll) {
-#pragma unroll
-            for (int j = JLO + ((JLO + PAR) & 1); j < JHI; j += 2) to[j] = ld(src, off, j);
-        } else {
-#pragma unroll
-            for (int j = JLO + ((JLO + PAR) & 1); j < JHI; j += 2)
-                if ((g >> j) & 1u) to[j] = ld(src, off, j);
-        }
     }
 
     // Energy / J (fixed point) of the bonds of the colour-1 sample cells of the row in slot SO among the owned
@@ -357,6 +335,7 @@ struct RlWave {
     }
 
     // One step (P = y & 3): row y + 1 arrives, row y + 2 is requested, colour 0 of row y, colour 1 of row y - 1.
+    // The old angles of the step's updates are those its rows were loaded with.
     template <int P>
     __device__ __forceinline__ void step(int y)
     {
@@ -368,20 +347,18 @@ struct RlWave {
             ++brow;
         }
         trow0 = tb + (int64_t)(brow < 0 ? 0 : (brow >= a.nby_t ? a.nby_t - 1 : brow)) * a.nbx_t;
+        // keeps the per-column choice of TM_TWO from being hoisted out of the row loop as a table of pointers
+        if (TM == TM_TWO) asm volatile("" : "+s"(jsplit));
         offy += wrow;
         // row parity: y & 1 = P & 1, so colour 0 of row y and colour 1 of row y - 1 have column offset P & 1.
-        // The old angles of this step's cells are requested before the next row, so that waiting for them does
-        // not wait for the next row's loads.
         const int y1 = y - 1;
         const bool do0 = y >= 0 && y < a.H, do1 = y1 >= ys && y1 < ye;
-        if (do0) old_angles<P & 1, 1, kWC - 1>(gap[S0], smp[S0], offy, to0);
-        if (do1) old_angles<P & 1, 2, kWC - 2>(gap[SU], smp[SU], offy - wrow, to1);
         arrive<SD>();
-        if (y + 2 <= ye + 1) request(y + 2, offy + 2 * wrow);
+        if (y + 2 <= ye + 1) request<S2>(y + 2, offy + 2 * wrow);
         else pgap = psmp = 0u;
-        if (do0) colour<0, P & 1, S0, SU, SD, -1, kB / 4, 1, kWC - 1>(trow0, y, offy, to0);
+        if (do0) colour<0, P & 1, S0, SU, SD, -1, kB / 4, 1, kWC - 1>(trow0, y, offy);
         if (do1) {
-            int e = colour<1, P & 1, SU, S2, S0, 0, kB / 4 - 1, 2, kWC - 2>(trow1, y1, offy - wrow, to1);
+            int e = colour<1, P & 1, SU, S2, S0, 0, kB / 4 - 1, 2, kWC - 2>(trow1, y1, offy - wrow);
             if (ENERGY) e += sample_energy<P & 1, SU, S2, S0>();
             e_acc += e;
         }
@@ -390,7 +367,15 @@ struct RlWave {
     __device__ __forceinline__ void run()
     {
         e_acc = 0;
-        if (ALIGNED) {
+        if (TM == TM_TWO) {
+            bca = bcol(0);
+            bcb = bcol(kWC - 1);
+            jsplit = 0;
+            if (bca != bcb)
+                for (int j = 0; j < kWC; ++j) jsplit += bcol(j) == bca ? 1 : 0;
+            jsplit = __builtin_amdgcn_readfirstlane(jsplit);
+        }
+        if (TM == TM_ALIGNED) {
             bc = x0 / a.tb_w;
             bcl = x0 % a.tb_w == 0 && bc > 0 ? bc - 1 : bc;
             bcr = (x0 + kB) % a.tb_w == 0 && bc + 1 < a.nbx_t ? bc + 1 : bc;
@@ -399,14 +384,18 @@ struct RlWave {
         brow = (ys - 2 + a.tb_h) / a.tb_h - 1;
         brem = (ys - 2 + a.tb_h) % a.tb_h;
         trow0 = tb;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < kWC; ++j) ang[i][j] = 0.0f;
         wrow = (int64_t)a.W * 256;
         offy = ((int64_t)(ys - 2) * a.W + (x0 - 2)) * 256;   // row ys - 2; the first step moves it to ys - 1
         // rows ys - 2 and ys - 1 into their slots (ys is a multiple of 4: slots 2 and 3), row ys requested
-        request(ys - 2, offy);
+        request<2>(ys - 2, offy);
         arrive<2>();
-        request(ys - 1, offy + wrow);
+        request<3>(ys - 1, offy + wrow);
         arrive<3>();
-        request(ys, offy + 2 * wrow);
+        request<0>(ys, offy + 2 * wrow);
         for (int yb = ys - 1; yb <= ye; yb += 4) {
             step<3>(yb);
             if (yb + 1 > ye) break;
@@ -419,7 +408,7 @@ struct RlWave {
     }
 };
 
-template <bool ALIGNED, bool ENERGY, bool DIR>
+template <int TM, bool ENERGY, bool DIR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kRlWaves))) void k_sweep_rl(
     RlArgs a, const uint2* __restrict__ cells, const void* __restrict__ tbv, const float* __restrict__ src,
     float* __restrict__ dst, long long* __restrict__ epart)
@@ -431,9 +420,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
     const uint32_t item = xcd < rem ? xcd * (per + 1u) + k : rem * (per + 1u) + (xcd - rem) * per + k;
     if (item >= N) return;
     const int64_t group = (int64_t)(item / ((uint32_t)a.nbands * (uint32_t)a.nseg)) * ((int64_t)a.H * a.W * 256);
-    using TB = typename RlWave<kRlBand, ALIGNED, ENERGY, DIR>::TB;
+    using TB = typename RlWave<kRlBand, TM, ENERGY, DIR>::TB;
     const TB* tb = static_cast<const TB*>(tbv);
-    RlWave<kRlBand, ALIGNED, ENERGY, DIR> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
+    RlWave<kRlBand, TM, ENERGY, DIR> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
                                        reinterpret_cast<char*>(dst) + group};
     w.band = (int)(item % (uint32_t)a.nbands);
     const uint32_t rest = item / (uint32_t)a.nbands;
@@ -585,22 +574,25 @@ hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb,
                            float* dst, long long* epart, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    const bool aligned = a.tb_w % kRlBand == 0;
+    const int tm = a.tb_w % kRlBand == 0 ? TM_ALIGNED : (a.tb_w >= kRlBand + 3 ? TM_TWO : TM_ANY);
     const dim3 grid((unsigned)a.n_items);
     const void* t = tbd ? static_cast<const void*>(tbd) : static_cast<const void*>(tb);
-#define MPR_RL_LAUNCH(AL, EN, DI) \
-    hipLaunchKernelGGL((k_sweep_rl<AL, EN, DI>), grid, dim3(64), 0, s, a, cells, t, src, dst, epart)
+#define MPR_RL_LAUNCH(TMV, EN, DI) \
+    hipLaunchKernelGGL((k_sweep_rl<TMV, EN, DI>), grid, dim3(64), 0, s, a, cells, t, src, dst, epart)
+#define MPR_RL_LAUNCH_TM(EN, DI)                          \
+    do {                                                  \
+        if (tm == TM_ALIGNED) MPR_RL_LAUNCH(TM_ALIGNED, EN, DI); \
+        else if (tm == TM_TWO) MPR_RL_LAUNCH(TM_TWO, EN, DI);     \
+        else MPR_RL_LAUNCH(TM_ANY, EN, DI);                \
+    } while (0)
     if (tbd) {
-        if (aligned && epart) MPR_RL_LAUNCH(true, true, true);
-        else if (aligned) MPR_RL_LAUNCH(true, false, true);
-        else if (epart) MPR_RL_LAUNCH(false, true, true);
-        else MPR_RL_LAUNCH(false, false, true);
+        if (epart) MPR_RL_LAUNCH_TM(true, true);
+        else MPR_RL_LAUNCH_TM(false, true);
     } else {
-        if (aligned && epart) MPR_RL_LAUNCH(true, true, false);
-        else if (aligned) MPR_RL_LAUNCH(true, false, false);
-        else if (epart) MPR_RL_LAUNCH(false, true, false);
-        else MPR_RL_LAUNCH(false, false, false);
+        if (epart) MPR_RL_LAUNCH_TM(true, false);
+        else MPR_RL_LAUNCH_TM(false, false);
     }
+#undef MPR_RL_LAUNCH_TM
 #undef MPR_RL_LAUNCH
     return hipGetLastError();
 }
