@@ -263,7 +263,11 @@ struct RlWave {
     __device__ __forceinline__ bool exact_at(const TB& T, int y, int64_t off, int j, float tp, float to,
                                              float ui) const
     {
-        const int x = x0 - 2 + j;
+        // the band origin through an opaque copy: the per-column offsets below are then computed here, on this
+        // rare path, instead of being kept for every window column for the whole launch
+        int xb = x0;
+        asm volatile("" : "+s"(xb));
+        const int x = xb - 2 + j;
         const bool pu = y > 0, pl = x > 0, pr = x + 1 < a.W, pd = y + 1 < a.H;
         const int64_t ou = pu ? off - wrow : off, od = pd ? off + wrow : off;
         const int jl = pl ? j - 1 : j, jr = pr ? j + 1 : j;
@@ -286,11 +290,23 @@ struct RlWave {
         else return exact64(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.T, u);
     }
 
+    // The temperature entry of window column j in the row trow.  The table is read-only for the whole launch and the
+    // address is wave-uniform: it is read through the constant address space, which makes it a scalar load.
     __device__ __forceinline__ TB tband(const TB* trow, int j) const
     {
-        if (TM == TM_ALIGNED) return trow[j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)];
-        if (TM == TM_TWO) return j < jsplit ? trow[bca] : trow[bcb];
-        return trow[bcol(j)];
+        using CU = const __attribute__((address_space(4))) uint32_t;
+        const int k = TM == TM_ALIGNED ? (j == 1 ? bcl : (j == kWC - 2 ? bcr : bc))
+                                       : (TM == TM_TWO ? (j < jsplit ? bca : bcb) : bcol(j));
+        const uint64_t ad = (uint64_t)(trow + k);
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ad);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ad >> 32));
+        const CU* p = (const CU*)(lo | hi << 32);
+        uint32_t w[sizeof(TB) / 4];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(TB) / 4); ++i) w[i] = p[i];
+        TB t;
+        __builtin_memcpy(&t, w, sizeof(TB));
+        return t;
     }
 
     // Colour COL of the row in slot SO (grid row y): the pairs of groups m0 + MLO .. m0 + MHI, sites restricted to
