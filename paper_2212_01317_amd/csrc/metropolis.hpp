@@ -86,7 +86,7 @@ __device__ __forceinline__ float band_of(float T, float delta)
 __device__ __forceinline__ TBand make_tband(float T, float J, float delta)
 {
     TBand b;
-    b.T = T;
+    b.T = T > 0.0f ? T : 0.0f;      // a temperature that is not > 0 (NaN included) is held as +0
     b.kappa = T > 0.0f ? (float)((double)J * 1.4426950408889634074 / (double)T) : 0.0f;
     b.band = band_of(T, delta);
     b.kb = kBandY * b.kappa;

@@ -102,6 +102,7 @@ struct RlWave {
     float ang[4][kWC];                 // per slot: the angles of the row as loaded (requested two steps ahead);
                                        // they are the old angles of the row's updates
     uint32_t pgap, psmp;
+    uint2 nbits;                       // gap / sample bits of the next row to be requested, loaded one request ahead
     int brow, brem;                    // temperature row of the step's row y, and y - brow tb_h
     const TB* trow0;                   // temperature rows of y and y - 1 (clamped into the grid)
     const TB* trow1;
@@ -144,7 +145,10 @@ struct RlWave {
     template <int S>
     __device__ __forceinline__ void request(int y, int64_t off)
     {
-        const uint2 b = row_bits(y);
+        // rows are requested in order: the bits of row y were loaded by the previous request; load those of row
+        // y + 1 now (clamped to the last row the table holds, H + 1; rows beyond it are never requested)
+        const uint2 b = nbits;
+        nbits = row_bits(y + 1 <= a.H + 1 ? y + 1 : a.H + 1);
         pgap = b.x;
         psmp = b.y;
         const uint32_t in = pgap | psmp;
@@ -206,7 +210,8 @@ struct RlWave {
         // 0 only when ui = w24) within the error band of w24; T = 0: r = dE within delta (dE < 0 and dE <= 0 differ
         // only at dE = 0, which lies inside the band).
         float r, tol;
-        if (T.T > 0.0f) {
+        // T > 0 as a scalar integer test on the bits of T (the table holds T > 0 or +0)
+        if (__float_as_int(T.T) > 0) {
             const float w24 = exp2_fast(fminf(fmaf(X, T.kappa, 24.0f), 25.0f));
             r = ui - w24;
             tol = fmaf(w24, fmaf(fabsf(X), T.kb, T.band), 0.015625f);
@@ -407,6 +412,7 @@ struct RlWave {
         wrow = (int64_t)a.W * 256;
         offy = ((int64_t)(ys - 2) * a.W + (x0 - 2)) * 256;   // row ys - 2; the first step moves it to ys - 1
         // rows ys - 2 and ys - 1 into their slots (ys is a multiple of 4: slots 2 and 3), row ys requested
+        nbits = row_bits(ys - 2);
         request<2>(ys - 2, offy);
         arrive<2>();
         request<3>(ys - 1, offy + wrow);
