@@ -36,24 +36,48 @@ namespace {
 
 __device__ __forceinline__ int fix24(float x) { return __float2int_rn(x * 16777216.0f); }
 
-// Philox4x32-10 when only c2 differs between lanes: the uniform halves of the first three rounds stay on the
-// scalar unit; the remaining rounds use the three-input xor.
-__device__ __forceinline__ U4 philox_rl(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+// Philox4x32-10 of the counter (site, sweep, realization, w3) and key (k0, k1) when only the realization differs
+// between lanes.  The realization enters round 0 only through M1 * realization, and the result of round 0's first
+// word depends on nothing else that varies (sweep and key are fixed for a launch), so the lane parts of rounds 0 and
+// 1 are three per-lane constants: lc1 = lo(M1 r), and (lph, lpl) = M0 * (hi(M1 r) ^ sweep ^ k0).  A call then does
+// the site's half of rounds 0 and 1 (scalar, but two xors), and rounds 2..9 with the three-input xor.
+struct PhiloxLane {
+    uint32_t lc1, lph, lpl;
+};
+
+__device__ __forceinline__ PhiloxLane philox_lane(uint32_t real, uint32_t sweep, uint32_t k0)
+{
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)real;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ sweep ^ k0;
+    const uint64_t q = (uint64_t)0xD2511F53u * (uint64_t)n0;
+    return PhiloxLane{(uint32_t)p1, (uint32_t)(q >> 32), (uint32_t)q};
+}
+
+__device__ __forceinline__ U4 philox_site(uint32_t site, uint32_t w3, const PhiloxLane& L, uint32_t k0, uint32_t k1)
 {
     // keep the key schedule as per-call scalar adds instead of twenty loop-invariant registers
     asm volatile("" : "+s"(k0), "+s"(k1));
-#pragma unroll
-    for (int round = 0; round < 3; ++round) {
-        if (round > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
+    // round 0, the site's half (wave-uniform)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)site;
+    const uint32_t n2u = (uint32_t)(p0 >> 32) ^ w3 ^ k1, c3u = (uint32_t)p0;
+    // round 1: M1 * n2u is wave-uniform, M0 * (first word) is the lane constant (lph, lpl)
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    const uint64_t q1 = (uint64_t)0xCD9E8D57u * (uint64_t)n2u;
+    uint32_t c0 = ((uint32_t)(q1 >> 32) ^ k0) ^ L.lc1;
+    uint32_t c1 = (uint32_t)q1;
+    uint32_t c2 = (c3u ^ k1) ^ L.lph;
+    uint32_t c3 = L.lpl;
+    // round 2: c1 is wave-uniform
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    {
+        const uint64_t a0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t a1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(a1 >> 32) ^ (c1 ^ k0);
+        const uint32_t n2 = xor3((uint32_t)(a0 >> 32), c3, k1);
+        c1 = (uint32_t)a1;
+        c3 = (uint32_t)a0;
         c0 = n0;
         c2 = n2;
     }
@@ -61,12 +85,12 @@ __device__ __forceinline__ U4 philox_rl(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int round = 3; round < 10; ++round) {
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
+        const uint64_t a0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t a1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = xor3((uint32_t)(a1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(a0 >> 32), c3, k1);
+        c1 = (uint32_t)a1;
+        c3 = (uint32_t)a0;
         c0 = n0;
         c2 = n2;
     }
@@ -93,6 +117,7 @@ struct RlWave {
     char* dst;
     int band, x0, ys, ye, lane;
     uint32_t real;                     // global realization index of this lane
+    PhiloxLane pl;                     // the lane's constant parts of the first two Philox rounds
     uint32_t lane4;                    // byte offset of this lane inside a site's 64 realizations
     int64_t offy;                      // byte offset of (row y of the current step, window column 0) in the group
     int64_t wrow;                      // bytes per grid row: W * 256
@@ -331,7 +356,7 @@ struct RlWave {
             const bool g1 = in1 && ((gap[SO] >> k1) & 1u);
             if (!(g0 || g1)) continue;
             const TB T0 = tband(trow, k0), T1 = tband(trow, k1);
-            const U4 w = philox_rl(base + (uint32_t)m, a.sweep, real, w3, a.key0, a.key1);
+            const U4 w = philox_site(base + (uint32_t)m, w3, pl, a.key0, a.key1);
             if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, ang[SO][k0], w.x, w.y);
             if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, ang[SO][k1], w.z, w.w);
         }
@@ -388,6 +413,7 @@ struct RlWave {
     __device__ __forceinline__ void run()
     {
         e_acc = 0;
+        pl = philox_lane(real, a.sweep, a.key0);
         if (TM == TM_TWO) {
             bca = bcol(0);
             bcb = bcol(kWC - 1);

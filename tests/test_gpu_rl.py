@@ -1,7 +1,8 @@
 """The realization-lane sweep (sweep_kernel = LANES: one realization per lane, state with the realization innermost)
 against the oracle and against the tile sweep (TILES): the same chains bit for bit, the same energy series and
 stopping sweep, on grids with ragged bands, several and ragged row segments, temperature blocks that straddle the
-bands or line up with them, per-site temperatures, zero-temperature blocks, groups of realizations with idle lanes,
+bands or line up with them (and the narrowest blocks read as two columns per window and the widest that are not),
+per-site temperatures, zero-temperature blocks, groups of realizations with idle lanes,
 and the automatic choice at the 4096^2 headline shape."""
 import numpy as np
 import pytest
@@ -46,6 +47,8 @@ def _run_both(sc, T, lb, oc, cfg):
     (9, 1, (4, 1), 64, 0.5, False),          # one column
     (1, 29, (1, 5), 65, 0.4, False),         # one row
     (3, 5, (3, 5), 64, 0.7, False),          # one block smaller than a band
+    (50, 61, (7, 15), 64, 0.6, True),        # narrowest blocks looked up as two columns per window (15 wide)
+    (50, 61, (9, 14), 64, 0.6, False),       # blocks one narrower: up to three columns per window
 ])
 def test_rl_fixed_matches_oracle(H, W, lb, R, p, zero):
     sc = synth.random_small(H, W, p, seed=H * 31 + W)
