@@ -157,8 +157,9 @@ mpr_status mpr_calibrate_directional(const float* t, const uint8_t* mask, int64_
  *   or, with cfg->t_mode == MPR_T_SITE, T_blocks[H*W]: one temperature per site (the sweeps use T of the site).
  *   Start: gaps take the block mean of the sample angles (a block without samples: the global sample mean), or a
  *   uniform draw (tag 1).  Then sweeps k = 1, 2, ...: all gap sites of colour (x + y) % 2 == 0, then of colour 1,
- *   each an independent-uniform Metropolis proposal t' = u1 accepted iff u2 < exp(-dE / T_b) (T_b = 0: iff
- *   dE <= 0), dE from Eq. (1) over the in-grid nearest neighbours (open boundaries).  After each sweep the
+ *   each an independent-uniform Metropolis proposal t' = u1 accepted iff u2 < exp(-dE / T_b) (T_b = 0, and any
+ *   T_b that is not > 0, NaN included: iff dE <= 0), dE from Eq. (1) over the in-grid nearest neighbours (open
+ *   boundaries).  After each sweep the
  *   realization-averaged whole-grid energy per bond e(k) is recorded (e(0) before the first sweep).
  *   FIXED: k* = n_eq.  AUTO: at k = n_fit + j n_f the ordinary least-squares slope beta of the last n_fit energies
  *   is taken; equilibrium when beta * sign(e(k) - e(0)) <= 0; the cap n_max gives MPR_WARN_NOT_CONVERGED.

@@ -137,3 +137,23 @@ def test_auto_choice_and_errors():
     with pytest.raises(M.MprError):
         M.mpr_simulate(dev(t), dev(sc.mask), dev(T), 8, 8,
                        M.SimConfig(n_real=64, order=M.ORDER_DC, sweep_kernel=M.SWEEP_LANES))
+
+
+def test_temperatures_not_above_zero_act_as_zero():
+    """Blocks whose temperature is negative, -0 or NaN follow the T = 0 rule (accept iff dE <= 0), as in the oracle,
+    in both sweep kernels (blocks 16 wide: the lane kernel reads them as two temperature columns per window)."""
+    H, W, lb = 40, 52, (8, 16)
+    sc = synth.random_small(H, W, 0.55, seed=9)
+    t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+    T = _temps(H, W, lb, seed=4)
+    T.ravel()[::4] = -0.2
+    T.ravel()[1::5] = -0.0
+    T.ravel()[2::6] = np.nan
+    o = oracle.simulate(t, sc.mask, T, *lb, OCfg(n_real=64, init_mode=1, stop_mode=0, n_eq=6, n_samp=1, seed=13))
+    for kernel in (M.SWEEP_LANES, M.SWEEP_TILES):
+        print(f"[rl] non-positive temperatures, kernel {kernel}", flush=True)
+        cfg = M.SimConfig(n_real=64, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=6, n_samp=1, seed=13,
+                          sweep_kernel=kernel)
+        g = M.mpr_simulate(dev(t), dev(sc.mask), dev(T), *lb, cfg)
+        assert np.array_equal(host(g.state), o.state)
+        assert np.array_equal(host(g.acc), o.acc)
