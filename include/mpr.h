@@ -212,14 +212,18 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
                         void* workspace, size_t ws_bytes, void* stream);
 
 /* Batched simulation (a project addition): many scenes of different sizes and gap fractions, each with n_real
- * realizations, advanced together by one persistent sweep kernel per sweep that takes (scene, tile, realization
- * chunk) work items from a device work queue, largest scenes first.  Each scene follows exactly the arithmetic of
- * mpr_simulate with cfg->scene_id replaced by its own scene_id (its own stopping test and sampling sweeps), so its
- * results are bit-identical to a single-scene call.  Sweeps are replayed from a HIP graph captured once per call
- * (n_f sweeps per graph); the stream is synchronised once per graph replay.  tile_h: 16 or 32 (tile height of the
- * sweep kernel; results do not depend on it), or 0 to time one sweep with each and keep the faster
- * (*tile_h_used_out reports the choice).  sweeps_done_out[n_scenes] (host, optional): k* per scene.
- * Workspace: mpr_simulate_batched_workspace_bytes (a second state buffer per scene plus small per-scene arrays). */
+ * realizations.  Each scene follows exactly the arithmetic of mpr_simulate with cfg->scene_id replaced by its own
+ * scene_id (its own stopping test and sampling sweeps), so its results are bit-identical to a single-scene call.
+ * Scenes for which mpr_simulate would take the realization-lane sweep (cfg->sweep_kernel AUTO with n_real >= 64 and
+ * a grid that fills the device, or LANES) are run one after the other as such calls; the others are advanced
+ * together by one persistent sweep kernel per sweep that takes (scene, tile, realization chunk) work items from a
+ * device work queue, largest scenes first (cfg->sweep_kernel = TILES sends every scene there).  Their sweeps are
+ * replayed from a HIP graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph
+ * replay.  tile_h: 16 or 32 (tile height of that kernel; results do not depend on it), or 0 to time one sweep with
+ * each and keep the faster (*tile_h_used_out reports the choice, 0 when no scene ran on it).
+ * sweeps_done_out[n_scenes] (host, optional): k* per scene.  Workspace: mpr_simulate_batched_workspace_bytes (for the
+ * persistent batch a second state buffer per scene plus small per-scene arrays; the largest single-scene workspace
+ * of the other scenes; the same memory serves both). */
 typedef struct {
     int64_t H, W;             /* grid of this scene */
     int32_t lb_h, lb_w;       /* its temperature blocks */

@@ -965,18 +965,8 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
 
 extern "C" {
 
-size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
-{
-    if (!scenes || n_scenes < 1 || !cfg) return 0;
-    for (int i = 0; i < n_scenes; ++i)
-        if (scenes[i].H < 1 || scenes[i].W < 1 || scenes[i].lb_h < 1 || scenes[i].lb_w < 1) return 0;
-    Carve c{nullptr, 0, 0};
-    return batch_ws(c, scenes, n_scenes, cfg, nullptr);
-}
-
-mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
-                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
-                                void* stream)
+// The arguments of a batched call, checked once for the whole batch.
+static mpr_status check_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h)
 {
     if (!scenes || n_scenes < 1 || n_scenes > (1 << 20)) return fail(MPR_ERR_INVALID_ARG, "need 1 .. 2^20 scenes");
     if (!cfg) return fail(MPR_ERR_INVALID_ARG, "cfg is NULL");
@@ -1004,7 +994,24 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
             return fail(MPR_ERR_INVALID_ARG, "scene %d: NULL pointer", i);
         if (sc.scene_id >= (1u << 28)) return fail(MPR_ERR_INVALID_ARG, "scene %d: scene_id must be < 2^28", i);
     }
-    st = check_ws(workspace, ws_bytes, mpr_simulate_batched_workspace_bytes(scenes, n_scenes, cfg));
+    return MPR_OK;
+}
+
+// The persistent tile-kernel batch over the scenes given (all of them run on the tile kernel).
+static size_t batched_tiles_ws(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
+{
+    Carve c{nullptr, 0, 0};
+    return batch_ws(c, scenes, n_scenes, cfg, nullptr);
+}
+
+static mpr_status batched_tiles(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
+                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
+                                void* stream)
+{
+    mpr_status st = check_batched(scenes, n_scenes, cfg, tile_h);
+    if (st != MPR_OK) return st;
+    const mpr_sim_config& c = *cfg;
+    st = check_ws(workspace, ws_bytes, batched_tiles_ws(scenes, n_scenes, cfg));
     if (st != MPR_OK) return st;
     hipStream_t s = S(stream);
     Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
@@ -1215,6 +1222,72 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         all_converged &= runs[i].converged != 0;
     }
     if (!all_converged) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
+    return ok();
+}
+
+// A scene runs on its own (mpr_simulate with its scene_id) when mpr_simulate would take the realization-lane sweep
+// for it; the other scenes form the persistent tile-kernel batch.  Both give the scene's single-scene results.
+static bool batch_scene_on_lanes(const mpr_scene& sc, const mpr_sim_config& c)
+{
+    return use_rl(sc.H, sc.W, &c);
+}
+
+size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
+{
+    if (!scenes || n_scenes < 1 || !cfg) return 0;
+    for (int i = 0; i < n_scenes; ++i)
+        if (scenes[i].H < 1 || scenes[i].W < 1 || scenes[i].lb_h < 1 || scenes[i].lb_w < 1) return 0;
+    std::vector<mpr_scene> tiles;
+    size_t lanes = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        const mpr_scene& sc = scenes[i];
+        if (batch_scene_on_lanes(sc, *cfg))
+            lanes = std::max(lanes, mpr_simulate_workspace_bytes(sc.H, sc.W, sc.lb_h, sc.lb_w, cfg));
+        else
+            tiles.push_back(sc);
+    }
+    const size_t t = tiles.empty() ? 0 : batched_tiles_ws(tiles.data(), (int32_t)tiles.size(), cfg);
+    return std::max(lanes, t);
+}
+
+mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
+                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
+                                void* stream)
+{
+    mpr_status st = check_batched(scenes, n_scenes, cfg, tile_h);
+    if (st != MPR_OK) return st;
+    st = check_ws(workspace, ws_bytes, mpr_simulate_batched_workspace_bytes(scenes, n_scenes, cfg));
+    if (st != MPR_OK) return st;
+    std::vector<mpr_scene> tiles;
+    std::vector<int> tile_index;
+    bool warn = false;
+    for (int i = 0; i < n_scenes; ++i) {
+        const mpr_scene& sc = scenes[i];
+        if (!batch_scene_on_lanes(sc, *cfg)) {
+            tiles.push_back(sc);
+            tile_index.push_back(i);
+            continue;
+        }
+        mpr_sim_config ci = *cfg;
+        ci.scene_id = sc.scene_id;
+        int32_t k = 0;
+        st = mpr_simulate(sc.t, sc.mask, sc.H, sc.W, sc.T_blocks, sc.lb_h, sc.lb_w, &ci, sc.state, sc.acc, sc.energy, &k,
+                          workspace, ws_bytes, stream);
+        if (st == MPR_WARN_NOT_CONVERGED) warn = true;
+        else if (st != MPR_OK) return st;
+        if (sweeps_done_out) sweeps_done_out[i] = k;
+    }
+    if (tile_h_used_out) *tile_h_used_out = 0;
+    if (!tiles.empty()) {
+        std::vector<int32_t> k(tiles.size(), 0);
+        st = batched_tiles(tiles.data(), (int32_t)tiles.size(), cfg, tile_h, k.data(), tile_h_used_out, workspace,
+                           ws_bytes, stream);
+        if (st == MPR_WARN_NOT_CONVERGED) warn = true;
+        else if (st != MPR_OK) return st;
+        if (sweeps_done_out)
+            for (size_t j = 0; j < tiles.size(); ++j) sweeps_done_out[tile_index[j]] = k[j];
+    }
+    if (warn) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
     return ok();
 }
 

@@ -1,5 +1,7 @@
 """Batched simulation on the GPU: every scene of one persistent batched call equals its own single-scene call bit
 for bit (states, accumulators, stopping sweep, energy series), whatever tile height the sweep kernel uses."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -49,3 +51,38 @@ def test_batched_equals_single_scene(stop_mode, tile_h):
         assert np.array_equal(host(out.state), host(single.state))
         assert np.array_equal(host(out.acc), host(single.acc))
         assert np.array_equal(host(out.energy), host(single.energy))
+
+
+def test_batched_mixed_kernels_equal_single_scene():
+    """With 64 realizations, a scene large enough for the realization-lane sweep runs on its own inside the batched
+    call and the small ones form the persistent tile batch; every scene still equals its single-scene call, and
+    sweep_kernel = TILES (every scene in the tile batch) gives the same results."""
+    shapes = [(1024, 800, 0.6, 11), (70, 130, 0.5, 12), (33, 57, 0.7, 13)]
+    scenes = []
+    for i, (H, W, p, seed) in enumerate(shapes):
+        sc = synth.random_small(H, W, p, seed=seed)
+        t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+        B = (-(-H // 16)) * (-(-W // 16))
+        T = np.random.default_rng(seed).uniform(0.02, 0.5, B).astype(np.float32)
+        scenes.append(dict(t=dev(t), mask=dev(sc.mask), T_blocks=dev(T), block=(16, 16), scene_id=2000 + i))
+    cfg = M.SimConfig(n_real=64, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_max=200, seed=5)
+    print("[batched] mixed kernels", flush=True)
+    b = M.mpr_simulate_batched(scenes, cfg, want_energy=True)
+    tiles = M.mpr_simulate_batched(scenes, M.SimConfig(**{**cfg.__dict__, "sweep_kernel": M.SWEEP_TILES}),
+                                   want_energy=True)
+    assert b.tile_h in (16, 32) and tiles.tile_h in (16, 32)
+    for sc, out, out_t in zip(scenes, b.outputs, tiles.outputs):
+        single = M.mpr_simulate(sc["t"], sc["mask"], sc["T_blocks"], *sc["block"],
+                                M.SimConfig(**{**cfg.__dict__, "scene_id": sc["scene_id"]}))
+        for o in (out, out_t):
+            assert o.sweeps == single.sweeps
+            assert np.array_equal(host(o.state), host(single.state))
+            assert np.array_equal(host(o.acc), host(single.acc))
+            assert np.array_equal(host(o.energy), host(single.energy))
+    L = M.lib()
+    c_auto, c_tiles = cfg.to_c(), M.SimConfig(**{**cfg.__dict__, "sweep_kernel": M.SWEEP_TILES}).to_c()
+    assert (L.mpr_simulate_workspace_bytes(1024, 800, 16, 16, ctypes.byref(c_auto))
+            != L.mpr_simulate_workspace_bytes(1024, 800, 16, 16, ctypes.byref(c_tiles)))   # the lane sweep takes it
+    only_lanes = M.mpr_simulate_batched(scenes[:1], cfg)
+    assert only_lanes.tile_h == 0
+    assert np.array_equal(host(only_lanes.outputs[0].state), host(b.outputs[0].state))
