@@ -69,3 +69,34 @@ def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(ValueError):
         _lib.mpr_map_angles(torch.zeros(4, 4), torch.ones(4, 4, dtype=torch.uint8))
+
+
+def test_batched_workspace_covers_both_kernels():
+    """Host-only size queries: a scene that the realization-lane sweep takes needs exactly its single-scene
+    workspace inside a batch; with sweep_kernel = TILES (or few realizations) the batch needs the persistent tile
+    batch's; a mixed batch needs the larger of the two."""
+    L = _lib.lib()
+    auto = _lib.SimConfig(n_real=64).to_c()
+    tiles = _lib.SimConfig(n_real=64, sweep_kernel=_lib.SWEEP_TILES).to_c()
+    few = _lib.SimConfig(n_real=8).to_c()
+    big, small = (1024, 800), (70, 130)
+
+    def batch(shapes):
+        arr = (_lib.mpr_scene * len(shapes))()
+        for i, (H, W) in enumerate(shapes):
+            arr[i] = _lib.mpr_scene(H, W, 16, 16, i, None, None, None, None, None, None)
+        return arr, len(shapes)
+
+    single_lanes = L.mpr_simulate_workspace_bytes(*big, 16, 16, ctypes.byref(auto))
+    single_tiles = L.mpr_simulate_workspace_bytes(*big, 16, 16, ctypes.byref(tiles))
+    assert single_lanes != single_tiles                      # the lane sweep takes the large scene
+    assert L.mpr_simulate_batched_workspace_bytes(*batch([big]), ctypes.byref(auto)) == single_lanes
+    tile_only = L.mpr_simulate_batched_workspace_bytes(*batch([big]), ctypes.byref(tiles))
+    assert tile_only > 0 and tile_only != single_lanes
+    small_only = L.mpr_simulate_batched_workspace_bytes(*batch([small]), ctypes.byref(auto))
+    assert small_only == L.mpr_simulate_batched_workspace_bytes(*batch([small]), ctypes.byref(tiles))
+    assert (L.mpr_simulate_batched_workspace_bytes(*batch([big, small]), ctypes.byref(auto))
+            == max(single_lanes, small_only))
+    assert (L.mpr_simulate_batched_workspace_bytes(*batch([big, small]), ctypes.byref(few))
+            == L.mpr_simulate_batched_workspace_bytes(*batch([big, small]),
+                                                      ctypes.byref(_lib.SimConfig(n_real=8, sweep_kernel=_lib.SWEEP_TILES).to_c())))
