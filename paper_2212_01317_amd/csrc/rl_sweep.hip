@@ -10,7 +10,8 @@
 // A wave owns a band of B = kRlBand columns [x0, x0 + B) and a segment of rows [ys, ye) of one group of 64
 // realizations, and streams the rows downwards with a window of four rows in registers: the angle as loaded and
 // (cos, sin) of each site of columns x0 - 2 .. x0 + B + 1.  Step y updates colour 0 of row y and then colour 1 of
-// row y - 1, whose colour-0 neighbours (rows y - 2 .. y) are then current; every update writes its cell at once.
+// row y - 1, whose colour-0 neighbours (rows y - 2 .. y) are then current; a colour-0 update writes its cell at
+// once, the colour-1 row is written after the next row has arrived.
 // A row is requested two steps before it is updated, into the slot it then occupies, and its loaded angles are the
 // old angles of its updates, so nothing is read twice.  Colour 0 is also updated one site outside the band
 // (columns x0 - 1, x0 + B) and one row outside the segment (rows ys - 1, ye): these updates use the same
@@ -134,6 +135,12 @@ struct RlWave {
     int bc, bcl, bcr;                  // TM_ALIGNED: temperature columns of the owned columns and of the two ring columns
     int bca, bcb, jsplit;              // TM_TWO: the two temperature columns and the first window column of bcb
     long long e_acc;
+    // Colour-1 results are written one step late, after the next row has arrived: no other wave reads a colour-1
+    // cell in this sweep (this wave's exact tests read colour-1 neighbours from src), and the arrival then does not
+    // wait for stores that were issued just before it.  (Not with DIR, whose larger update leaves no registers.)
+    float pend[kWC];                   // new angles of the last colour-1 row, by window column
+    uint32_t pend_gap;                 // its gap bits (0: nothing pending)
+    int64_t pend_off;                  // its byte offset
 
     // the lane's element of window column j of the row at byte offset off (wave-uniform base + lane offset + an
     // immediate j * 256)
@@ -281,7 +288,8 @@ struct RlWave {
         const float cf = acc ? cp : c[SO][j], sf = acc ? sp : s[SO][j];
         c[SO][j] = cf;
         s[SO][j] = sf;
-        st(off, j, acc ? tp : to);
+        if (COL == 1 && !DIR) pend[j] = acc ? tp : to;
+        else st(off, j, acc ? tp : to);
         return ENERGY ? fix24(-fmaf(cf, Cx, sf * Sy)) : 0;
     }
 
@@ -400,6 +408,7 @@ struct RlWave {
         const int y1 = y - 1;
         const bool do0 = y >= 0 && y < a.H, do1 = y1 >= ys && y1 < ye;
         arrive<SD>();
+        flush<(P + 1) & 1>();
         if (y + 2 <= ye + 1) request<S2>(y + 2, offy + 2 * wrow);
         else pgap = psmp = 0u;
         if (do0) colour<0, P & 1, S0, SU, SD, -1, kB / 4, 1, kWC - 1>(trow0, y, offy);
@@ -407,7 +416,22 @@ struct RlWave {
             int e = colour<1, P & 1, SU, S2, S0, 0, kB / 4 - 1, 2, kWC - 2>(trow1, y1, offy - wrow);
             if (ENERGY) e += sample_energy<P & 1, SU, S2, S0>();
             e_acc += e;
+            if (!DIR) {
+                pend_gap = gap[SU];
+                pend_off = offy - wrow;
+            }
         }
+    }
+
+    // Writes the pending colour-1 row (column offset PAR: window columns 2 + PAR, 4 + PAR, ... 12 + PAR).
+    template <int PAR>
+    __device__ __forceinline__ void flush()
+    {
+        if (pend_gap == 0u) return;
+#pragma unroll
+        for (int j = 2 + PAR; j < kWC - 2; j += 2)
+            if ((pend_gap >> j) & 1u) st(pend_off, j, pend[j]);
+        pend_gap = 0u;
     }
 
     __device__ __forceinline__ void run()
@@ -444,6 +468,7 @@ struct RlWave {
         request<3>(ys - 1, offy + wrow);
         arrive<3>();
         request<0>(ys, offy + 2 * wrow);
+        pend_gap = 0u;
         for (int yb = ys - 1; yb <= ye; yb += 4) {
             step<3>(yb);
             if (yb + 1 > ye) break;
@@ -453,6 +478,9 @@ struct RlWave {
             if (yb + 3 > ye) break;
             step<2>(yb + 3);
         }
+        // the colour-1 row of the last step (y = ye, column offset ye & 1)
+        if (ye & 1) flush<1>();
+        else flush<0>();
     }
 };
 
