@@ -123,7 +123,7 @@ int validate_blocks(int64_t n);
 // Realization-lane sweep (rl_sweep.hip): single-checkerboard order, state layout [H W][Rp] with the realization
 // innermost (Rp = R rounded up to 64); a wave owns kRlBand columns x kRlSegRows rows of 64 realizations.
 constexpr int kRlBand = 12;
-constexpr int kRlSegRows = 128;        // longest row segment (rows are halved for small grids, down to 32)
+constexpr int kRlSegRows = 96;         // longest row segment (rows are halved for small grids, down to 32)
 constexpr int64_t kRlTargetWaves = 8192; // segments are shortened until a sweep has this many waves
 constexpr int64_t kRlMinWaves = 2048;    // fewer waves than this: the fused tile sweep is used instead
 constexpr int kRlWaves = 2;      // waves per SIMD the kernel is compiled for

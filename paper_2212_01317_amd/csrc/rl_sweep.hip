@@ -607,7 +607,7 @@ RlGeom rl_geometry(int64_t H, int64_t W, int R)
     const int64_t groups = g.Rp / 64;
     g.seg_rows = kRlSegRows;
     while (g.seg_rows > 32 && (int64_t)g.nbands * ((H + g.seg_rows - 1) / g.seg_rows) * groups < kRlTargetWaves)
-        g.seg_rows /= 2;
+        g.seg_rows = g.seg_rows / 2 > 32 ? g.seg_rows / 2 : 32;
     g.nseg = (int)((H + g.seg_rows - 1) / g.seg_rows);
     g.n_items = (int64_t)g.nbands * g.nseg * groups;
     return g;
