@@ -98,9 +98,6 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_predict.restype = None
     L.orc_validate.argtypes = [_f32p, _f32p, _u8p, _i64, _f64p]
     L.orc_validate.restype = None
-    L.orc_chain_trace.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _u64, _u32, _u32, _i32,
-                                  _i32, _i64p, _i32, _f32p]
-    L.orc_chain_trace.restype = None
     L.orc_block_energy.argtypes = [_f32p, _u8p, _i64, _i64, _i32, _i32, _flt, _flt, _f64p]
     L.orc_block_energy.restype = None
     L.orc_temperature_grad.argtypes = [_f32p, _f64p, _f64p, _i64, _i32, _i64, _f32p, _f64p]
@@ -329,17 +326,6 @@ def validate(zhat, truth, eval_mask):
     zh = _c(zhat, np.float32).ravel()
     lib().orc_validate(zh, _c(truth, np.float32).ravel(), _c(eval_mask, np.uint8).ravel(), zh.size, out)
     return float(out[0]), float(out[1])
-
-
-def chain_trace(state, mask, T_blocks, lb_h, lb_w, k_start, n_sweeps, sites, q=0.5, J=1.0, seed=0, scene=0,
-                real=0):
-    assert state.dtype == np.float32 and state.flags["C_CONTIGUOUS"]
-    H, W = state.shape
-    sites = _c(sites, np.int64)
-    tr = np.zeros((n_sweeps, len(sites)), np.float32)
-    lib().orc_chain_trace(state, _c(mask, np.uint8), H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, q, J, seed,
-                          scene, real, k_start, n_sweeps, sites, len(sites), tr)
-    return tr
 
 
 def run_pipeline(z, mask, lb_h, lb_w, curve_T, curve_e, cfg: SimConfig):

@@ -726,18 +726,6 @@ void orc_validate(const float* zhat, const float* truth, const uint8_t* eval_mas
     out[1] = P > 0 ? sqrt(s2 / (double)P) : 0.0;
 }
 
-/* Run n_sweeps sweeps (counter k_start+1 ...) of one realization and record the value of the listed sites after
- * every sweep into trace[sweep][site].  Used by the distribution tests on tiny grids. */
-void orc_chain_trace(float* s, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks, int32_t lb_h,
-                     int32_t lb_w, float q, float J, uint64_t seed, uint32_t scene, uint32_t real, int32_t k_start,
-                     int32_t n_sweeps, const int64_t* sites, int32_t n_sites, float* trace)
-{
-    for (int32_t i = 0; i < n_sweeps; ++i) {
-        orc_sweep(s, mask, H, W, T_blocks, lb_h, lb_w, q, J, seed, scene, real, (uint32_t)(k_start + 1 + i));
-        for (int32_t j = 0; j < n_sites; ++j) trace[(int64_t)i * n_sites + j] = s[sites[j]];
-    }
-}
-
 /* ------------------------------------------------------------------------------------------------------------
  * Gradient of the realization-averaged prediction with respect to the block temperatures (a project addition
  * built on Sec. 2.2.2).  For a density proportional to exp(-sum_b H_b / T_b), d<f>/dT_b = Cov(f, H_b) / T_b^2.

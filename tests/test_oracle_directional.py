@@ -115,3 +115,27 @@ def test_directional_calibration_follows_the_anisotropy(curve):
     S, N, _, _ = oracle.block_stats(t, mask, *lb)
     assert np.array_equal(Nh + Nv, N)
     assert np.allclose(Sh + Sv, S, rtol=1e-12, atol=1e-12)
+
+
+def test_temperatures_below_the_floor_run_the_floor_chain():
+    """Reading of the directional extension (the paper gives no parameters for it): both direction temperatures are
+    raised to at least fl32(1e-3 J), so that J a_h / Tx + J a_v / Ty stays finite.  A temperature below the floor
+    (0, a denormal, 1e-5 J) gives exactly the chain of the floor value, for either direction and for J != 1; a value
+    above the floor gives another chain."""
+    sc, t, T = _case(seed=13)
+    nb = T.size
+    for J in (1.0, 2.0):
+        floor = np.float32(1e-3 * J)
+        cfg = SimConfig(n_real=2, init_mode=0, stop_mode=0, n_eq=8, n_samp=1, seed=31, directional=1, J=J)
+        Ty = np.full(nb, 0.2, np.float32)
+        at_floor = oracle.simulate(t, sc.mask, np.concatenate([np.full(nb, floor, np.float32), Ty]), 8, 8, cfg)
+        for below in (0.0, 1e-40, 1e-5 * J, float(np.nextafter(floor, np.float32(0)))):
+            low = oracle.simulate(t, sc.mask, np.concatenate([np.full(nb, below, np.float32), Ty]), 8, 8, cfg)
+            assert np.array_equal(low.state, at_floor.state), (J, below)
+            assert np.array_equal(low.acc, at_floor.acc)
+        # the floor acts on Ty the same way
+        a = oracle.simulate(t, sc.mask, np.concatenate([Ty, np.zeros(nb, np.float32)]), 8, 8, cfg)
+        b = oracle.simulate(t, sc.mask, np.concatenate([Ty, np.full(nb, floor, np.float32)]), 8, 8, cfg)
+        assert np.array_equal(a.state, b.state)
+        above = oracle.simulate(t, sc.mask, np.concatenate([np.full(nb, 0.05 * J, np.float32), Ty]), 8, 8, cfg)
+        assert not np.array_equal(above.state, at_floor.state)

@@ -465,3 +465,81 @@ def test_simulate_auto_mode_stops_at_check_point(orc):
     assert orc.stop_check(res.energy, k) or not res.converged
     for kk in range(25, k, 5):
         assert not orc.stop_check(res.energy[: kk + 1], kk)
+
+
+# --------------------------------------------------------------------------------------------------------------
+# Whole-grid specific energy (Sec. 3.3, Fig. 9): Eq. (1) summed over every bond of the open grid, per bond
+# --------------------------------------------------------------------------------------------------------------
+
+def test_energy_constant_and_alternating_grids(orc):
+    """A constant grid has every bond at -J cos 0 = -J: -1 per bond exactly.  Alternating 0/1 turns put every bond
+    at -J cos(pi) = +J (q = 1/2): +1 per bond exactly.  Neither depends on J."""
+    for (H, W) in ((2, 2), (3, 3), (5, 8), (1, 7), (9, 1)):
+        assert orc.energy(np.full((H, W), 0.37, np.float32)) == -1.0
+        assert orc.energy(np.full((H, W), 0.37, np.float32), J=2.5) == -1.0
+        alt = (np.add.outer(np.arange(H), np.arange(W)) % 2).astype(np.float32)
+        assert abs(orc.energy(alt) - 1.0) < 1e-15
+        assert abs(orc.energy(alt, J=0.3) - 1.0) < 1e-15
+
+
+def test_energy_hand_values_3x3(orc):
+    """3 x 3 grids by hand.  (i) One corner at 1 turn, the rest 0: the corner's two bonds are +1, the other ten -1,
+    so e = (2 - 10) / 12 = -2/3; a periodic grid (18 bonds) or a count of sites (9) would give another value.
+    (ii) A ramp t = (x + y) / 4: all twelve bonds have dt = 1/4, e = -cos(pi/4).  (iii) q = 1/4 on the corner grid:
+    the corner bonds are -cos(pi/2) = 0, so e = -10/12."""
+    g = np.zeros((3, 3), np.float32)
+    g[0, 0] = 1.0
+    assert abs(orc.energy(g) - (-2.0 / 3.0)) < 1e-15
+    ramp = (np.add.outer(np.arange(3), np.arange(3)) / 4.0).astype(np.float32)
+    assert abs(orc.energy(ramp) + math.cos(math.pi / 4)) < 1e-15
+    assert abs(orc.energy(g, q=0.25) - (-10.0 / 12.0)) < 1e-15
+    # 2 x 2 by hand: t = [[0, 1/2], [1/4, 1]] has bonds 0, -sqrt(1/2), 0, +sqrt(1/2): e = 0
+    assert abs(orc.energy(np.array([[0.0, 0.5], [0.25, 1.0]], np.float32))) < 1e-15
+
+
+def test_energy_bond_count_of_the_open_grid(orc):
+    """Exactly one bond differs from the rest: e = (-(N - 1) + 1) / N identifies N = H (W - 1) + W (H - 1), the
+    bond count of the open grid (Sec. 2.1: nearest neighbours inside the grid).  A single site has no bond: 0."""
+    for (H, W) in ((1, 2), (2, 1), (2, 3), (4, 4), (3, 7), (6, 5)):
+        g = np.zeros((H, W), np.float32)
+        g[H - 1, W - 1] = 1.0    # a corner: exactly two bonds (one on a 1-wide grid) at +1
+        nb = H * (W - 1) + W * (H - 1)
+        corner_bonds = (1 if W > 1 else 0) + (1 if H > 1 else 0)
+        expect = (corner_bonds * 1.0 - (nb - corner_bonds)) / nb
+        assert abs(orc.energy(g) - expect) < 1e-14, (H, W)
+    assert orc.energy(np.zeros((1, 1), np.float32)) == 0.0
+
+
+def test_energy_of_a_complete_grid_is_the_one_block_sample_energy(orc):
+    """With every site observed and one block covering the grid, Eq. (2)'s per-bond sample energy S/(J N) runs over
+    the same bonds as the whole-grid energy: the two agree (and the brute-force bond sum agrees with both; q enters
+    both sides as an FP32 parameter)."""
+    rng = np.random.default_rng(8)
+    for (H, W, q, J) in ((7, 9, 0.5, 1.0), (12, 5, 0.3, 2.0)):
+        t = rng.random((H, W)).astype(np.float32)
+        S, N, _, _ = orc.block_stats(t, np.ones((H, W), np.uint8), H, W, q=q, J=J)
+        e = orc.energy(t, q=q, J=J)
+        assert N[0] == H * (W - 1) + W * (H - 1)
+        assert abs(e - S[0] / (J * N[0])) < 1e-14
+        brute = 0.0
+        for y in range(H):
+            for x in range(W):
+                for (yy, xx) in ((y, x + 1), (y + 1, x)):
+                    if yy < H and xx < W:
+                        brute += -math.cos(2 * math.pi * float(np.float32(q)) * (float(t[y, x]) - float(t[yy, xx])))
+        assert abs(e - brute / N[0]) < 1e-14
+
+
+def test_energy_series_of_simulate_is_the_realization_mean(orc):
+    """The series that drives the stopping test is, after every sweep, the mean over realizations of the whole-grid
+    energy per bond of each realization's state (Fig. 9 averages realizations); e(0) is the start."""
+    rng = np.random.default_rng(4)
+    H, W = 10, 13
+    t = rng.random((H, W)).astype(np.float32)
+    m = (rng.random((H, W)) < 0.5).astype(np.uint8)
+    T = np.array([[0.3, 0.1], [0.2, 0.5]], np.float32)
+    cfg = orc.SimConfig(n_real=3, init_mode=1, stop_mode=0, n_eq=4, n_samp=0, seed=5)
+    res = orc.simulate(t, m, T, 5, 7, cfg)
+    assert abs(res.energy[-1] - np.mean([orc.energy(res.state[r]) for r in range(3)])) < 1e-15
+    start = orc.simulate(t, m, T, 5, 7, orc.SimConfig(**{**cfg.__dict__, "n_eq": 0}))
+    assert abs(res.energy[0] - np.mean([orc.energy(start.state[r]) for r in range(3)])) < 1e-15
