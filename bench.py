@@ -25,15 +25,23 @@ if ROOT not in sys.path:
 
 # Algorithmic VALU work of one gap-site update, in lane-operations priced by the issue cost of each instruction
 # relative to a full-rate 32-bit add, as measured on the device (mpr_probe_instruction_rates):
-#   half a Philox4x32-10 block (the two sites of a pair share one): 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3) / 2
+#   half a Philox4x32-10 block (the two sites of a pair share one): 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3), each
+#     instruction priced by the probe of a 64-bit product feeding a three-input xor (the round's own shape, so that a
+#     product and an xor that issue together are priced together)
 #   two uniforms: shift + v_cvt_f32_u32 each, plus the scale of the proposal
 #   proposal angle, v_cos_f32, v_sin_f32
 #   local field from four neighbours' (cos, sin): 6 adds;  energy change: 2 sub, mul, fma
 #   Boltzmann test: fma (log2 of the ratio), v_exp_f32, compare;  select / store of t, cos, sin: 3
-# and per site and sweep (every site of a realization, as a neighbour): its angle, v_cos_f32, v_sin_f32.
+# and per site and sweep (every site of a realization, as a neighbour): its angle, v_cos_f32, v_sin_f32, and its share
+# of the whole-grid energy that the stopping test reads after every sweep (6 lane-operations: the bond terms of the
+# site and the fixed-point partial sum).
+A_SITE_ENERGY = 6.0
+
+
 def algorithmic_costs(r):
+    pair = r["v_mad_u64_u32+v_bitop3_b32"]
     parts = {
-        "philox_half_block": 10 * (2 * r["v_mad_u64_u32"] + 2 * r["v_bitop3_b32"]) / 2,
+        "philox_half_block": 10 * (2 * pair + 2 * pair) / 2,
         "uniforms": 2 * (1 + r["v_cvt_f32_u32"]) + 1,
         "proposal_sincos": 1 + r["v_sin_f32"] + r["v_cos_f32"],
         "local_field": 6.0,
@@ -41,7 +49,13 @@ def algorithmic_costs(r):
         "boltzmann_test": 2 + r["v_exp_f32"],
         "select_store": 3.0,
     }
-    return sum(parts.values()), 1 + r["v_sin_f32"] + r["v_cos_f32"], parts
+    site = {"angle_sincos": 1 + r["v_sin_f32"] + r["v_cos_f32"], "energy": A_SITE_ENERGY}
+    return sum(parts.values()), sum(site.values()), dict(parts, **{"site_" + k: v for k, v in site.items()})
+
+
+# The pricing written before any measurement (quarter-rate 64-bit products and transcendentals): 82 lane-cycles per
+# update plus 15 per site and sweep; reported beside the measured pricing for comparison.
+A_UPDATE_NOMINAL, A_SITE_NOMINAL = 82.0, 15.0
 
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
@@ -119,6 +133,9 @@ def parse():
     ap.add_argument("--n-real", type=int, default=256)
     ap.add_argument("--roofline-sweeps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--other-p", default="0.3,0.9",
+                    help="further gap fractions of the 4096^2 workload, each timed and priced on its own ('' = none)")
+    ap.add_argument("--other-p-steps", type=int, default=2)
     ap.add_argument("--profile-sweeps", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and gradient measurements")
     ap.add_argument("--batch-scenes", type=int, default=256)
@@ -131,64 +148,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the realizations would shard over "
-              f"GPUs with a single all-reduce of the accumulator, which this build does not run.", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def c3_leg(sc, p, R, lb, cT, ce, dev, steps, warmup, kchoice, kernel, roofline_sweeps, state):
+    """The 4096^2 workload at gap fraction p: `warmup` untimed and `steps` timed steps (map -> calibrate -> simulate
+    with the automatic stop -> predict -> validate, inputs resident in HBM), then the roofline of the sweep kernel at
+    that p.  Returns the measured quantities and the step objects the extra legs reuse."""
     import torch
 
     import paper_2212_01317_amd as mpr
     from paper_2212_01317_amd import synth
-
-    L = args.size
-    R = args.n_real
-    lb = (32, 32)
-    t0 = time.time()
-    sc = synth.config3(args.p, L, L)
-    log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={args.p}, gaps={int((sc.mask == 0).sum())}")
-    extras_inputs = None
-    if not args.no_extras and args.profile_sweeps == 0:
-        # generated before the GPU is touched (worker processes are started from a process without a GPU context)
-        t0 = time.time()
-        scenes4 = synth.config4_scenes(args.batch_scenes, workers=min(16, os.cpu_count() or 1))
-        sc5 = synth.config5()
-        extras_inputs = (scenes4, sc5)
-        log(f"[bench] batched and gradient workloads generated in {time.time() - t0:.1f}s")
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
+    L = sc.z_obs.shape[0]
     z = torch.from_numpy(sc.z_obs).to(dev)
     mask = torch.from_numpy(sc.mask).to(dev)
     truth = torch.from_numpy(sc.z_true).to(dev)
     evm = torch.from_numpy(sc.eval_mask).to(dev)
     n_gap = int((sc.mask == 0).sum())
-    state = torch.empty((R, L, L), dtype=torch.float32, device=dev)
-    kchoice = {"auto": mpr.SWEEP_AUTO, "tiles": mpr.SWEEP_TILES, "lanes": mpr.SWEEP_LANES}[args.sweep_kernel]
     cfg = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_AUTO, n_samp=1, n_fit=20,
                         n_f=5, n_max=1000, seed=synth.seed_for(3, synth.ROLE_PHILOX), sweep_kernel=kchoice)
     fixed = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=0, n_samp=0,
                           seed=cfg.seed, sweep_kernel=kchoice)
-
-    if args.profile_sweeps > 0:
-        # counter runs: a small matching curve (T values do not change the traffic), the start, an even number of
-        # sweeps, and a 1 GiB elementwise copy (read 1 GiB, write 1 GiB) that calibrates the byte counters
-        small = dict(L=16, n_therm=20, n_meas=20, seed=1, decades=(-3, 2), per_decade=4)
-        cT, ce = mpr.reference_curve(0.5, dev, spec=small)
-        t, rng = mpr.mpr_map_angles(z, mask)
-        T, _, _ = mpr.mpr_calibrate_temperature(t, mask, lb[0], lb[1], cT, ce)
-        n = args.profile_sweeps
-        prof = mpr.SimConfig(**{**fixed.__dict__, "n_eq": n})
-        mpr.mpr_simulate(t, mask, T, lb[0], lb[1], prof, state=state, want_energy=True)
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.mul(a, 1.0, out=b)
-        torch.cuda.synchronize()
-        log(f"[bench] profile run done: {n} sweeps, then a 1 GiB elementwise copy")
-        return
-
-    cT, ce = mpr.reference_curve(0.5, dev)          # a constant of the method, computed once per process
     ws_need = mpr.lib().mpr_simulate_workspace_bytes(L, L, lb[0], lb[1], ctypes.byref(cfg.to_c()))
     ws = torch.empty(ws_need, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
@@ -201,29 +178,28 @@ def main():
         err = mpr.mpr_validate(zhat, truth, evm)
         return sim, err, T
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         sim, err, T = step()
         torch.cuda.synchronize()
-        log(f"[bench] warmup {i}: k*={sim.sweeps} converged={sim.converged}")
+        log(f"[bench] p={p} warmup {i}: k*={sim.sweeps} converged={sim.converged}")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     updates = 0
     sweeps = []
-    for i in range(args.steps):
+    for i in range(steps):
         sim, err, T = step()
         sweeps.append(sim.sweeps + cfg.n_samp)
         updates += R * n_gap * (sim.sweeps + cfg.n_samp)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     errs = err.cpu().numpy()
-    log(f"[bench] {args.steps} steps in {elapsed:.3f}s, sweeps/step {sweeps}, AAE {errs[0]:.5f} RASE {errs[1]:.5f}")
+    log(f"[bench] p={p}: {steps} steps in {elapsed:.3f}s, sweeps/step {sweeps}, AAE {errs[0]:.5f} RASE {errs[1]:.5f}")
 
     # Roofline of the dominant kernel: one sweep of all R realizations as the simulation runs it (with the energy
     # of the sweep, as under the automatic stop).  HIP events on the stream the library launches on (torch's
     # current stream) bracket two fixed-length simulations of the same start, n1 and n1 + ns sweeps; their
     # difference is ns sweeps, each one sweep launch plus the two small launches that reduce its energy.
-    kernel = sweep_kernel(R, args.sweep_kernel)
-    ns = args.roofline_sweeps
+    ns = roofline_sweeps
     n1 = 4
 
     def timed_simulation(n):
@@ -247,19 +223,90 @@ def main():
     ops_launch = upd_launch * a_upd + float(R) * L * L * a_site
     achieved = ops_launch / t_launch
     sweep_upd_rate = upd_launch / t_launch
-    log(f"[bench] sweep launch {t_launch * 1e3:.3f} ms -> {sweep_upd_rate:.3e} upd/s in the sweep kernel")
-
-    traffic = measured_traffic(kernel, L, R, args.p)
+    log(f"[bench] p={p}: sweep launch {t_launch * 1e3:.3f} ms -> {sweep_upd_rate:.3e} upd/s in the sweep kernel, "
+        f"ALU roofline fraction {achieved / PEAK_LANE_OPS:.3f}")
+    traffic = measured_traffic(kernel, L, R, p)
     alg_bytes = float(R) * n_gap * 8.0              # 4 B read + 4 B written per gap site and realization
-    value = updates / elapsed
+    roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                "frac_nominal_pricing": (upd_launch * A_UPDATE_NOMINAL + float(R) * L * L * A_SITE_NOMINAL)
+                / t_launch / PEAK_LANE_OPS,
+                "traffic_gbs": traffic / t_launch / 1e9 if traffic else None,
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "launch_ms": t_launch * 1e3, "ops_per_launch": ops_launch,
+                "a_update": a_upd, "a_site": a_site, "a_parts": a_parts,
+                "instruction_cost_vs_add": rates, "add_ns_per_wave_instruction": add_ns,
+                "sweep_kernel_updates_per_s": sweep_upd_rate}
+    return {"value": updates / elapsed, "ms_per_step": elapsed / steps * 1e3, "steps": steps, "sweeps": sweeps,
+            "gap_sites": n_gap, "roofline": roofline, "aae": float(errs[0]), "rase": float(errs[1]),
+            "cfg": cfg, "errs": errs}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the realizations would shard over "
+              f"GPUs with a single all-reduce of the accumulator, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_2212_01317_amd as mpr
+    from paper_2212_01317_amd import synth
+
+    L = args.size
+    R = args.n_real
+    lb = (32, 32)
+    t0 = time.time()
+    sc = synth.config3(args.p, L, L)
+    log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={args.p}, gaps={int((sc.mask == 0).sum())}")
+    extras_inputs = None
+    other_p = [float(x) for x in args.other_p.split(",") if x.strip()] if args.profile_sweeps == 0 else []
+    if not args.no_extras and args.profile_sweeps == 0:
+        # generated before the GPU is touched (worker processes are started from a process without a GPU context)
+        t0 = time.time()
+        scenes4 = synth.config4_scenes(args.batch_scenes, workers=min(16, os.cpu_count() or 1))
+        sc5 = synth.config5()
+        extras_inputs = (scenes4, sc5)
+        log(f"[bench] batched and gradient workloads generated in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    state = torch.empty((R, L, L), dtype=torch.float32, device=dev)
+    kchoice = {"auto": mpr.SWEEP_AUTO, "tiles": mpr.SWEEP_TILES, "lanes": mpr.SWEEP_LANES}[args.sweep_kernel]
+    kernel = sweep_kernel(R, args.sweep_kernel)
+
+    if args.profile_sweeps > 0:
+        # counter runs: a small matching curve (T values do not change the traffic), the start, an even number of
+        # sweeps, and a 1 GiB elementwise copy (read 1 GiB, write 1 GiB) that calibrates the byte counters
+        z = torch.from_numpy(sc.z_obs).to(dev)
+        mask = torch.from_numpy(sc.mask).to(dev)
+        small = dict(L=16, n_therm=20, n_meas=20, seed=1, decades=(-3, 2), per_decade=4)
+        cT, ce = mpr.reference_curve(0.5, dev, spec=small)
+        t, rng = mpr.mpr_map_angles(z, mask)
+        T, _, _ = mpr.mpr_calibrate_temperature(t, mask, lb[0], lb[1], cT, ce)
+        n = args.profile_sweeps
+        prof = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=n, n_samp=0,
+                             seed=synth.seed_for(3, synth.ROLE_PHILOX), sweep_kernel=kchoice)
+        mpr.mpr_simulate(t, mask, T, lb[0], lb[1], prof, state=state, want_energy=True)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log(f"[bench] profile run done: {n} sweeps, then a 1 GiB elementwise copy")
+        return
+
+    cT, ce = mpr.reference_curve(0.5, dev)          # a constant of the method, computed once per process
+    head = c3_leg(sc, args.p, R, lb, cT, ce, dev, args.steps, args.warmup, kchoice, kernel, args.roofline_sweeps,
+                  state)
+    n_gap, cfg, errs = head["gap_sites"], head["cfg"], head["errs"]
     out = {
         "metric": "SV-MPR gap-site updates/s at 4096^2 (C3)",
-        "value": value,
+        "value": head["value"],
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -270,17 +317,22 @@ def main():
                                f"1 sampling sweep; step = map+calibrate+simulate+predict+validate",
                    "H": L, "W": L, "p": args.p, "gap_sites": n_gap, "n_real": R, "block": list(lb),
                    "sweep_kernel": kernel,
-                   "sweeps_per_step": sweeps},
-        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                     "traffic_gbs": traffic / t_launch / 1e9 if traffic else None,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "launch_ms": t_launch * 1e3, "ops_per_launch": ops_launch,
-                     "a_update": a_upd, "a_site": a_site, "a_update_parts": a_parts,
-                     "instruction_cost_vs_add": rates, "add_ns_per_wave_instruction": add_ns,
-                     "sweep_kernel_updates_per_s": sweep_upd_rate},
-        "validation": {"aae": float(errs[0]), "rase": float(errs[1])},
+                   "sweeps_per_step": head["sweeps"]},
+        "roofline": head["roofline"],
+        "validation": {"aae": head["aae"], "rase": head["rase"]},
     }
+    if other_p:
+        # the other gap fractions of the same configuration: each its own step timing and its own roofline
+        legs = {}
+        for p in other_p:
+            t0 = time.time()
+            scp = synth.config3(p, L, L)
+            log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={p}")
+            leg = c3_leg(scp, p, R, lb, cT, ce, dev, args.other_p_steps, 1, kchoice, kernel, args.roofline_sweeps,
+                         state)
+            legs[f"{p:g}"] = {k: v for k, v in leg.items() if k not in ("cfg", "errs")}
+            del scp
+        out["other_gap_fractions"] = legs
     if extras_inputs is not None:
         out["sst"] = bench_sst(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
         out["directional"] = bench_directional(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
@@ -525,26 +577,83 @@ def bench_gradient(sc, cT, ce, dev):
                          "z": [float(x) for x in zs], "sum_ratio": ratio}}
 
 
+def host_cpu():
+    """CPU model and logical CPU count of this host (lscpu, else /proc/cpuinfo), and the CPUs this process may use."""
+    import subprocess
+    model, ncpu = None, None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name" and model is None:
+                model = v.strip()
+            if k.strip() == "CPU(s)" and ncpu is None:
+                ncpu = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, ncpu, usable
+
+
 def cpu_baseline(sc, lb):
-    """The CPU oracle, single-threaded, on a bounded sample of the same workload: map + calibration + 4 realizations
-    x (3 equilibration sweeps + 1 sampling sweep)."""
+    """The CPU oracle on this host's cores, on bounded samples of the benchmark's workloads (about 25 s):
+    the 4096^2 input (map + calibration + 4 sweeps of 2 realizations single-threaded, and of 2 realizations per thread
+    with the OpenMP build, realizations spread over threads), and the 128^2 plain-MPR configuration (10 realizations,
+    100 + 100 sweeps) in full, both builds.  value = the OpenMP rate on the 4096^2 sample."""
     import numpy as np
 
     import oracle
+    from paper_2212_01317_amd import synth
+    model, ncpu, usable = host_cpu()
+    nthr = oracle.threads(parallel=True)
     Tg = np.geomspace(1e-3, 1e2, 31).astype(np.float32)
     e = oracle.reference_curve(Tg, L=24, n_therm=200, n_meas=300, seed=21)
     n_gap = int((sc.mask == 0).sum())
-    t0 = time.perf_counter()
-    t, rng = oracle.map_angles(sc.z_obs, sc.mask)
-    T, _, _ = oracle.calibrate_temperature(t, sc.mask, lb[0], lb[1], Tg.astype(np.float64), e)
-    res = oracle.simulate(t, sc.mask, T, lb[0], lb[1],
-                          oracle.SimConfig(n_real=4, init_mode=1, stop_mode=0, n_eq=3, n_samp=1, seed=1))
-    el = time.perf_counter() - t0
-    upd = n_gap * 4 * 4
-    log(f"[bench] cpu oracle: {upd} updates in {el:.1f}s")
-    return {"value": upd / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"same 4096^2 input; map + calibration + 4 realizations x 4 sweeps ({upd} updates), "
-                      f"{el:.1f} s single-threaded FP64"}
+
+    def c3(parallel, R):
+        t0 = time.perf_counter()
+        t, rng = oracle.map_angles(sc.z_obs, sc.mask)
+        T, _, _ = oracle.calibrate_temperature(t, sc.mask, lb[0], lb[1], Tg.astype(np.float64), e)
+        oracle.simulate(t, sc.mask, T, lb[0], lb[1],
+                        oracle.SimConfig(n_real=R, init_mode=1, stop_mode=0, n_eq=3, n_samp=1, seed=1),
+                        parallel=parallel)
+        el = time.perf_counter() - t0
+        return n_gap * R * 4 / el, el
+
+    one, el1 = c3(False, 2)
+    par, elp = c3(True, 2 * nthr)
+    c1 = synth.config1()
+    n1 = int((c1.mask == 0).sum())
+
+    def c1_full(parallel):
+        t0 = time.perf_counter()
+        t, rng = oracle.map_angles(c1.z_obs, c1.mask)
+        T, _, _ = oracle.calibrate_temperature(t, c1.mask, 128, 128, Tg.astype(np.float64), e)
+        res = oracle.simulate(t, c1.mask, T, 128, 128,
+                              oracle.SimConfig(n_real=10, init_mode=0, stop_mode=0, n_eq=100, n_samp=100, seed=1),
+                              parallel=parallel)
+        oracle.predict(res.acc, c1.z_obs, c1.mask, 1000, rng)
+        return time.perf_counter() - t0
+
+    c1_one, c1_par = c1_full(False), c1_full(True)
+    log(f"[bench] cpu oracle on {model} ({usable} usable CPUs): 4096^2 sample {one:.3e} upd/s on 1 thread, "
+        f"{par:.3e} on {nthr}; 128^2 in full {c1_one:.2f}s / {c1_par:.2f}s")
+    return {"value": par, "unit": "site-updates/s", "cores": nthr, "kind": "oracle",
+            "cpu_model": model, "host_logical_cpus": ncpu, "usable_cpus": usable,
+            "sample": f"4096^2 input of the benchmark; map + calibration + {2 * nthr} realizations x 4 sweeps "
+                      f"({n_gap * 2 * nthr * 4} updates) in {elp:.1f}s with the OpenMP build of the FP64 oracle "
+                      f"(realizations over {nthr} threads)",
+            "single_thread": {"value": one, "sample": f"2 realizations x 4 sweeps, {el1:.1f}s"},
+            "config1_full": {"workload": "128^2 GRF(8), 33% gaps, global T, 10 realizations, 100 + 100 sweeps",
+                             "updates": n1 * 10 * 200, "seconds_1_thread": c1_one, "seconds_openmp": c1_par,
+                             "openmp_threads": nthr, "updates_per_s_1_thread": n1 * 2000 / c1_one,
+                             "updates_per_s_openmp": n1 * 2000 / c1_par}}
 
 
 if __name__ == "__main__":

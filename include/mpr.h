@@ -221,7 +221,9 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
  * replayed from a HIP graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph
  * replay.  tile_h: 16 or 32 (tile height of that kernel; results do not depend on it), or 0 to time one sweep with
  * each and keep the faster (*tile_h_used_out reports the choice, 0 when no scene ran on it).
- * sweeps_done_out[n_scenes] (host, optional): k* per scene.  Workspace: mpr_simulate_batched_workspace_bytes (for the
+ * sweeps_done_out[n_scenes] (host, optional): k* per scene; converged_out[n_scenes] (host, optional): 1 where the scene
+ * met the equilibrium test (or ran FIXED), 0 where AUTO reached n_max without it (the call then returns
+ * MPR_WARN_NOT_CONVERGED).  Workspace: mpr_simulate_batched_workspace_bytes (for the
  * persistent batch a second state buffer per scene plus small per-scene arrays; the largest single-scene workspace
  * of the other scenes; the same memory serves both). */
 typedef struct {
@@ -238,7 +240,8 @@ typedef struct {
 size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg);
 mpr_status mpr_simulate_batched(const mpr_scene* scenes /* host array */, int32_t n_scenes,
                                 const mpr_sim_config* cfg, int32_t tile_h, int32_t* sweeps_done_out,
-                                int32_t* tile_h_used_out, void* workspace, size_t ws_bytes, void* stream);
+                                int32_t* converged_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
+                                void* stream);
 
 /* Temperature gradient (a project addition on Sec. 2.2.2: tuning the block temperatures by gradient).
  * For a density proportional to exp(-sum_b H_b / T_b), d<f>/dT_b = Cov(f, H_b) / T_b^2.
@@ -265,11 +268,14 @@ mpr_status mpr_temperature_grad(const float* state, const double* H_blocks, cons
                                 size_t ws_bytes, void* stream);
 
 /* mpr_probe_instruction_rates: measurement support for the ALU roofline of the sweep (the per-update cost is priced
- * from the device's own instruction rates, not from a data sheet).  Times nine probe kernels, each a fixed number of
- * wave-instructions of one kind in independent dependency chains over the whole device, and writes to cost_out (host,
- * n_out >= 9) the issue cost of each relative to v_add_u32 = 1: [0] v_add_u32, [1] v_mad_u64_u32, [2] v_mul_lo_u32,
- * [3] v_mul_hi_u32, [4] v_bitop3_b32, [5] v_sin_f32, [6] v_cos_f32, [7] v_exp_f32, [8] v_cvt_f32_u32 (2 = half
- * rate).  add_ns_out (host, nullable): device time per wave-instruction of v_add_u32, in ns.  workspace: device,
+ * from the device's own instruction rates, not from a data sheet).  Times twelve probe kernels, each a fixed number of
+ * wave-instructions in independent dependency chains over the whole device, and writes to cost_out (host,
+ * n_out >= 12) the issue cost per wave-instruction of each relative to v_add_u32 = 1 (2 = half rate):
+ * [0] v_add_u32, [1] v_mad_u64_u32, [2] v_mul_lo_u32, [3] v_mul_hi_u32, [4] v_bitop3_b32, [5] v_sin_f32,
+ * [6] v_cos_f32, [7] v_exp_f32, [8] v_cvt_f32_u32, [9] v_xor_b32, and two pairs, each cost per instruction of the
+ * pair: [10] v_mad_u64_u32 beside an independent v_add_u32 (0.5 would mean the two issue together), [11]
+ * v_mad_u64_u32 whose high half a v_bitop3_b32 consumes (the shape of a Philox round).  add_ns_out (host, nullable):
+ * device time per wave-instruction of v_add_u32, in ns.  workspace: device,
  * mpr_probe_instruction_rates_workspace_bytes() bytes (probe outputs).  Synchronises the stream. */
 size_t mpr_probe_instruction_rates_workspace_bytes(void);
 mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* add_ns_out, void* workspace,

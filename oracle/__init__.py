@@ -17,28 +17,46 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpr_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
+# the same source built with OpenMP over the realizations of orc_simulate (CPU-baseline timing on all host cores;
+# its results equal the single-threaded build's bit for bit)
+_LIB_OMP_PATH = os.path.join(_HERE, "liborc_omp.so")
 
 _lib = None
+_lib_omp = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, IEEE semantics: no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, _SRC,
-                               "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile the oracle with gcc (-O2, IEEE semantics: no fast-math), single-threaded and with OpenMP."""
+    for path, extra in ((_LIB_PATH, []), (_LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", *extra, "-o", tmp,
+                                   _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def lib() -> ctypes.CDLL:
-    global _lib
+def lib(parallel: bool = False) -> ctypes.CDLL:
+    """The oracle library; parallel=True loads the OpenMP build (same results, realizations over threads)."""
+    global _lib, _lib_omp
+    if parallel:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP_PATH):
+                build(force=False)
+            _lib_omp = ctypes.CDLL(_LIB_OMP_PATH)
+            _declare(_lib_omp)
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build(force=False)
         _lib = ctypes.CDLL(_LIB_PATH)
         _declare(_lib)
     return _lib
+
+
+def threads(parallel: bool = False) -> int:
+    """Threads orc_simulate's realization loops use in the chosen build."""
+    return int(lib(parallel).orc_threads())
 
 
 _f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
@@ -102,6 +120,8 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_block_energy.restype = None
     L.orc_temperature_grad.argtypes = [_f32p, _f64p, _f64p, _i64, _i32, _i64, _f32p, _f64p]
     L.orc_temperature_grad.restype = None
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = ctypes.c_int
 
 
 # ---------------------------------------------------------------------------------------------------------------
@@ -287,7 +307,7 @@ class SimResult:
     converged: bool
 
 
-def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
+def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, parallel: bool = False) -> SimResult:
     t = _c(t, np.float32)
     mask = _c(mask, np.uint8)
     H, W = t.shape
@@ -297,7 +317,7 @@ def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig) -> SimResult:
     ncap = (cfg.n_max if cfg.stop_mode == 1 else cfg.n_eq) + 1
     en = np.zeros(ncap, np.float64)
     conv = _i32(0)
-    k = lib().orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
+    k = lib(parallel).orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
                            cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp, cfg.n_fit, cfg.n_f,
                            cfg.n_max, cfg.seed, cfg.scene, cfg.t_mode, cfg.order, cfg.directional, state, acc, en,
                            ctypes.byref(conv))

@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
 
@@ -121,6 +124,17 @@ int orc_map_angles(const float* z, const uint8_t* mask, int64_t H, int64_t W, fl
     range[0] = zmin;
     range[1] = zmax;
     return 0;
+}
+
+/* Threads the realization loops of orc_simulate run on: 1 in the plain build, the OpenMP team size in the parallel
+ * build of the CPU baseline. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Eq. (1): the energy of one bond of the MPR Hamiltonian, -J cos(q (phi_a - phi_b)), with phi = 2*pi*t. */
@@ -577,6 +591,9 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     }
     float global_mean = all_cnt > 0 ? (float)(all_sum / (double)all_cnt) : 0.0f;
 
+    /* Realizations are independent chains: with OpenMP (the parallel build of the CPU baseline) they are spread over
+     * threads; every sum over realizations is still taken in realization order, so both builds agree bit for bit. */
+#pragma omp parallel for schedule(static)
     for (int32_t r = 0; r < R; ++r) {
         float* s = state + (int64_t)r * HW;
         uint32_t real = (uint32_t)(r + real_offset);
@@ -599,14 +616,17 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     for (int64_t n = 0; n < HW; ++n) acc[n] = 0.0;
 
     int32_t k_cap = stop_mode == 1 ? n_max : n_eq;
+    double* e_r = (double*)malloc(sizeof(double) * (size_t)R);
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < R; ++r) e_r[r] = orc_energy(state + (int64_t)r * HW, H, W, q, J);
     double e0 = 0.0;
-    for (int32_t r = 0; r < R; ++r) e0 += orc_energy(state + (int64_t)r * HW, H, W, q, J);
+    for (int32_t r = 0; r < R; ++r) e0 += e_r[r];
     energy[0] = e0 / (double)R;
     int32_t k = 0;
     *converged = 1;
     while (k < k_cap) {
         ++k;
-        double ek = 0.0;
+#pragma omp parallel for schedule(static)
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
             if (directional)
@@ -618,14 +638,17 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
             else
                 orc_sweep(s, mask, H, W, T_blocks, tb_h, tb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
                           (uint32_t)k);
-            ek += orc_energy(s, H, W, q, J);
+            e_r[r] = orc_energy(s, H, W, q, J);
         }
+        double ek = 0.0;
+        for (int32_t r = 0; r < R; ++r) ek += e_r[r];
         energy[k] = ek / (double)R;
         if (stop_mode == 1 && orc_stop_check(energy, k, n_fit, n_f)) break;
         if (stop_mode == 1 && k == n_max) *converged = 0;
     }
     int32_t k_star = k;
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
+#pragma omp parallel for schedule(static)
         for (int32_t r = 0; r < R; ++r) {
             float* s = state + (int64_t)r * HW;
             if (directional)
@@ -644,6 +667,7 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
                 if (!mask[n]) acc[n] += (double)s[n];
         }
     }
+    free(e_r);
     free(S);
     free(N);
     free(Tsum);

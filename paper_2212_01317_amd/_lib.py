@@ -116,7 +116,8 @@ _SIGS = {
     "mpr_predict": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "mpr_simulate_batched_workspace_bytes": ([ctypes.POINTER(mpr_scene), _i32, ctypes.POINTER(mpr_sim_config)], _sz),
     "mpr_simulate_batched": ([ctypes.POINTER(mpr_scene), _i32, ctypes.POINTER(mpr_sim_config), _i32,
-                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
+                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp, _sz, _vp],
+                             ctypes.c_int),
     "mpr_block_energy_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
     "mpr_block_energy": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "mpr_temperature_grad_workspace_bytes": ([_i64, _i64, _i32], _sz),
@@ -365,7 +366,7 @@ def mpr_sst_temperatures(T_blocks, H: int, W: int, lb_h: int, lb_w: int, r_s: in
 
 
 PROBE_NAMES = ("v_add_u32", "v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_bitop3_b32", "v_sin_f32", "v_cos_f32",
-               "v_exp_f32", "v_cvt_f32_u32")
+               "v_exp_f32", "v_cvt_f32_u32", "v_xor_b32", "v_mad_u64_u32+v_add_u32", "v_mad_u64_u32+v_bitop3_b32")
 
 
 def mpr_probe_instruction_rates(device=None):
@@ -450,12 +451,13 @@ def mpr_simulate_batched(scenes, cfg: SimConfig, tile_h: int = 0, want_energy: b
     dev = scenes[0]["t"].device
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
     done = (_i32 * n)()
+    conv = (_i32 * n)()
     used = _i32(0)
-    st = _check(lib().mpr_simulate_batched(arr, n, ctypes.byref(c), int(tile_h), done, ctypes.byref(used), _p(ws),
-                                           ws.numel(), _stream()), allow_warn=True)
+    st = _check(lib().mpr_simulate_batched(arr, n, ctypes.byref(c), int(tile_h), done, conv, ctypes.byref(used),
+                                           _p(ws), ws.numel(), _stream()), allow_warn=True)
     res = []
     for i, (state, acc, en) in enumerate(outs):
         k = int(done[i])
         e = en[: k + 1] if en is not None else torch.empty(0, dtype=torch.float64, device=dev)
-        res.append(SimOutput(state=state, acc=acc, energy=e, sweeps=k, converged=True))
+        res.append(SimOutput(state=state, acc=acc, energy=e, sweeps=k, converged=bool(conv[i])))
     return BatchOutput(outputs=res, tile_h=int(used.value), converged=(st == MPR_OK))

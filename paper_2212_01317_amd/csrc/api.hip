@@ -1005,8 +1005,8 @@ static size_t batched_tiles_ws(const mpr_scene* scenes, int32_t n_scenes, const 
 }
 
 static mpr_status batched_tiles(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
-                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
-                                void* stream)
+                                int32_t* sweeps_done_out, int32_t* converged_out, int32_t* tile_h_used_out,
+                                void* workspace, size_t ws_bytes, void* stream)
 {
     mpr_status st = check_batched(scenes, n_scenes, cfg, tile_h);
     if (st != MPR_OK) return st;
@@ -1219,6 +1219,7 @@ static mpr_status batched_tiles(const mpr_scene* scenes, int32_t n_scenes, const
             MPR_HIP(hipMemcpyAsync(scenes[i].state, w.alt[i], sizeof(float) * (size_t)(R * hs[i].HW),
                                    hipMemcpyDeviceToDevice, s));
         if (sweeps_done_out) sweeps_done_out[i] = runs[i].k_star;
+        if (converged_out) converged_out[i] = runs[i].converged != 0 ? 1 : 0;
         all_converged &= runs[i].converged != 0;
     }
     if (!all_converged) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
@@ -1251,8 +1252,8 @@ size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_s
 }
 
 mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
-                                int32_t* sweeps_done_out, int32_t* tile_h_used_out, void* workspace, size_t ws_bytes,
-                                void* stream)
+                                int32_t* sweeps_done_out, int32_t* converged_out, int32_t* tile_h_used_out,
+                                void* workspace, size_t ws_bytes, void* stream)
 {
     mpr_status st = check_batched(scenes, n_scenes, cfg, tile_h);
     if (st != MPR_OK) return st;
@@ -1276,16 +1277,19 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
         if (st == MPR_WARN_NOT_CONVERGED) warn = true;
         else if (st != MPR_OK) return st;
         if (sweeps_done_out) sweeps_done_out[i] = k;
+        if (converged_out) converged_out[i] = st == MPR_OK ? 1 : 0;
     }
     if (tile_h_used_out) *tile_h_used_out = 0;
     if (!tiles.empty()) {
-        std::vector<int32_t> k(tiles.size(), 0);
-        st = batched_tiles(tiles.data(), (int32_t)tiles.size(), cfg, tile_h, k.data(), tile_h_used_out, workspace,
-                           ws_bytes, stream);
+        std::vector<int32_t> k(tiles.size(), 0), cv(tiles.size(), 1);
+        st = batched_tiles(tiles.data(), (int32_t)tiles.size(), cfg, tile_h, k.data(), cv.data(), tile_h_used_out,
+                           workspace, ws_bytes, stream);
         if (st == MPR_WARN_NOT_CONVERGED) warn = true;
         else if (st != MPR_OK) return st;
-        if (sweeps_done_out)
-            for (size_t j = 0; j < tiles.size(); ++j) sweeps_done_out[tile_index[j]] = k[j];
+        for (size_t j = 0; j < tiles.size(); ++j) {
+            if (sweeps_done_out) sweeps_done_out[tile_index[j]] = k[j];
+            if (converged_out) converged_out[tile_index[j]] = cv[j];
+        }
     }
     if (warn) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
     return ok();
@@ -1303,7 +1307,6 @@ mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* 
     double ns[mpr::kProbeCount];
     MPR_HIP(mpr::time_probes(static_cast<uint32_t*>(workspace), S(stream), ns));
     for (int i = 0; i < mpr::kProbeCount; ++i) cost_out[i] = ns[i] / ns[0];
-    cost_out[1] -= 1.0;                 // the 64-bit product probe also executes one xor per step
     if (add_ns_out) *add_ns_out = ns[0] / mpr::probe_wave_instructions();
     return ok();
 }

@@ -176,9 +176,11 @@ hipError_t launch_sst(const float* T_blocks, int64_t H, int64_t W, int32_t lb_h,
                       int32_t n_s, double* a, double* b, float* out, hipStream_t s);
 
 // ---- instruction-rate probe (rates.hip) ----
-// Probes, in order: v_add_u32, v_mad_u64_u32 (+ one v_xor_b32 per step), v_mul_lo_u32, v_mul_hi_u32, v_bitop3_b32,
-// v_sin_f32, v_cos_f32, v_exp_f32, v_cvt_f32_u32.  ns[i] = kernel time of probe i (same instruction count each).
-constexpr int kProbeCount = 9;
+// Probes, in order: v_add_u32, v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32, v_bitop3_b32, v_sin_f32, v_cos_f32,
+// v_exp_f32, v_cvt_f32_u32, v_xor_b32, and two pairs: v_mad_u64_u32 with an independent v_add_u32, and
+// v_mad_u64_u32 feeding a v_bitop3_b32.  ns[i] = kernel time of probe i per wave-instruction of the probe, times the
+// number of wave-instructions of the v_add_u32 probe (so that ns[i] / ns[0] is the issue cost relative to the add).
+constexpr int kProbeCount = 12;
 int probe_grid();
 size_t probe_out_bytes();
 double probe_wave_instructions();

@@ -484,6 +484,11 @@ struct RlWave {
     }
 };
 
+// A band starts on a column that is a multiple of 4 (its Philox pairs are whole: pair index x0 / 4 + m), a segment on
+// a row that is a multiple of 4 (window slot = row & 3, colour parity = slot parity).
+static_assert(kRlBand % 4 == 0, "bands must start on a multiple of 4 columns");
+static_assert(kRlSegRows % 4 == 0, "row segments must start on a multiple of 4 rows");
+
 template <int TM, bool ENERGY, bool DIR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kRlWaves))) void k_sweep_rl(
     RlArgs a, const uint2* __restrict__ cells, const void* __restrict__ tbv, const float* __restrict__ src,
@@ -604,10 +609,14 @@ RlGeom rl_geometry(int64_t H, int64_t W, int R)
     g.nbands = (int)((W + kRlBand - 1) / kRlBand);
     // row segments of kRlSegRows rows, halved (down to 32) while the grid has fewer than kRlTargetWaves waves:
     // each segment adds two ring rows of colour-0 updates
+    // (segments start on rows that are multiples of 4: the first two rows of a segment's window go to slots 2 and 3,
+    // and the colour of a step's rows follows from the slot; halved heights are rounded up to a multiple of 4)
     const int64_t groups = g.Rp / 64;
     g.seg_rows = kRlSegRows;
-    while (g.seg_rows > 32 && (int64_t)g.nbands * ((H + g.seg_rows - 1) / g.seg_rows) * groups < kRlTargetWaves)
-        g.seg_rows = g.seg_rows / 2 > 32 ? g.seg_rows / 2 : 32;
+    while (g.seg_rows > 32 && (int64_t)g.nbands * ((H + g.seg_rows - 1) / g.seg_rows) * groups < kRlTargetWaves) {
+        const int half = (g.seg_rows / 2 + 3) / 4 * 4;
+        g.seg_rows = half > 32 ? half : 32;
+    }
     g.nseg = (int)((H + g.seg_rows - 1) / g.seg_rows);
     g.n_items = (int64_t)g.nbands * g.nseg * groups;
     return g;

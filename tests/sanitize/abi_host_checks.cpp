@@ -137,12 +137,12 @@ int main()
     expect(mpr_sweep(fp, fp, mp, 8, 8, fp, 4, 4, nullptr, 1, 1, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
            "sweep cfg NULL");
     expect(mpr_sst_temperatures(fp, 8, 8, 4, 4, -1, 2, fp, ws, 64, nullptr), MPR_ERR_INVALID_ARG, "sst r_s < 0");
-    expect(mpr_simulate_batched(sc.data(), 0, &c, 0, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
+    expect(mpr_simulate_batched(sc.data(), 0, &c, 0, nullptr, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
            "batched without scenes");
-    expect(mpr_simulate_batched(sc.data(), 4, &c, 24, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
+    expect(mpr_simulate_batched(sc.data(), 4, &c, 24, nullptr, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
            "batched tile_h 24");
     sc[2].state = nullptr;
-    expect(mpr_simulate_batched(sc.data(), 4, &c, 0, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
+    expect(mpr_simulate_batched(sc.data(), 4, &c, 0, nullptr, nullptr, nullptr, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
            "batched NULL state");
     expect(mpr_temperature_grad(fp, dp, fp, mp, 8, 8, 1, 4, dp, fp, dp, ws, 64, nullptr), MPR_ERR_INVALID_ARG,
            "gradient with one realization");

@@ -86,3 +86,47 @@ def test_batched_mixed_kernels_equal_single_scene():
     only_lanes = M.mpr_simulate_batched(scenes[:1], cfg)
     assert only_lanes.tile_h == 0
     assert np.array_equal(host(only_lanes.outputs[0].state), host(b.outputs[0].state))
+
+
+ORACLE_SHAPES = [(40, 52, 0.5, 21), (23, 70, 0.3, 22), (64, 31, 0.8, 23), (1, 45, 0.5, 24), (33, 33, 0.9, 25),
+                 (9, 9, 0.4, 26)]
+
+
+@pytest.mark.parametrize("kernel", ["auto", "lanes"])
+def test_batched_matches_oracle(kernel):
+    """Every scene of a batched call with the automatic stop against the oracle run of that scene (its own scene_id,
+    all 64 realizations): the same stopping sweep (or a marginal slope where they differ), the energy series within
+    1e-5 per bond, states equal at >= 99.99 % of (realization, site), the prediction's mean |dphi| <= 1e-3 rad.
+    'auto' sends these small scenes to the persistent batch, 'lanes' to the realization-lane sweep."""
+    lb = (16, 16)
+    R = 64
+    host_scenes, scenes = [], []
+    for i, (H, W, p, seed) in enumerate(ORACLE_SHAPES):
+        sc = synth.random_small(H, W, p, seed=seed)
+        sc.mask.ravel()[0] = 1
+        t, _ = oracle.map_angles(sc.z_obs, sc.mask)
+        B = (-(-H // lb[0])) * (-(-W // lb[1]))
+        T = np.random.default_rng(seed).uniform(0.02, 0.5, B).astype(np.float32)
+        host_scenes.append((t, sc.mask, T))
+        scenes.append(dict(t=dev(t), mask=dev(sc.mask), T_blocks=dev(T), block=lb, scene_id=3000 + i))
+    sk = M.SWEEP_LANES if kernel == "lanes" else M.SWEEP_AUTO
+    cfg = M.SimConfig(n_real=R, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_max=150, seed=91,
+                      sweep_kernel=sk)
+    print(f"[batched vs oracle] {kernel}", flush=True)
+    b = M.mpr_simulate_batched(scenes, cfg, want_energy=True)
+    for i, ((t, mask, T), out) in enumerate(zip(host_scenes, b.outputs)):
+        o = oracle.simulate(t, mask, T, *lb, oracle.SimConfig(n_real=R, init_mode=1, stop_mode=1, n_samp=1, n_max=150,
+                                                              seed=91, scene=3000 + i), parallel=True)
+        eg = host(out.energy)
+        n = min(len(eg), len(o.energy))
+        assert np.max(np.abs(eg[:n] - o.energy[:n])) <= 1e-5, i
+        assert out.converged == o.converged, i
+        if out.sweeps != o.k_star:
+            k = min(out.sweeps, o.k_star)
+            assert abs(oracle.ols_slope(o.energy[k - 19: k + 1])) < 1e-5, (i, out.sweeps, o.k_star)
+            continue
+        gs = host(out.state)
+        assert float(np.mean(gs == o.state)) >= 0.9999, i
+        gap = mask == 0
+        dphi = 2 * np.pi * np.abs(host(out.acc)[gap] - o.acc[gap]) / R
+        assert dphi.size == 0 or dphi.mean() <= 1e-3, i

@@ -1,6 +1,10 @@
 """Parity at the configurations' full sizes, in the launch configuration the benchmark times: all realizations run
 on the GPU, and sampled realizations are recomputed by the oracle one by one (the random stream is keyed by the
-global realization index, so a one-realization oracle run reproduces realization r exactly)."""
+global realization index, so a one-realization oracle run reproduces realization r exactly).  The headline
+configuration is checked at its three gap fractions; the automatic stop at full size is checked through properties
+that hold at any size."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import torch
@@ -22,28 +26,78 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("which", ["c3_p0.6", "c2"])
-def test_fullsize_sampled_realizations(which):
+def _curve():
+    T_curve = np.geomspace(1e-3, 1e2, 31).astype(np.float32)
+    e_curve = oracle.reference_curve(T_curve, L=16, n_therm=40, n_meas=40, seed=5)
+    return dev(T_curve.astype(np.float64)), dev(e_curve)
+
+
+# (case, fixed sweeps): 4096^2 at the three gap fractions of the headline configuration, and the 1024^2 SV-MPR one
+CASES = [("c3_p0.3", 20), ("c3_p0.6", 4), ("c3_p0.9", 12), ("c2", 2)]
+
+
+@pytest.mark.parametrize("which,n_eq", CASES)
+def test_fullsize_sampled_realizations(which, n_eq):
     if which == "c2":
         sc, R, lb, seed = synth.config2(), 100, (16, 16), synth.seed_for(2, synth.ROLE_PHILOX)
     else:
-        sc, R, lb, seed = synth.config3(0.6), 256, (32, 32), synth.seed_for(3, synth.ROLE_PHILOX)
-    print(f"case {which}: {sc.z_true.shape}, R = {R}", flush=True)
+        sc, R, lb, seed = synth.config3(float(which.split("p")[1])), 256, (32, 32), synth.seed_for(3, synth.ROLE_PHILOX)
+    print(f"case {which}: {sc.z_true.shape}, R = {R}, {n_eq} + 1 sweeps", flush=True)
     z, m = dev(sc.z_obs), dev(sc.mask)
     t, rg = M.mpr_map_angles(z, m)
-    T_curve = np.geomspace(1e-3, 1e2, 31).astype(np.float32)
-    e_curve = oracle.reference_curve(T_curve, L=16, n_therm=40, n_meas=40, seed=5)
-    T, _, _ = M.mpr_calibrate_temperature(t, m, lb[0], lb[1], dev(T_curve.astype(np.float64)), dev(e_curve))
-    cfg = M.SimConfig(n_real=R, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=2, n_samp=1, seed=seed)
+    T, _, _ = M.mpr_calibrate_temperature(t, m, lb[0], lb[1], *_curve())
+    cfg = M.SimConfig(n_real=R, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_FIXED, n_eq=n_eq, n_samp=1, seed=seed)
     g = M.mpr_simulate(t, m, T, lb[0], lb[1], cfg)
     t_h, T_h = host(t), host(T)
     gs = host(g.state)
     eg = host(g.energy)
-    for r in (0, R - 1):
-        o = oracle.simulate(t_h, sc.mask, T_h, lb[0], lb[1],
-                            OCfg(n_real=1, real_offset=r, init_mode=1, stop_mode=0, n_eq=2, n_samp=1, seed=seed))
+
+    def one(r):
+        return oracle.simulate(t_h, sc.mask, T_h, lb[0], lb[1],
+                               OCfg(n_real=1, real_offset=r, init_mode=1, stop_mode=0, n_eq=n_eq, n_samp=1, seed=seed))
+
+    with ThreadPoolExecutor(2) as ex:
+        outs = list(ex.map(one, (0, R - 1)))
+    for r, o in zip((0, R - 1), outs):
         frac = float(np.mean(gs[r] == o.state[0]))
         print(f"realization {r}: state agreement {frac:.7f}", flush=True)
         assert frac >= 0.9999
         # realization-averaged energies differ, but e(0) is the same for every realization under a block-mean start
         assert abs(eg[0] - o.energy[0]) <= 1e-5
+
+
+def test_fullsize_automatic_stop_properties():
+    """The headline run as the benchmark times it (4096^2, p = 0.6, R = 256, automatic stop, one sampling sweep):
+    the stopping sweep is the first check point at which the oracle's stopping rule accepts the GPU's energy series
+    (and none before it); e(0) equals the oracle's start energy; the accumulator is the FP64 sum over realizations of
+    the final states at the gaps and 0 at the samples; the samples are never modified."""
+    sc, R, lb, seed = synth.config3(0.6), 256, (32, 32), synth.seed_for(3, synth.ROLE_PHILOX)
+    print("case c3_p0.6 AUTO", flush=True)
+    z, m = dev(sc.z_obs), dev(sc.mask)
+    t, rg = M.mpr_map_angles(z, m)
+    T, _, _ = M.mpr_calibrate_temperature(t, m, lb[0], lb[1], *_curve())
+    cfg = M.SimConfig(n_real=R, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_fit=20, n_f=5,
+                      n_max=1000, seed=seed)
+    g = M.mpr_simulate(t, m, T, lb[0], lb[1], cfg)
+    e = host(g.energy)
+    k = g.sweeps
+    print(f"k* = {k}", flush=True)
+    assert len(e) == k + 1 and g.converged
+    assert oracle.stop_check(e, k, 20, 5)
+    for kk in range(1, k):
+        assert not oracle.stop_check(e, kk, 20, 5), kk
+    t_h = host(t)
+    o = oracle.simulate(t_h, sc.mask, host(T), lb[0], lb[1],
+                        OCfg(n_real=1, init_mode=1, stop_mode=0, n_eq=0, n_samp=0, seed=seed))
+    assert abs(e[0] - o.energy[0]) <= 1e-5
+    acc = g.acc.double()
+    gap = m == 0
+    rows = torch.arange(0, sc.mask.shape[0], 7, device=m.device)      # every 7th row
+    s_rows = torch.zeros_like(acc[rows])
+    for r in range(R):                                                # in realization order, as the definition adds
+        s_rows += g.state[r][rows].double()
+    assert torch.equal(acc[rows][gap[rows]], s_rows[gap[rows]])
+    assert torch.all(acc[~gap] == 0)
+    samp = ~gap
+    for r in (0, 97, R - 1):
+        assert torch.equal(g.state[r][samp], t[samp])

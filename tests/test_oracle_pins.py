@@ -543,3 +543,21 @@ def test_energy_series_of_simulate_is_the_realization_mean(orc):
     assert abs(res.energy[-1] - np.mean([orc.energy(res.state[r]) for r in range(3)])) < 1e-15
     start = orc.simulate(t, m, T, 5, 7, orc.SimConfig(**{**cfg.__dict__, "n_eq": 0}))
     assert abs(res.energy[0] - np.mean([orc.energy(start.state[r]) for r in range(3)])) < 1e-15
+
+
+def test_parallel_build_matches_the_plain_build(orc):
+    """The OpenMP build (realizations over threads, used to time the CPU baseline on all host cores) takes every sum
+    over realizations in realization order: states, accumulator, energy series and stopping sweep are bit-identical
+    to the single-threaded build, in FIXED and AUTO mode."""
+    rng = np.random.default_rng(12)
+    H, W = 24, 30
+    t = rng.random((H, W)).astype(np.float32)
+    m = (rng.random((H, W)) < 0.45).astype(np.uint8)
+    T = rng.uniform(0.05, 0.4, (3, 4)).astype(np.float32)
+    for cfg in (orc.SimConfig(n_real=7, init_mode=1, stop_mode=0, n_eq=9, n_samp=3, seed=3),
+                orc.SimConfig(n_real=5, init_mode=0, stop_mode=1, n_samp=2, n_max=60, seed=4)):
+        a = orc.simulate(t, m, T, 8, 8, cfg)
+        b = orc.simulate(t, m, T, 8, 8, cfg, parallel=True)
+        assert np.array_equal(a.state, b.state) and np.array_equal(a.acc, b.acc)
+        assert np.array_equal(a.energy, b.energy) and a.k_star == b.k_star
+    assert orc.threads(False) == 1 and orc.threads(True) >= 1
