@@ -141,6 +141,24 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
                                      int32_t n_curve, float* T_out, double* e_blocks_out, int32_t* nbonds_out,
                                      void* workspace, size_t ws_bytes, void* stream);
 
+/* Size in bytes of the static device scratch of the entry points that allocate nothing (one copy per device). */
+#define MPR_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid hipMalloc): the
+ * calibration of mpr_calibrate_temperature, with the same arguments, results and errors, but no workspace argument:
+ * its scratch is a static device array of MPR_NOALLOC_SCRATCH_BYTES (16 MiB) per device, which the library holds on
+ * every device it runs on until the process ends.  Grids and block sizes whose mpr_calibrate_workspace_bytes exceed
+ * that size return MPR_ERR_WORKSPACE_TOO_SMALL before any device work (4096 x 4096 with 32 x 32 blocks needs
+ * 0.56 MiB, 16384 x 16384 with 32 x 32 blocks 9 MiB).  Allocates nothing and calls no allocating routine.  The
+ * pointers and the stream belong to the current device, whose array is used (its address is looked up on the first
+ * call on that device).  Every call on a device shares that device's array, which keeps the last call's contents
+ * (nothing in it has to start at zero: the calibration writes every entry before reading it); calls that overlap on
+ * one device (other streams or host threads) race.  Synchronises the stream, like mpr_calibrate_temperature. */
+mpr_status mpr_calibrate_temperature_noalloc(const float* t, const uint8_t* mask, int64_t H, int64_t W,
+                                             int32_t lb_h, int32_t lb_w, float q, float J, const double* curve_T,
+                                             const double* curve_e, int32_t n_curve, float* T_out,
+                                             double* e_blocks_out, int32_t* nbonds_out, void* stream);
+
 /* Directional-coupling extension (Sec. 4 suggests an exchange interaction that depends on the direction, with the
  * parameters kept local to blocks): per block, Tx by the energy matching of mpr_calibrate_temperature applied to its
  * horizontal sample bonds only (a sample and its right neighbour) and Ty to its vertical ones (a sample and its

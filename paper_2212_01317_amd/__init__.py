@@ -12,12 +12,13 @@ import torch
 
 from .autograd import MPRFunction
 from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL, MprError, SimConfig, SimOutput, lib,
-                   mpr_block_stats, mpr_calibrate_temperature, mpr_calibrate_directional, mpr_map_angles, mpr_predict, mpr_reference_curve,
+                   mpr_block_stats, mpr_calibrate_temperature, mpr_calibrate_temperature_noalloc, mpr_calibrate_directional, mpr_map_angles, mpr_predict, mpr_reference_curve,
                    mpr_simulate, mpr_sweep, mpr_validate, mpr_block_energy, mpr_temperature_grad,
                    mpr_simulate_batched, BatchOutput, mpr_probe_instruction_rates, mpr_sst_temperatures)
 
 __all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "COUPLING_ISOTROPIC", "COUPLING_DIRECTIONAL", "MprError", "SimConfig", "SimOutput",
-           "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_calibrate_directional", "mpr_map_angles",
+           "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_calibrate_temperature_noalloc",
+           "mpr_calibrate_directional", "mpr_map_angles",
            "mpr_predict",
            "mpr_reference_curve", "mpr_simulate", "mpr_sweep", "mpr_validate", "default_T_grid", "reference_curve", "predict",
            "Prediction", "CURVE_SPEC", "MPRFunction", "mpr_block_energy", "mpr_temperature_grad",

@@ -105,6 +105,8 @@ _SIGS = {
     "mpr_calibrate_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "mpr_calibrate_temperature": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
                                    _sz, _vp], ctypes.c_int),
+    "mpr_calibrate_temperature_noalloc": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp,
+                                           _vp, _vp], ctypes.c_int),
     "mpr_calibrate_directional": ([_vp, _vp, _i64, _i64, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp, _vp, _vp, _sz,
                                    _vp], ctypes.c_int),
     "mpr_simulate_workspace_bytes": ([_i64, _i64, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
@@ -243,6 +245,30 @@ def mpr_calibrate_temperature(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.
     _check(lib().mpr_calibrate_temperature(_p(t), _p(mask), H, W, lb_h, lb_w, q, J, _p(curve_T), _p(curve_e),
                                            int(curve_T.numel()), _p(T), _p(eb), _p(nb), _p(ws), ws.numel(),
                                            _stream()))
+    return T, eb, nb
+
+
+def mpr_calibrate_temperature_noalloc(t, mask, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0, out=None):
+    """mpr_calibrate_temperature with the library's static device scratch instead of a workspace.  `out` = (T, e_b,
+    n_b) preallocated outputs ([nby, nbx] float32, float64, int32) makes the call allocate nothing at all."""
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(curve_T, torch.float64, "curve_T")
+    _dev(curve_e, torch.float64, "curve_e")
+    H, W = _hw(t)
+    nby, nbx = -(-H // lb_h), -(-W // lb_w)
+    if out is None:
+        out = (torch.empty((nby, nbx), dtype=torch.float32, device=t.device),
+               torch.empty((nby, nbx), dtype=torch.float64, device=t.device),
+               torch.empty((nby, nbx), dtype=torch.int32, device=t.device))
+    T, eb, nb = out
+    for x, dt, name in ((T, torch.float32, "T"), (eb, torch.float64, "e_b"), (nb, torch.int32, "n_b")):
+        _dev(x, dt, name)
+        if x.numel() != nby * nbx:
+            raise ValueError(f"{name} has {x.numel()} entries, the grid has {nby * nbx} blocks")
+    _check(lib().mpr_calibrate_temperature_noalloc(_p(t), _p(mask), H, W, lb_h, lb_w, q, J, _p(curve_T),
+                                                   _p(curve_e), int(curve_T.numel()), _p(T), _p(eb), _p(nb),
+                                                   _stream()))
     return T, eb, nb
 
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -45,6 +46,33 @@ mpr_status ok()
     } while (0)
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Scratch memory of the entry points that allocate nothing (mpr_calibrate_temperature_noalloc): a file-scope device
+// array, one copy per device, held until the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address is taken once per device with hipGetSymbolAddress (with that device current)
+// and only that address is passed to kernels.
+__device__ __align__(256) unsigned char scratch[MPR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the first call on that device).
+mpr_status scratch_for_current_device(void** out)
+{
+    int dev = -1;
+    MPR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPR_ERR_INVALID_ARG, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MPR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MPR_ERR_HIP, "hipGetSymbolAddress returned a NULL address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPR_OK;
+}
 
 mpr_status check_grid(int64_t H, int64_t W)
 {
@@ -648,6 +676,27 @@ mpr_status mpr_calibrate_temperature(const float* t, const uint8_t* mask, int64_
     if (n_have == 0)
         return fail(MPR_ERR_NO_SAMPLE_BONDS, "no pair of neighbouring samples: the temperature cannot be estimated");
     return ok();
+}
+
+mpr_status mpr_calibrate_temperature_noalloc(const float* t, const uint8_t* mask, int64_t H, int64_t W,
+                                             int32_t lb_h, int32_t lb_w, float q, float J, const double* curve_T,
+                                             const double* curve_e, int32_t n_curve, float* T_out,
+                                             double* e_blocks_out, int32_t* nbonds_out, void* stream)
+{
+    mpr_status st = check_grid(H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks(H, W, lb_h, lb_w)) != MPR_OK) return st;
+    const size_t need = mpr_calibrate_workspace_bytes(H, W, lb_h, lb_w);
+    if (need > (size_t)MPR_NOALLOC_SCRATCH_BYTES)
+        return fail(MPR_ERR_WORKSPACE_TOO_SMALL,
+                    "mpr_calibrate_temperature_noalloc: %lld x %lld with %d x %d blocks needs %zu bytes of scratch, "
+                    "the static scratch holds %zu (use mpr_calibrate_temperature with a workspace)",
+                    (long long)H, (long long)W, lb_h, lb_w, need, (size_t)MPR_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((st = scratch_for_current_device(&ws)) != MPR_OK) return st;
+    // every scratch entry the calibration reads is written earlier in the same call: nothing has to start at zero
+    return mpr_calibrate_temperature(t, mask, H, W, lb_h, lb_w, q, J, curve_T, curve_e, n_curve, T_out, e_blocks_out,
+                                     nbonds_out, ws, (size_t)MPR_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 mpr_status mpr_calibrate_directional(const float* t, const uint8_t* mask, int64_t H, int64_t W, int32_t lb_h,

@@ -65,6 +65,22 @@ def test_reference_curve_rejects_odd_lattice():
     assert L.mpr_reference_curve(0.6, dummy, 4, 16, 10, 10, 0, dummy, dummy, 1 << 30, None) == 1
 
 
+def test_noalloc_calibration_rejects_sizes_beyond_its_scratch():
+    """The entry point without a workspace refuses, before any device work, a grid whose calibration scratch exceeds
+    the static array (1 x 1 blocks on 4096^2 need 576 MiB), and accepts the size check of the headline shape."""
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(0x1000)     # never dereferenced: the size check fails first
+    assert L.mpr_calibrate_workspace_bytes(4096, 4096, 1, 1) > 16 << 20
+    assert L.mpr_calibrate_workspace_bytes(16384, 16384, 32, 32) <= 16 << 20
+    st = L.mpr_calibrate_temperature_noalloc(dummy, dummy, 4096, 4096, 1, 1, 0.5, 1.0, dummy, dummy, 4, dummy, None,
+                                             None, None)
+    assert st == 6
+    assert b"static scratch" in L.mpr_last_error()
+    st = L.mpr_calibrate_temperature_noalloc(dummy, dummy, 0, 4096, 32, 32, 0.5, 1.0, dummy, dummy, 4, dummy, None,
+                                             None, None)
+    assert st == 2
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(ValueError):
