@@ -122,6 +122,23 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_temperature_grad.restype = None
     L.orc_threads.argtypes = []
     L.orc_threads.restype = ctypes.c_int
+    # the 3D lattice
+    L.orc_site_uniforms3.argtypes = [_u64, _u32, _u32, _u32, _u32, _i64, _i64, _i64, _i64, _i64, _f64p]
+    L.orc_site_uniforms3.restype = None
+    L.orc_block_stats3.argtypes = [_f32p, _u8p, _i64, _i64, _i64, _i32, _i32, _i32, _flt, _flt, _f64p, _i32p, _f64p,
+                                   _i32p]
+    L.orc_block_stats3.restype = None
+    L.orc_sweep3.argtypes = [_f32p, _u8p, _i64, _i64, _i64, _f32p, _i32, _i32, _i32, _flt, _flt, _u64, _u32, _u32,
+                             _u32]
+    L.orc_sweep3.restype = None
+    L.orc_energy3.argtypes = [_f32p, _i64, _i64, _i64, _flt, _flt]
+    L.orc_energy3.restype = _dbl
+    L.orc_reference_curve3.argtypes = [_flt, _f32p, _i32, _i32, _i32, _i32, _u64, _f64p]
+    L.orc_reference_curve3.restype = None
+    L.orc_simulate3.argtypes = [_f32p, _u8p, _i64, _i64, _i64, _f32p, _i32, _i32, _i32, _flt, _flt, _i32, _i32, _i32,
+                                _i32, _i32, _i32, _i32, _i32, _i32, _u64, _u32, _f32p, _f64p, _f64p,
+                                ctypes.POINTER(_i32)]
+    L.orc_simulate3.restype = _i32
 
 
 # ---------------------------------------------------------------------------------------------------------------
@@ -378,3 +395,75 @@ def temperature_grad(states, Hrb, w, T_blocks):
     out = np.zeros(B, np.float64)
     lib().orc_temperature_grad(st, Hrb, _c(w, np.float64).ravel(), HW, R, B, _c(T_blocks, np.float32).ravel(), out)
     return out
+
+
+# ---------------------------------------------------------------------------------------------------------------
+# the 3D lattice (Sec. 4 extension): grids are [D, H, W], blocks (lb_d, lb_h, lb_w)
+# ---------------------------------------------------------------------------------------------------------------
+
+def n_blocks3(D, H, W, lb_d, lb_h, lb_w):
+    return (-(-D // lb_d)), (-(-H // lb_h)), (-(-W // lb_w))
+
+
+def site_uniforms3(seed, scene, tag, sweep, real, H, W, x, y, z):
+    out = np.zeros(2, np.float64)
+    lib().orc_site_uniforms3(seed, scene, tag, sweep, real, H, W, x, y, z, out)
+    return out
+
+
+def block_stats3(t, mask, lb_d, lb_h, lb_w, q=0.5, J=1.0):
+    t = _c(t, np.float32)
+    mask = _c(mask, np.uint8)
+    D, H, W = t.shape
+    B = int(np.prod(n_blocks3(D, H, W, lb_d, lb_h, lb_w)))
+    S, Ts = np.zeros(B, np.float64), np.zeros(B, np.float64)
+    N, No = np.zeros(B, np.int32), np.zeros(B, np.int32)
+    lib().orc_block_stats3(t, mask, D, H, W, lb_d, lb_h, lb_w, q, J, S, N, Ts, No)
+    return S, N, Ts, No
+
+
+def calibrate_temperature3(t, mask, lb_d, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    """Eq. (2) per 3D block, energy matching with a matching curve of the 3D model, median fill."""
+    D, H, W = np.shape(t)
+    S, N, _, _ = block_stats3(t, mask, lb_d, lb_h, lb_w, q, J)
+    T = calibrate_blocks(S, N, curve_T, curve_e, J)
+    shp = n_blocks3(D, H, W, lb_d, lb_h, lb_w)
+    return T.reshape(shp), S.reshape(shp), N.reshape(shp)
+
+
+def sweep3(state, mask, T_blocks, lb_d, lb_h, lb_w, k, q=0.5, J=1.0, seed=0, scene=0, real=0):
+    assert state.dtype == np.float32 and state.flags["C_CONTIGUOUS"]
+    D, H, W = state.shape
+    lib().orc_sweep3(state, _c(mask, np.uint8), D, H, W, _c(T_blocks, np.float32).ravel(), lb_d, lb_h, lb_w, q, J,
+                     seed, scene, real, k)
+
+
+def energy3(state, q=0.5, J=1.0) -> float:
+    s = _c(state, np.float32)
+    D, H, W = s.shape
+    return lib().orc_energy3(s, D, H, W, q, J)
+
+
+def reference_curve3(T_grid, L=16, n_therm=200, n_meas=400, seed=0, q=0.5):
+    Tg = _c(T_grid, np.float32)
+    e = np.zeros(len(Tg), np.float64)
+    lib().orc_reference_curve3(q, Tg, len(Tg), L, n_therm, n_meas, seed, e)
+    return e
+
+
+def simulate3(t, mask, T_blocks, lb_d, lb_h, lb_w, cfg: SimConfig, parallel: bool = False) -> SimResult:
+    """Conditional simulation of a [D, H, W] scene (block temperatures, single-checkerboard order)."""
+    t = _c(t, np.float32)
+    mask = _c(mask, np.uint8)
+    D, H, W = t.shape
+    R = cfg.n_real
+    state = np.zeros((R, D, H, W), np.float32)
+    acc = np.zeros((D, H, W), np.float64)
+    ncap = (cfg.n_max if cfg.stop_mode == 1 else cfg.n_eq) + 1
+    en = np.zeros(ncap, np.float64)
+    conv = _i32(0)
+    k = lib(parallel).orc_simulate3(t, mask, D, H, W, _c(T_blocks, np.float32).ravel(), lb_d, lb_h, lb_w, cfg.q,
+                                    cfg.J, R, cfg.real_offset, cfg.init_mode, cfg.stop_mode, cfg.n_eq, cfg.n_samp,
+                                    cfg.n_fit, cfg.n_f, cfg.n_max, cfg.seed, cfg.scene, state, acc, en,
+                                    ctypes.byref(conv))
+    return SimResult(state=state, acc=acc, energy=en[: k + 1].copy(), k_star=int(k), converged=bool(conv.value))

@@ -810,3 +810,302 @@ void orc_temperature_grad(const float* states, const double* Hrb, const double* 
     }
     free(g);
 }
+
+/* ============================================================================================================
+ * The three-dimensional lattice (the extension to 3D named in Sec. 4).  Reading: the same model on a D x H x W grid
+ * of sites n = (z*H + y)*W + x with the six nearest neighbours of the simple cubic lattice and open boundaries; the
+ * two colours of the checkerboard are c = (x + y + z) mod 2 (sites of one colour share no bond); the temperature
+ * blocks are lb_d x lb_h x lb_w boxes, b = ((z/lb_d)*nby + y/lb_h)*nbx + x/lb_w; every site owns the bonds to its
+ * +x, +y and +z neighbours.  The random-number stream is that of the plane with the row index r = z*H + y in place
+ * of y and the colour (x + y + z) mod 2: pair index r*((W + 3)/4) + (x >> 2), words 2*((x >> 1) & 1) and the next.
+ * On one plane (D = 1) every function below is the two-dimensional one.
+ * ============================================================================================================ */
+static void site_uniforms3(uint64_t seed, uint32_t scene, uint32_t tag, uint32_t sweep, uint32_t real, int64_t H,
+                           int64_t W, int64_t x, int64_t y, int64_t z, double* u1, double* u2)
+{
+    uint32_t colour = (uint32_t)((x + y + z) & 1);
+    int64_t row = z * H + y;
+    uint32_t pair = (uint32_t)(row * ((W + 3) / 4) + (x >> 2));
+    uint32_t ctr[4] = { pair, sweep, real, (scene << 4) | (tag << 1) | colour };
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    int half = (int)((x >> 1) & 1);
+    *u1 = u24(w[2 * half]);
+    *u2 = u24(w[2 * half + 1]);
+}
+
+void orc_site_uniforms3(uint64_t seed, uint32_t scene, uint32_t tag, uint32_t sweep, uint32_t real, int64_t H,
+                        int64_t W, int64_t x, int64_t y, int64_t z, double out[2])
+{
+    site_uniforms3(seed, scene, tag, sweep, real, H, W, x, y, z, &out[0], &out[1]);
+}
+
+/* Eq. (2) per 3D block: sample-bond energies and counts over the +x, +y, +z bonds whose ends are both samples, and
+ * the sum and count of the observed t. */
+void orc_block_stats3(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W, int32_t lb_d,
+                      int32_t lb_h, int32_t lb_w, float q, float J, double* S, int32_t* N, double* Tsum, int32_t* Nobs)
+{
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h, nbz = (D + lb_d - 1) / lb_d;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    int64_t HW = H * W;
+    for (int64_t b = 0; b < nbx * nby * nbz; ++b) {
+        S[b] = 0.0;
+        N[b] = 0;
+        Tsum[b] = 0.0;
+        Nobs[b] = 0;
+    }
+    for (int64_t z = 0; z < D; ++z) {
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = 0; x < W; ++x) {
+                int64_t n = z * HW + y * W + x;
+                if (!mask[n]) continue;
+                int64_t b = ((z / lb_d) * nby + y / lb_h) * nbx + x / lb_w;
+                Tsum[b] += (double)t[n];
+                Nobs[b] += 1;
+                if (x + 1 < W && mask[n + 1]) {
+                    S[b] += bond_energy(t[n], t[n + 1], tpq, J);
+                    N[b] += 1;
+                }
+                if (y + 1 < H && mask[n + W]) {
+                    S[b] += bond_energy(t[n], t[n + W], tpq, J);
+                    N[b] += 1;
+                }
+                if (z + 1 < D && mask[n + HW]) {
+                    S[b] += bond_energy(t[n], t[n + HW], tpq, J);
+                    N[b] += 1;
+                }
+            }
+        }
+    }
+}
+
+/* One Metropolis update of gap site (x, y, z): the proposal and the test of metropolis_site, over the in-grid
+ * neighbours in the order back (z - 1), up, left, right, down, front (z + 1); `periodic` wraps them (reference
+ * lattice only). */
+static void metropolis_site3(float* s, int64_t D, int64_t H, int64_t W, int64_t x, int64_t y, int64_t z, double T,
+                             double two_pi_q, double J, double u1, double u2, int periodic)
+{
+    int64_t HW = H * W;
+    int64_t n = z * HW + y * W + x;
+    double t_old = (double)s[n];
+    double t_new = (double)(float)u1;
+    int64_t nb[6];
+    int cnt = 0;
+    if (periodic) {
+        nb[cnt++] = ((z + D - 1) % D) * HW + y * W + x;
+        nb[cnt++] = z * HW + ((y + H - 1) % H) * W + x;
+        nb[cnt++] = z * HW + y * W + (x + W - 1) % W;
+        nb[cnt++] = z * HW + y * W + (x + 1) % W;
+        nb[cnt++] = z * HW + ((y + 1) % H) * W + x;
+        nb[cnt++] = ((z + 1) % D) * HW + y * W + x;
+    } else {
+        if (z > 0) nb[cnt++] = n - HW;
+        if (y > 0) nb[cnt++] = n - W;
+        if (x > 0) nb[cnt++] = n - 1;
+        if (x + 1 < W) nb[cnt++] = n + 1;
+        if (y + 1 < H) nb[cnt++] = n + W;
+        if (z + 1 < D) nb[cnt++] = n + HW;
+    }
+    double acc = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+        double tj = (double)s[nb[i]];
+        acc += cos(two_pi_q * (t_new - tj)) - cos(two_pi_q * (t_old - tj));
+    }
+    double dE = -J * acc;
+    int accept;
+    if (T > 0.0) {
+        accept = u2 < exp(-dE / T);
+    } else {
+        accept = dE <= 0.0;
+    }
+    if (accept) s[n] = (float)t_new;
+}
+
+/* Single-checkerboard sweep of the 3D grid: all gap sites of colour 0, then of colour 1, each with the temperature
+ * of its block. */
+void orc_sweep3(float* s, const uint8_t* mask, int64_t D, int64_t H, int64_t W, const float* T_blocks, int32_t lb_d,
+                int32_t lb_h, int32_t lb_w, float q, float J, uint64_t seed, uint32_t scene, uint32_t real,
+                uint32_t sweep)
+{
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h;
+    double tpq = 2.0 * ORC_PI * (double)q;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int64_t z = 0; z < D; ++z) {
+            for (int64_t y = 0; y < H; ++y) {
+                for (int64_t x = (y + z + colour) & 1; x < W; x += 2) {
+                    if (mask[(z * H + y) * W + x]) continue;
+                    double T = (double)T_blocks[((z / lb_d) * nby + y / lb_h) * nbx + x / lb_w];
+                    double u1, u2;
+                    site_uniforms3(seed, scene, ORC_TAG_SWEEP, sweep, real, H, W, x, y, z, &u1, &u2);
+                    metropolis_site3(s, D, H, W, x, y, z, T, tpq, (double)J, u1, u2, 0);
+                }
+            }
+        }
+    }
+}
+
+/* Whole-grid specific energy of the 3D grid: Eq. (1) summed over all bonds, divided by J times their number. */
+double orc_energy3(const float* s, int64_t D, int64_t H, int64_t W, float q, float J)
+{
+    double tpq = 2.0 * ORC_PI * (double)q;
+    int64_t HW = H * W;
+    double sum = 0.0;
+    int64_t nbonds = 0;
+    for (int64_t z = 0; z < D; ++z) {
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = 0; x < W; ++x) {
+                int64_t n = z * HW + y * W + x;
+                if (x + 1 < W) {
+                    sum += bond_energy(s[n], s[n + 1], tpq, (double)J);
+                    ++nbonds;
+                }
+                if (y + 1 < H) {
+                    sum += bond_energy(s[n], s[n + W], tpq, (double)J);
+                    ++nbonds;
+                }
+                if (z + 1 < D) {
+                    sum += bond_energy(s[n], s[n + HW], tpq, (double)J);
+                    ++nbonds;
+                }
+            }
+        }
+    }
+    return nbonds > 0 ? sum / ((double)J * (double)nbonds) : 0.0;
+}
+
+/* The matching curve of the 3D model: equilibrium energy per bond of the unconditional model at J = 1 on a periodic
+ * L x L x L lattice (L even), one chain per temperature (realization index i of the reference stream), started
+ * from t = 1/2, n_therm sweeps, then the per-bond energy (3 L^3 bonds) averaged over n_meas sweeps. */
+void orc_reference_curve3(float q, const float* T_grid, int32_t nT, int32_t L, int32_t n_therm, int32_t n_meas,
+                          uint64_t seed, double* e_out)
+{
+    double tpq = 2.0 * ORC_PI * (double)q;
+    int64_t L3 = (int64_t)L * L * L, L2 = (int64_t)L * L;
+    float* s = (float*)malloc(sizeof(float) * (size_t)L3);
+    for (int32_t i = 0; i < nT; ++i) {
+        double T = (double)T_grid[i];
+        for (int64_t n = 0; n < L3; ++n) s[n] = 0.5f;
+        double acc_e = 0.0;
+        for (int32_t k = 1; k <= n_therm + n_meas; ++k) {
+            for (int colour = 0; colour < 2; ++colour) {
+                for (int64_t z = 0; z < L; ++z) {
+                    for (int64_t y = 0; y < L; ++y) {
+                        for (int64_t x = (y + z + colour) & 1; x < L; x += 2) {
+                            double u1, u2;
+                            site_uniforms3(seed, 0u, ORC_TAG_REFCURVE, (uint32_t)k, (uint32_t)i, L, L, x, y, z, &u1,
+                                           &u2);
+                            metropolis_site3(s, L, L, L, x, y, z, T, tpq, 1.0, u1, u2, 1);
+                        }
+                    }
+                }
+            }
+            if (k > n_therm) {
+                double sum = 0.0;
+                for (int64_t z = 0; z < L; ++z)
+                    for (int64_t y = 0; y < L; ++y)
+                        for (int64_t x = 0; x < L; ++x) {
+                            double tn = (double)s[z * L2 + y * L + x];
+                            sum += bond_energy(tn, (double)s[z * L2 + y * L + (x + 1) % L], tpq, 1.0);
+                            sum += bond_energy(tn, (double)s[z * L2 + ((y + 1) % L) * L + x], tpq, 1.0);
+                            sum += bond_energy(tn, (double)s[((z + 1) % L) * L2 + y * L + x], tpq, 1.0);
+                        }
+                acc_e += sum / (3.0 * (double)L3);
+            }
+        }
+        e_out[i] = n_meas > 0 ? acc_e / (double)n_meas : 0.0;
+    }
+    free(s);
+}
+
+/* Conditional simulation of one 3D scene, all realizations in lockstep, with the steps of orc_simulate (block-mean
+ * or uniform start, energy series e(0..k), FIXED or AUTO stop by orc_stop_check with the cap n_max, n_samp sampling
+ * sweeps accumulated into acc), single-checkerboard order and block temperatures.  Returns k*; *converged as in
+ * orc_simulate. */
+int32_t orc_simulate3(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W, const float* T_blocks,
+                      int32_t lb_d, int32_t lb_h, int32_t lb_w, float q, float J, int32_t R, int32_t real_offset,
+                      int32_t init_mode, int32_t stop_mode, int32_t n_eq, int32_t n_samp, int32_t n_fit, int32_t n_f,
+                      int32_t n_max, uint64_t seed, uint32_t scene, float* state, double* acc, double* energy,
+                      int32_t* converged)
+{
+    int64_t n_all = D * H * W;
+    int64_t nbx = (W + lb_w - 1) / lb_w, nby = (H + lb_h - 1) / lb_h, nbz = (D + lb_d - 1) / lb_d;
+    int64_t B = nbx * nby * nbz;
+    double* S = (double*)malloc(sizeof(double) * (size_t)B);
+    int32_t* N = (int32_t*)malloc(sizeof(int32_t) * (size_t)B);
+    double* Tsum = (double*)malloc(sizeof(double) * (size_t)B);
+    int32_t* Nobs = (int32_t*)malloc(sizeof(int32_t) * (size_t)B);
+    orc_block_stats3(t, mask, D, H, W, lb_d, lb_h, lb_w, q, J, S, N, Tsum, Nobs);
+    double all_sum = 0.0;
+    int64_t all_cnt = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        all_sum += Tsum[b];
+        all_cnt += Nobs[b];
+    }
+    float global_mean = all_cnt > 0 ? (float)(all_sum / (double)all_cnt) : 0.0f;
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < R; ++r) {
+        float* s = state + (int64_t)r * n_all;
+        uint32_t real = (uint32_t)(r + real_offset);
+        for (int64_t z = 0; z < D; ++z) {
+            for (int64_t y = 0; y < H; ++y) {
+                for (int64_t x = 0; x < W; ++x) {
+                    int64_t n = (z * H + y) * W + x;
+                    if (mask[n]) {
+                        s[n] = t[n];
+                    } else if (init_mode == 1) {
+                        int64_t b = ((z / lb_d) * nby + y / lb_h) * nbx + x / lb_w;
+                        s[n] = Nobs[b] > 0 ? (float)(Tsum[b] / (double)Nobs[b]) : global_mean;
+                    } else {
+                        double u1, u2;
+                        site_uniforms3(seed, scene, ORC_TAG_INIT, 0u, real, H, W, x, y, z, &u1, &u2);
+                        s[n] = (float)u1;
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t n = 0; n < n_all; ++n) acc[n] = 0.0;
+    int32_t k_cap = stop_mode == 1 ? n_max : n_eq;
+    double* e_r = (double*)malloc(sizeof(double) * (size_t)R);
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < R; ++r) e_r[r] = orc_energy3(state + (int64_t)r * n_all, D, H, W, q, J);
+    double e0 = 0.0;
+    for (int32_t r = 0; r < R; ++r) e0 += e_r[r];
+    energy[0] = e0 / (double)R;
+    int32_t k = 0;
+    *converged = 1;
+    while (k < k_cap) {
+        ++k;
+#pragma omp parallel for schedule(static)
+        for (int32_t r = 0; r < R; ++r) {
+            float* s = state + (int64_t)r * n_all;
+            orc_sweep3(s, mask, D, H, W, T_blocks, lb_d, lb_h, lb_w, q, J, seed, scene, (uint32_t)(r + real_offset),
+                       (uint32_t)k);
+            e_r[r] = orc_energy3(s, D, H, W, q, J);
+        }
+        double ek = 0.0;
+        for (int32_t r = 0; r < R; ++r) ek += e_r[r];
+        energy[k] = ek / (double)R;
+        if (stop_mode == 1 && orc_stop_check(energy, k, n_fit, n_f)) break;
+        if (stop_mode == 1 && k == n_max) *converged = 0;
+    }
+    int32_t k_star = k;
+    for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
+#pragma omp parallel for schedule(static)
+        for (int32_t r = 0; r < R; ++r)
+            orc_sweep3(state + (int64_t)r * n_all, mask, D, H, W, T_blocks, lb_d, lb_h, lb_w, q, J, seed, scene,
+                       (uint32_t)(r + real_offset), (uint32_t)(k_star + s_i));
+        for (int32_t r = 0; r < R; ++r) {
+            const float* s = state + (int64_t)r * n_all;
+            for (int64_t n = 0; n < n_all; ++n)
+                if (!mask[n]) acc[n] += (double)s[n];
+        }
+    }
+    free(e_r);
+    free(S);
+    free(N);
+    free(Tsum);
+    free(Nobs);
+    return k_star;
+}
