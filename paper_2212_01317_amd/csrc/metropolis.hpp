@@ -16,13 +16,11 @@ __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// a ^ b ^ k in one gfx950 three-input bit operation (truth table 0x96 over the inputs a = 0xF0, b = 0xCC, k = 0xAA);
-// k is wave-uniform (a Philox round key) and stays in a scalar register.
+// a ^ b ^ k in one gfx950 three-input bit operation (truth table 0x96 over the inputs a = 0xF0, b = 0xCC, k = 0xAA).
+// The builtin, not inline assembly: the compiler then knows the instruction and inserts no wait states for it.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
 {
-    uint32_t d;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
-    return d;
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
 // Philox4x32-10 written with the three-input xor (the same function as philox4x32_10).  In the sweeps only c0

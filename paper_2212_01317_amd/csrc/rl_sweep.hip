@@ -8,17 +8,19 @@
 // unit, and no lane idles on a sample site.
 //
 // A wave owns a band of B = kRlBand columns [x0, x0 + B) and a segment of rows [ys, ye) of one group of 64
-// realizations, and streams the rows downwards with a window of four rows in registers: the angle as loaded and
-// (cos, sin) of each site of columns x0 - 2 .. x0 + B + 1.  Step y updates colour 0 of row y and then colour 1 of
+// realizations, and streams the rows downwards with a window of four rows: (cos, sin) of each site of columns
+// x0 - 2 .. x0 + B + 1 in registers, the angles in LDS.  Step y updates colour 0 of row y and then colour 1 of
 // row y - 1, whose colour-0 neighbours (rows y - 2 .. y) are then current; a colour-0 update writes its cell at
 // once, the colour-1 row is written after the next row has arrived.
-// A row is requested two steps before it is updated, into the slot it then occupies, and its loaded angles are the
-// old angles of its updates, so nothing is read twice.  Colour 0 is also updated one site outside the band
+// A row is requested two steps before it is updated, into the slot it then occupies; at its arrival its loaded angles
+// go to a four-slot ring in LDS, from which its updates read their old angles, so nothing is read twice from memory
+// and the angles do not hold vector registers for four steps.  Colour 0 is also updated one site outside the band
 // (columns x0 - 1, x0 + B) and one row outside the segment (rows ys - 1, ye): these updates use the same
 // counter-based random numbers and the same inputs as in the wave that owns the site, so they are bit-identical to
-// it (and so are the duplicate writes), and the two columns beyond (x0 - 2, x0 + B + 1) are read only.  Sweep k reads `src` and writes `dst`; both hold the sample angles at the sample sites.  The rare exact
-// decision reads the neighbours' angles from memory (colour-1 neighbours from `src`, colour-0 neighbours, already
-// updated, from `dst`).
+// it (and so are the duplicate writes), and the two columns beyond (x0 - 2, x0 + B + 1) are read only.  Sweep k
+// reads `src` and writes `dst`; both hold the sample angles at the sample sites.  The rare exact decision, a function
+// out of line (one copy of its code, which keeps the loop within the instruction cache), reads the neighbours'
+// angles from memory (colour-1 neighbours from `src`, colour-0 neighbours, already updated, from `dst`).
 //
 // The update, the decision (FP32 filter, exact FP64 test inside its error band), the random numbers and the
 // fixed-point energy of each colour-1 site are those of the fused sweep, so the chains, the energy series and the
@@ -40,62 +42,99 @@ __device__ __forceinline__ int fix24(float x) { return __float2int_rn(x * 167772
 // Philox4x32-10 of the counter (site, sweep, realization, w3) and key (k0, k1) when only the realization differs
 // between lanes.  The realization enters round 0 only through M1 * realization, and the result of round 0's first
 // word depends on nothing else that varies (sweep and key are fixed for a launch), so the lane parts of rounds 0 and
-// 1 are three per-lane constants: lc1 = lo(M1 r), and (lph, lpl) = M0 * (hi(M1 r) ^ sweep ^ k0).  A call then does
-// the site's half of rounds 0 and 1 (scalar, but two xors), and rounds 2..9 with the three-input xor.
+// 1 are three per-lane constants: lo(M1 r), and (hi, lo) of M0 * (hi(M1 r) ^ sweep ^ k0); the round-1 keys are
+// folded into the first two (lc1 = lo(M1 r) ^ k0', lph = hi(...) ^ k1', with k' the keys of round 1).  A call then
+// does the site's half of rounds 0 and 1 on the scalar unit (w3k1 = w3 ^ k1 folds the round-0 key into the counter
+// word), and rounds 2..9 with the three-input xor and the round keys held in vector registers (the same in every
+// lane), so that the rounds need no scalar key arithmetic.
 struct PhiloxLane {
     uint32_t lc1, lph, lpl;
 };
 
-__device__ __forceinline__ PhiloxLane philox_lane(uint32_t real, uint32_t sweep, uint32_t k0)
+__device__ __forceinline__ PhiloxLane philox_lane(uint32_t real, uint32_t sweep, uint32_t k0, uint32_t k1)
 {
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)real;
     const uint32_t n0 = (uint32_t)(p1 >> 32) ^ sweep ^ k0;
     const uint64_t q = (uint64_t)0xD2511F53u * (uint64_t)n0;
-    return PhiloxLane{(uint32_t)p1, (uint32_t)(q >> 32), (uint32_t)q};
+    return PhiloxLane{(uint32_t)p1 ^ (k0 + 0x9E3779B9u), (uint32_t)(q >> 32) ^ (k1 + 0xBB67AE85u), (uint32_t)q};
 }
 
-__device__ __forceinline__ U4 philox_site(uint32_t site, uint32_t w3, const PhiloxLane& L, uint32_t k0, uint32_t k1)
+struct RoundKeys {
+    uint32_t k[16];   // (k0, k1) of rounds 2 .. 9
+};
+
+// The round keys in vector registers: the empty asm makes each key a vector value, so the rounds read it from a
+// register instead of recomputing it on the scalar unit.
+
+__device__ __forceinline__ RoundKeys round_keys(uint32_t k0, uint32_t k1)
 {
-    // keep the key schedule as per-call scalar adds instead of twenty loop-invariant registers
-    asm volatile("" : "+s"(k0), "+s"(k1));
+    RoundKeys r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        r.k[2 * i] = k0 + (uint32_t)(i + 2) * 0x9E3779B9u;
+        r.k[2 * i + 1] = k1 + (uint32_t)(i + 2) * 0xBB67AE85u;
+        asm volatile("" : "+v"(r.k[2 * i]), "+v"(r.k[2 * i + 1]));
+    }
+    return r;
+}
+
+// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96 = 0xF0 ^ 0xCC ^ 0xAA) with the round key k in a vector register
+__device__ __forceinline__ uint32_t xor3v(uint32_t a, uint32_t b, uint32_t k)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
+__device__ __forceinline__ U4 philox_site(uint32_t site, uint32_t w3k1, const PhiloxLane& L, const RoundKeys& RK)
+{
     // round 0, the site's half (wave-uniform)
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)site;
-    const uint32_t n2u = (uint32_t)(p0 >> 32) ^ w3 ^ k1, c3u = (uint32_t)p0;
-    // round 1: M1 * n2u is wave-uniform, M0 * (first word) is the lane constant (lph, lpl)
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
+    const uint32_t n2u = (uint32_t)(p0 >> 32) ^ w3k1, c3u = (uint32_t)p0;
+    // round 1: M1 * n2u is wave-uniform, M0 * (first word) is the lane constant
     const uint64_t q1 = (uint64_t)0xCD9E8D57u * (uint64_t)n2u;
-    uint32_t c0 = ((uint32_t)(q1 >> 32) ^ k0) ^ L.lc1;
+    uint32_t c0 = (uint32_t)(q1 >> 32) ^ L.lc1;
     uint32_t c1 = (uint32_t)q1;
-    uint32_t c2 = (c3u ^ k1) ^ L.lph;
+    uint32_t c2 = c3u ^ L.lph;
     uint32_t c3 = L.lpl;
-    // round 2: c1 is wave-uniform
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-    {
-        const uint64_t a0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t a1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(a1 >> 32) ^ (c1 ^ k0);
-        const uint32_t n2 = xor3((uint32_t)(a0 >> 32), c3, k1);
-        c1 = (uint32_t)a1;
-        c3 = (uint32_t)a0;
-        c0 = n0;
-        c2 = n2;
-    }
 #pragma unroll
-    for (int round = 3; round < 10; ++round) {
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
+    for (int round = 2; round < 10; ++round) {
         const uint64_t a0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t a1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = xor3((uint32_t)(a1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(a0 >> 32), c3, k1);
+        const uint32_t n0 = xor3v((uint32_t)(a1 >> 32), c1, RK.k[2 * (round - 2)]);
+        const uint32_t n2 = xor3v((uint32_t)(a0 >> 32), c3, RK.k[2 * (round - 2) + 1]);
         c1 = (uint32_t)a1;
         c3 = (uint32_t)a0;
         c0 = n0;
         c2 = n2;
     }
     return U4{c0, c1, c2, c3};
+}
+
+// The exact decision of one update, out of line (one copy of its code per kernel): the neighbours' angles from
+// memory at the lane's realization (colour 0: the colour-1 neighbours from src; colour 1: the colour-0 neighbours,
+// written earlier in this launch, from dst through the device-coherent path after all stores have completed), then
+// the FP64 test.  An absent neighbour reads the cell itself (in the grid) and is excluded by `present`.
+__device__ __noinline__ bool exact_site(const char* base, int64_t off, int64_t wrow, int j, int x, int y, int W, int H,
+                                        uint32_t lane4, int col, float tp, float to, float ui, double two_pi_q,
+                                        double J, float T)
+{
+    const bool pu = y > 0, pl = x > 0, pr = x + 1 < W, pd = y + 1 < H;
+    const char* p = base + off + (int64_t)j * 256 + lane4;
+    const int64_t du = pu ? -wrow : 0, dd = pd ? wrow : 0, dl = pl ? -256 : 0, dr = pr ? 256 : 0;
+    float nu, nl, nr, nd;
+    if (col == 0) {
+        nu = *reinterpret_cast<const float*>(p + du);
+        nl = *reinterpret_cast<const float*>(p + dl);
+        nr = *reinterpret_cast<const float*>(p + dr);
+        nd = *reinterpret_cast<const float*>(p + dd);
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        nu = __hip_atomic_load(reinterpret_cast<const float*>(p + du), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nl = __hip_atomic_load(reinterpret_cast<const float*>(p + dl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nr = __hip_atomic_load(reinterpret_cast<const float*>(p + dr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nd = __hip_atomic_load(reinterpret_cast<const float*>(p + dd), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned present = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
+    return exact64(tp, to, nu, nl, nr, nd, present, two_pi_q, J, T, ui * 5.9604644775390625e-8f);
 }
 
 // How a window column finds its temperature column: TM_ALIGNED when the blocks are a multiple of the band wide
@@ -119,19 +158,25 @@ struct RlWave {
     int band, x0, ys, ye, lane;
     uint32_t real;                     // global realization index of this lane
     PhiloxLane pl;                     // the lane's constant parts of the first two Philox rounds
+    RoundKeys rk;                      // the round keys of rounds 2 .. 9
     uint32_t lane4;                    // byte offset of this lane inside a site's 64 realizations
     int64_t offy;                      // byte offset of (row y of the current step, window column 0) in the group
     int64_t wrow;                      // bytes per grid row: W * 256
     // window of (cos, sin), slot = row & 3
     float c[4][kWC], s[4][kWC];
     uint32_t gap[4], smp[4];           // per slot: gap / sample bits of the window columns
-    float ang[4][kWC];                 // per slot: the angles of the row as loaded (requested two steps ahead);
-                                       // they are the old angles of the row's updates
+    float ang[4][kWC];                 // per slot: the angles of the row as loaded (requested two steps ahead),
+                                       // until the row arrives
+    float* sang;                       // LDS [4 slots][kWC][64]: the old angles of the arrived rows, by slot
     uint32_t pgap, psmp;
     uint2 nbits;                       // gap / sample bits of the next row to be requested, loaded one request ahead
     int brow, brem;                    // temperature row of the step's row y, and y - brow tb_h
     const TB* trow0;                   // temperature rows of y and y - 1 (clamped into the grid)
     const TB* trow1;
+    const TB* tA0;                     // TM_TWO: the entries bca and bcb of the rows of y and y - 1
+    const TB* tB0;
+    const TB* tA1;
+    const TB* tB1;
     int bc, bcl, bcr;                  // TM_ALIGNED: temperature columns of the owned columns and of the two ring columns
     int bca, bcb, jsplit;              // TM_TWO: the two temperature columns and the first window column of bcb
     long long e_acc;
@@ -188,15 +233,19 @@ struct RlWave {
 #pragma unroll
             for (int j = 0; j < kWC; ++j) ang[S][j] = ld(src, off, j);
         } else {
+            // a cell outside the grid is not loaded: its slot entry is given no value (it is never read), which
+            // ends the live range of the entry it replaces
 #pragma unroll
             for (int j = 0; j < kWC; ++j)
-                if ((in >> j) & 1u) ang[S][j] = ld(src, off, j);
+                ang[S][j] = ((in >> j) & 1u) ? ld(src, off, j) : __builtin_nondeterministic_value(0.0f);
         }
     }
 
     // Row y enters slot S: (cos, sin) of the requested angles; cells outside the grid get (0, 0).  The (cos, sin)
     // of every window column are computed from whatever the slot holds and then cleared outside the grid, so that
     // the common case writes the slot once.
+    __device__ __forceinline__ float& old_angle(int S, int j) const { return sang[(S * kWC + j) * 64 + lane4 / 4]; }
+
     template <int S>
     __device__ __forceinline__ void arrive()
     {
@@ -207,6 +256,8 @@ struct RlWave {
             const float t = a.q * ang[S][j];
             c[S][j] = cos_rev(t);
             s[S][j] = sin_rev(t);
+            if (j >= 1 && j < kWC - 1) old_angle(S, j) = ang[S][j];
+            ang[S][j] = __builtin_nondeterministic_value(0.0f);
         }
         const uint32_t in = pgap | psmp;
         if (in != kAll) {
@@ -241,16 +292,12 @@ struct RlWave {
         // exact FP64 test iff |r| <= tol.  T > 0: r = ui - w24 (its sign is that of the exact difference, and it is
         // 0 only when ui = w24) within the error band of w24; T = 0: r = dE within delta (dE < 0 and dE <= 0 differ
         // only at dE = 0, which lies inside the band).
-        float r, tol;
-        // T > 0 as a scalar integer test on the bits of T (the table holds T > 0 or +0)
-        if (__float_as_int(T.T) > 0) {
-            const float w24 = exp2_fast(fminf(fmaf(X, T.kappa, 24.0f), 25.0f));
-            r = ui - w24;
-            tol = fmaf(w24, fmaf(fabsf(X), T.kb, T.band), 0.015625f);
-        } else {
-            r = -a.J * X;
-            tol = a.delta_e;
-        }
+        // both forms, then a select on T > 0 (a scalar integer test on the bits of T: the table holds T > 0 or +0;
+        // for T = 0, kappa = 0 and the first form is finite and unused)
+        const float w24 = exp2_fast(fminf(fmaf(X, T.kappa, 24.0f), 25.0f));
+        const bool tpos = __float_as_int(T.T) > 0;
+        const float r = tpos ? ui - w24 : -a.J * X;
+        const float tol = tpos ? fmaf(w24, fmaf(fabsf(X), T.kb, T.band), 0.015625f) : a.delta_e;
         return decide<COL, SO>(r, tol, T, y, off, j, to, tp, ui, cp, sp, Cx, Sy);
         }
     }
@@ -301,6 +348,19 @@ struct RlWave {
     __device__ __forceinline__ bool exact_at(const TB& T, int y, int64_t off, int j, float tp, float to,
                                              float ui) const
     {
+        if constexpr (!DIR) {
+            int xb = x0;
+            asm volatile("" : "+s"(xb));
+            return exact_site(COL == 0 ? src : static_cast<const char*>(dst), off, wrow, j, xb - 2 + j, y, a.W, a.H,
+                              lane4, COL, tp, to, ui, a.two_pi_q, a.Jd, T.T);
+        } else {
+            return exact_dir<COL>(T, y, off, j, tp, to, ui);
+        }
+    }
+    template <int COL>
+    __device__ __forceinline__ bool exact_dir(const TB& T, int y, int64_t off, int j, float tp, float to,
+                                              float ui) const
+    {
         // the band origin through an opaque copy: the per-column offsets below are then computed here, on this
         // rare path, instead of being kept for every window column for the whole launch
         int xb = x0;
@@ -324,18 +384,19 @@ struct RlWave {
         }
         const unsigned pres = (pu ? 1u : 0u) | (pl ? 2u : 0u) | (pr ? 4u : 0u) | (pd ? 8u : 0u);
         const float u = ui * 5.9604644775390625e-8f;
-        if constexpr (DIR) return exact64_directional(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.Tx, T.Ty, u);
-        else return exact64(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.T, u);
+        return exact64_directional(tp, to, nu, nl, nr, nd, pres, a.two_pi_q, a.Jd, T.Tx, T.Ty, u);
     }
 
     // The temperature entry of window column j in the row trow.  The table is read-only for the whole launch and the
     // address is wave-uniform: it is read through the constant address space, which makes it a scalar load.
+    // ROW: 0 for row y (colour 0), 1 for row y - 1 (colour 1), the rows whose TM_TWO entries are tA0/tB0 and tA1/tB1
+    template <int ROW>
     __device__ __forceinline__ TB tband(const TB* trow, int j) const
     {
         using CU = const __attribute__((address_space(4))) uint32_t;
-        const int k = TM == TM_ALIGNED ? (j == 1 ? bcl : (j == kWC - 2 ? bcr : bc))
-                                       : (TM == TM_TWO ? (j < jsplit ? bca : bcb) : bcol(j));
-        const uint64_t ad = (uint64_t)(trow + k);
+        const int k = TM == TM_ALIGNED ? (j == 1 ? bcl : (j == kWC - 2 ? bcr : bc)) : (TM == TM_TWO ? 0 : bcol(j));
+        const TB* e = TM == TM_TWO ? (j < jsplit ? (ROW == 0 ? tA0 : tA1) : (ROW == 0 ? tB0 : tB1)) : trow + k;
+        const uint64_t ad = (uint64_t)e;
         const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ad);
         const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ad >> 32));
         const CU* p = (const CU*)(lo | hi << 32);
@@ -352,7 +413,7 @@ struct RlWave {
     template <int COL, int PAR, int SO, int SU, int SD, int MLO, int MHI, int JLO, int JHI>
     __device__ __forceinline__ int colour(const TB* trow, int y, int64_t off)
     {
-        const uint32_t w3 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COL);
+        const uint32_t w3k1 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)COL) ^ a.key1;
         const uint32_t base = (uint32_t)y * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
         int e = 0;
 #pragma unroll
@@ -363,10 +424,11 @@ struct RlWave {
             const bool g0 = in0 && ((gap[SO] >> k0) & 1u);
             const bool g1 = in1 && ((gap[SO] >> k1) & 1u);
             if (!(g0 || g1)) continue;
-            const TB T0 = tband(trow, k0), T1 = tband(trow, k1);
-            const U4 w = philox_site(base + (uint32_t)m, w3, pl, a.key0, a.key1);
-            if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, ang[SO][k0], w.x, w.y);
-            if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, ang[SO][k1], w.z, w.w);
+            const TB T0 = tband<COL>(trow, k0), T1 = tband<COL>(trow, k1);
+            const float to0 = old_angle(SO, k0), to1 = old_angle(SO, k1);
+            const U4 w = philox_site(base + (uint32_t)m, w3k1, pl, rk);
+            if (g0) e += update<COL, SO, SU, SD>(T0, y, off, k0, to0, w.x, w.y);
+            if (g1) e += update<COL, SO, SU, SD>(T1, y, off, k1, to1, w.z, w.w);
         }
         return e;
     }
@@ -401,6 +463,12 @@ struct RlWave {
             ++brow;
         }
         trow0 = tb + (int64_t)(brow < 0 ? 0 : (brow >= a.nby_t ? a.nby_t - 1 : brow)) * a.nbx_t;
+        if (TM == TM_TWO) {
+            tA1 = tA0;
+            tB1 = tB0;
+            tA0 = trow0 + bca;
+            tB0 = trow0 + bcb;
+        }
         // keeps the per-column choice of TM_TWO from being hoisted out of the row loop as a table of pointers
         if (TM == TM_TWO) asm volatile("" : "+s"(jsplit));
         offy += wrow;
@@ -427,17 +495,22 @@ struct RlWave {
     template <int PAR>
     __device__ __forceinline__ void flush()
     {
-        if (pend_gap == 0u) return;
+        if (pend_gap != 0u) {
 #pragma unroll
-        for (int j = 2 + PAR; j < kWC - 2; j += 2)
-            if ((pend_gap >> j) & 1u) st(pend_off, j, pend[j]);
+            for (int j = 2 + PAR; j < kWC - 2; j += 2)
+                if ((pend_gap >> j) & 1u) st(pend_off, j, pend[j]);
+        }
         pend_gap = 0u;
+        // the pending angles are dead until the next colour-1 row writes them
+#pragma unroll
+        for (int j = 0; j < kWC; ++j) pend[j] = __builtin_nondeterministic_value(0.0f);
     }
 
     __device__ __forceinline__ void run()
     {
         e_acc = 0;
-        pl = philox_lane(real, a.sweep, a.key0);
+        pl = philox_lane(real, a.sweep, a.key0, a.key1);
+        rk = round_keys(a.key0, a.key1);
         if (TM == TM_TWO) {
             bca = bcol(0);
             bcb = bcol(kWC - 1);
@@ -455,6 +528,10 @@ struct RlWave {
         brow = (ys - 2 + a.tb_h) / a.tb_h - 1;
         brem = (ys - 2 + a.tb_h) % a.tb_h;
         trow0 = tb;
+        if (TM == TM_TWO) {
+            tA0 = tb + bca;
+            tB0 = tb + bcb;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -503,8 +580,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
     const int64_t group = (int64_t)(item / ((uint32_t)a.nbands * (uint32_t)a.nseg)) * ((int64_t)a.H * a.W * 256);
     using TB = typename RlWave<kRlBand, TM, ENERGY, DIR>::TB;
     const TB* tb = static_cast<const TB*>(tbv);
+    __shared__ float sang[4 * (kRlBand + 4) * 64];
     RlWave<kRlBand, TM, ENERGY, DIR> w{a, cells, tb, reinterpret_cast<const char*>(src) + group,
                                        reinterpret_cast<char*>(dst) + group};
+    w.sang = sang;
     w.band = (int)(item % (uint32_t)a.nbands);
     const uint32_t rest = item / (uint32_t)a.nbands;
     const int seg = (int)(rest % (uint32_t)a.nseg);
