@@ -457,6 +457,63 @@ size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg,
     return c.used;
 }
 
+// The lane batch: per scene its temperature table, window bits, two lane-layout state buffers and reductions.
+struct BatchLaneWs {
+    mpr::BatchLaneScene* scenes;
+    mpr::BatchRun* runs;
+    int* order;
+    int64_t* prefix;
+    mpr::BatchLaneCtl* ctl;
+    StatsWs st;
+    double* Ts;
+    int* No;
+    float* gmean;
+    std::vector<mpr::TBand*> tp;
+    std::vector<uint2*> cells;
+    std::vector<float*> buf0, buf1;
+    std::vector<long long*> epart;
+    std::vector<double*> e_real, series;
+};
+
+size_t batchl_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg, BatchLaneWs* w)
+{
+    BatchLaneWs x;
+    const int64_t R = cfg->n_real > 0 ? cfg->n_real : 1;
+    x.scenes = c.take<mpr::BatchLaneScene>(n);
+    x.runs = c.take<mpr::BatchRun>(n);
+    x.order = c.take<int>(n);
+    x.prefix = c.take<int64_t>(n + 1);
+    x.ctl = c.take<mpr::BatchLaneCtl>(1);
+    int64_t max_np = 1, max_B = 1;
+    for (int i = 0; i < n; ++i) {
+        mpr::StatsGeom g = mpr::stats_geom(sc[i].H, sc[i].W, sc[i].lb_h, sc[i].lb_w);
+        max_np = std::max<int64_t>(max_np, g.B() * g.nchunk);
+        max_B = std::max<int64_t>(max_B, g.B());
+    }
+    x.st.pS = c.take<double>(max_np);
+    x.st.pTs = c.take<double>(max_np);
+    x.st.pN = c.take<int>(max_np);
+    x.st.pNo = c.take<int>(max_np);
+    x.Ts = c.take<double>(max_B);
+    x.No = c.take<int>(max_B);
+    x.gmean = c.take<float>(1);
+    const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
+    for (int i = 0; i < n; ++i) {
+        const int64_t H = sc[i].H, W = sc[i].W;
+        const mpr::RlGeom g = mpr::rl_geometry_full(H, W, (int)R);
+        x.tp.push_back(c.take<mpr::TBand>(nblocks_of(H, W, sc[i].lb_h, sc[i].lb_w)));
+        x.cells.push_back(c.take<uint2>((H + 4) * (int64_t)g.nbands));
+        x.buf0.push_back(c.take<float>((int64_t)g.Rp * H * W));
+        x.buf1.push_back(c.take<float>((int64_t)g.Rp * H * W));
+        const int64_t np = std::max<int64_t>((int64_t)g.nbands * g.nseg, mpr::energy_full_parts(H, W));
+        x.epart.push_back(c.take<long long>(np * R));
+        x.e_real.push_back(c.take<double>(R));
+        x.series.push_back(sc[i].energy ? sc[i].energy : c.take<double>((cap > 0 ? cap : 0) + 1));
+    }
+    if (w) *w = std::move(x);
+    return c.used;
+}
+
 // private stream used only to capture graphs (graphs are launched on the caller's stream)
 hipStream_t capture_stream()
 {
@@ -1275,11 +1332,217 @@ static mpr_status batched_tiles(const mpr_scene* scenes, int32_t n_scenes, const
     return ok();
 }
 
-// A scene runs on its own (mpr_simulate with its scene_id) when mpr_simulate would take the realization-lane sweep
-// for it; the other scenes form the persistent tile-kernel batch.  Both give the scene's single-scene results.
-static bool batch_scene_on_lanes(const mpr_scene& sc, const mpr_sim_config& c)
+// The batch runs on the realization-lane sweep when the realizations fill a wave's lanes (64 or more; or when the
+// lane sweep is asked for), every side is below 65536 and all scenes find their temperatures the same way (one
+// persistent kernel instance serves them all); otherwise on the persistent tile-kernel batch.  Both give every
+// scene its single-scene results.
+static bool batch_on_lanes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config& c)
 {
-    return use_rl(sc.H, sc.W, &c);
+    if (c.sweep_kernel == MPR_SWEEP_TILES) return false;
+    if (c.sweep_kernel != MPR_SWEEP_LANES && c.n_real < 64) return false;
+    const int tm = mpr::rl_tm(scenes[0].lb_w);
+    for (int i = 0; i < n_scenes; ++i)
+        if (scenes[i].H >= 65536 || scenes[i].W >= 65536 || mpr::rl_tm(scenes[i].lb_w) != tm) return false;
+    return true;
+}
+
+static size_t batched_lanes_ws(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
+{
+    Carve c{nullptr, 0, 0};
+    return batchl_ws(c, scenes, n_scenes, cfg, nullptr);
+}
+
+// All scenes in one persistent lane-sweep launch per sweep (k_batchl_sweep), chunks of sweeps replayed as a graph.
+static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg,
+                                int32_t* sweeps_done_out, int32_t* converged_out, void* workspace, size_t ws_bytes,
+                                void* stream)
+{
+    const mpr_sim_config& c = *cfg;
+    hipStream_t s = S(stream);
+    Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
+    BatchLaneWs w;
+    batchl_ws(cv, scenes, n_scenes, cfg, &w);
+    const int R = c.n_real;
+    const uint32_t key0 = (uint32_t)(c.seed & 0xffffffffu), key1 = (uint32_t)(c.seed >> 32);
+    bool any_energy_out = false;
+    for (int i = 0; i < n_scenes; ++i) any_energy_out |= scenes[i].energy != nullptr;
+    const bool energy = c.stop_mode == MPR_STOP_AUTO || any_energy_out;
+
+    std::vector<mpr::BatchLaneScene> hs(n_scenes);
+    std::vector<int64_t> work(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) {
+        const mpr_scene& sc = scenes[i];
+        mpr::StatsGeom g = mpr::stats_geom(sc.H, sc.W, sc.lb_h, sc.lb_w);
+        if (c.init_mode == MPR_INIT_BLOCK_MEAN) {
+            MPR_HIP(mpr::launch_block_stats(sc.t, sc.mask, g, 2.0 * mpr::kPi * (double)c.q, (double)c.J, w.st.pS,
+                                            w.st.pN, w.st.pTs, w.st.pNo, nullptr, nullptr, w.Ts, w.No, s));
+            MPR_HIP(mpr::launch_global_mean(w.Ts, w.No, g.B(), w.gmean, s));
+        }
+        mpr::InitArgs ia;
+        ia.state = sc.state;
+        ia.state2 = nullptr;
+        ia.t = sc.t;
+        ia.mask = sc.mask;
+        ia.Ts = w.Ts;
+        ia.No = w.No;
+        ia.gmean = w.gmean;
+        ia.H = sc.H;
+        ia.W = sc.W;
+        ia.lb_h = sc.lb_h;
+        ia.lb_w = sc.lb_w;
+        ia.nbx = g.nbx;
+        ia.R = R;
+        ia.real_offset = (uint32_t)c.real_offset;
+        ia.scene = sc.scene_id;
+        ia.key0 = key0;
+        ia.key1 = key1;
+        ia.mode = c.init_mode;
+        MPR_HIP(mpr::launch_init(ia, s));
+        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
+        const int64_t HW = sc.H * sc.W;
+        const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
+        const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
+        if (energy) {
+            const int nfull = mpr::energy_full_parts(sc.H, sc.W);
+            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
+            MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
+        }
+        if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, s));
+        MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], s));
+        MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], s));
+        const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
+        mpr::BatchLaneScene& d = hs[i];
+        mpr::RlArgs& ra = d.a;
+        ra = mpr::RlArgs{};
+        ra.H = (int)sc.H;
+        ra.W = (int)sc.W;
+        ra.R = R;
+        ra.Rp = rg.Rp;
+        ra.Mw = (int)((sc.W + 3) / 4);
+        ra.nbands = rg.nbands;
+        ra.nseg = rg.nseg;
+        ra.seg_rows = rg.seg_rows;
+        ra.n_items = rg.n_items;
+        ra.tb_h = sc.lb_h;
+        ra.tb_w = sc.lb_w;
+        ra.nbx_t = (int)((sc.W + sc.lb_w - 1) / sc.lb_w);
+        ra.nby_t = (int)((sc.H + sc.lb_h - 1) / sc.lb_h);
+        ra.tb_w_inv = sc.lb_w > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)sc.lb_w - 1) / (uint64_t)sc.lb_w) : 0u;
+        ra.sweep = 0u;
+        ra.real_offset = (uint32_t)c.real_offset;
+        ra.scene = sc.scene_id;
+        ra.key0 = key0;
+        ra.key1 = key1;
+        ra.q = c.q;
+        ra.J = c.J;
+        ra.delta_e = mpr::kDeltaE * c.J;
+        ra.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+        ra.Jd = (double)c.J;
+        d.cells = w.cells[i];
+        d.tb = w.tp[i];
+        d.buf[0] = w.buf0[i];
+        d.buf[1] = w.buf1[i];
+        d.acc = sc.acc;
+        d.mask = sc.mask;
+        d.epart = w.epart[i];
+        d.e_real = w.e_real[i];
+        d.series = w.series[i];
+        d.HW = HW;
+        d.work = rg.n_items;
+        d.nparts = rg.nbands * rg.nseg;
+        d.inv_norm = inv_norm;
+        work[i] = rg.n_items;
+    }
+    // largest scenes first
+    std::vector<int> order(n_scenes);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<int64_t> prefix(n_scenes + 1, 0);
+    for (int i = 0; i < n_scenes; ++i) prefix[i + 1] = prefix[i] + work[order[i]];
+    std::vector<mpr::BatchRun> runs(n_scenes, mpr::BatchRun{0, 0, 0, 1});
+    mpr::BatchLaneCtl ctl{};
+    ctl.n_active = n_scenes;
+    MPR_HIP(hipMemcpyAsync(w.scenes, hs.data(), sizeof(mpr::BatchLaneScene) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.runs, runs.data(), sizeof(mpr::BatchRun) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.order, order.data(), sizeof(int) * n_scenes, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.prefix, prefix.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice, s));
+    MPR_HIP(hipMemcpyAsync(w.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s));
+    MPR_HIP(hipStreamSynchronize(s));     // the host arrays above must outlive the copies
+
+    mpr::BatchLaneDev b;
+    b.scenes = w.scenes;
+    b.runs = w.runs;
+    b.order = w.order;
+    b.prefix = w.prefix;
+    b.ctl = w.ctl;
+    b.n = n_scenes;
+    b.tm = mpr::rl_tm(scenes[0].lb_w);
+    b.cfg.R = R;
+    b.cfg.real_offset = (uint32_t)c.real_offset;
+    b.cfg.key0 = key0;
+    b.cfg.key1 = key1;
+    b.cfg.q = c.q;
+    b.cfg.J = c.J;
+    b.cfg.delta_e = mpr::kDeltaE * c.J;
+    b.cfg.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+    b.cfg.Jd = (double)c.J;
+    b.cfg.energy = energy ? 1 : 0;
+    b.cfg.stop_mode = c.stop_mode;
+    b.cfg.n_fit = c.n_fit;
+    b.cfg.n_f = c.n_f;
+    b.cfg.n_max = c.n_max;
+    b.cfg.n_eq = c.n_eq;
+    b.cfg.n_samp = c.n_samp;
+    int acc_blocks = 1;
+    for (int i = 0; i < n_scenes; ++i)
+        acc_blocks = std::max<int>(acc_blocks, (int)std::min<int64_t>((hs[i].HW + 255) / 256, 1024));
+    const int grid = 256 * 4 * mpr::kRlWaves;          // one wave per workgroup, every wave slot of the device
+    const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
+    const int32_t total_max = cap + c.n_samp;
+
+    // the sweep loop: a graph of n_f sweeps replayed until every scene is done
+    const int per_graph = c.stop_mode == MPR_STOP_AUTO ? std::max(1, c.n_f) : 5;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = capture_stream();
+    if (cs) {
+        hipGraph_t graph = nullptr;
+        bool okc = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int i = 0; okc && i < per_graph; ++i) okc = mpr::launch_batchl_step(b, grid, acc_blocks, cs) == hipSuccess;
+        hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (okc && ec == hipSuccess && graph) {
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    int active = n_scenes, done = 0;
+    while (active > 0 && done < total_max + 1) {
+        if (exec) {
+            MPR_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int i = 0; i < per_graph; ++i) MPR_HIP(mpr::launch_batchl_step(b, grid, acc_blocks, s));
+        }
+        done += per_graph;
+        mpr::BatchLaneCtl hc;
+        MPR_HIP(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
+        MPR_HIP(hipStreamSynchronize(s));
+        active = hc.n_active;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (active > 0) return fail(MPR_ERR_HIP, "batched simulation did not finish within %d sweeps", total_max);
+
+    // results: the final lane buffers into the callers' state, k* per scene
+    MPR_HIP(hipMemcpyAsync(runs.data(), w.runs, sizeof(mpr::BatchRun) * n_scenes, hipMemcpyDeviceToHost, s));
+    MPR_HIP(hipStreamSynchronize(s));
+    bool all_converged = true;
+    for (int i = 0; i < n_scenes; ++i) {
+        const int total = runs[i].k_star + c.n_samp;
+        MPR_HIP(mpr::launch_rl_from_lanes(hs[i].buf[total & 1], hs[i].HW, R, scenes[i].state, s));
+        if (sweeps_done_out) sweeps_done_out[i] = runs[i].k_star;
+        if (converged_out) converged_out[i] = runs[i].converged != 0 ? 1 : 0;
+        all_converged &= runs[i].converged != 0;
+    }
+    if (!all_converged) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
+    return ok();
 }
 
 size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg)
@@ -1287,17 +1550,8 @@ size_t mpr_simulate_batched_workspace_bytes(const mpr_scene* scenes, int32_t n_s
     if (!scenes || n_scenes < 1 || !cfg) return 0;
     for (int i = 0; i < n_scenes; ++i)
         if (scenes[i].H < 1 || scenes[i].W < 1 || scenes[i].lb_h < 1 || scenes[i].lb_w < 1) return 0;
-    std::vector<mpr_scene> tiles;
-    size_t lanes = 0;
-    for (int i = 0; i < n_scenes; ++i) {
-        const mpr_scene& sc = scenes[i];
-        if (batch_scene_on_lanes(sc, *cfg))
-            lanes = std::max(lanes, mpr_simulate_workspace_bytes(sc.H, sc.W, sc.lb_h, sc.lb_w, cfg));
-        else
-            tiles.push_back(sc);
-    }
-    const size_t t = tiles.empty() ? 0 : batched_tiles_ws(tiles.data(), (int32_t)tiles.size(), cfg);
-    return std::max(lanes, t);
+    return batch_on_lanes(scenes, n_scenes, *cfg) ? batched_lanes_ws(scenes, n_scenes, cfg)
+                                                  : batched_tiles_ws(scenes, n_scenes, cfg);
 }
 
 mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const mpr_sim_config* cfg, int32_t tile_h,
@@ -1308,40 +1562,12 @@ mpr_status mpr_simulate_batched(const mpr_scene* scenes, int32_t n_scenes, const
     if (st != MPR_OK) return st;
     st = check_ws(workspace, ws_bytes, mpr_simulate_batched_workspace_bytes(scenes, n_scenes, cfg));
     if (st != MPR_OK) return st;
-    std::vector<mpr_scene> tiles;
-    std::vector<int> tile_index;
-    bool warn = false;
-    for (int i = 0; i < n_scenes; ++i) {
-        const mpr_scene& sc = scenes[i];
-        if (!batch_scene_on_lanes(sc, *cfg)) {
-            tiles.push_back(sc);
-            tile_index.push_back(i);
-            continue;
-        }
-        mpr_sim_config ci = *cfg;
-        ci.scene_id = sc.scene_id;
-        int32_t k = 0;
-        st = mpr_simulate(sc.t, sc.mask, sc.H, sc.W, sc.T_blocks, sc.lb_h, sc.lb_w, &ci, sc.state, sc.acc, sc.energy, &k,
-                          workspace, ws_bytes, stream);
-        if (st == MPR_WARN_NOT_CONVERGED) warn = true;
-        else if (st != MPR_OK) return st;
-        if (sweeps_done_out) sweeps_done_out[i] = k;
-        if (converged_out) converged_out[i] = st == MPR_OK ? 1 : 0;
+    if (batch_on_lanes(scenes, n_scenes, *cfg)) {
+        if (tile_h_used_out) *tile_h_used_out = 0;
+        return batched_lanes(scenes, n_scenes, cfg, sweeps_done_out, converged_out, workspace, ws_bytes, stream);
     }
-    if (tile_h_used_out) *tile_h_used_out = 0;
-    if (!tiles.empty()) {
-        std::vector<int32_t> k(tiles.size(), 0), cv(tiles.size(), 1);
-        st = batched_tiles(tiles.data(), (int32_t)tiles.size(), cfg, tile_h, k.data(), cv.data(), tile_h_used_out,
-                           workspace, ws_bytes, stream);
-        if (st == MPR_WARN_NOT_CONVERGED) warn = true;
-        else if (st != MPR_OK) return st;
-        for (size_t j = 0; j < tiles.size(); ++j) {
-            if (sweeps_done_out) sweeps_done_out[tile_index[j]] = k[j];
-            if (converged_out) converged_out[tile_index[j]] = cv[j];
-        }
-    }
-    if (warn) return fail(MPR_WARN_NOT_CONVERGED, "some scenes reached n_max without equilibrium");
-    return ok();
+    return batched_tiles(scenes, n_scenes, cfg, tile_h, sweeps_done_out, converged_out, tile_h_used_out, workspace,
+                         ws_bytes, stream);
 }
 
 // ---- instruction-rate probe ----

@@ -249,4 +249,130 @@ hipError_t launch_batch_step(const BatchDev& b, int variant, int next_variant, i
     return hipGetLastError();
 }
 
+// ---- the batch on the realization-lane sweep ----
+
+__global__ void k_batchl_begin(BatchLaneCtl* ctl)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+        ctl->queue[threadIdx.x] = 0ull;
+        if (threadIdx.x == 0) ctl->k += 1;
+    }
+}
+
+// e_real[r] of every equilibrating scene: one workgroup per (scene, realization), the partials summed as integers
+// (order-free), as in the single-scene reduction.
+__global__ __launch_bounds__(256) void k_batchl_energy_real(const BatchLaneScene* scenes, const BatchRun* runs)
+{
+    __shared__ long long lds[4];
+    const int s = blockIdx.x, r = blockIdx.y;
+    if (runs[s].phase != 0) return;
+    const BatchLaneScene& d = scenes[s];
+    const long long* row = d.epart + (int64_t)r * d.nparts;
+    long long v = 0;
+    for (int p = threadIdx.x; p < d.nparts; p += 256) v += row[p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) d.e_real[r] = ((double)(((lds[0] + lds[1]) + lds[2]) + lds[3]) * kFixUnit) * d.inv_norm;
+}
+
+__global__ __launch_bounds__(256) void k_batchl_energy_mean(const BatchLaneScene* scenes, const BatchRun* runs,
+                                                             const BatchLaneCtl* ctl, int R, int n_scenes)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_scenes || runs[s].phase != 0) return;
+    const BatchLaneScene& d = scenes[s];
+    double sum = 0.0;
+    for (int r = 0; r < R; ++r) sum += d.e_real[r];
+    d.series[ctl->k] = sum / (double)R;
+}
+
+// Sampling scenes: acc += sum over realizations (in order) of the state after this sweep (lane layout).
+__global__ __launch_bounds__(256) void k_batchl_accumulate(const BatchLaneScene* scenes, const BatchRun* runs,
+                                                            const BatchLaneCtl* ctl, int R)
+{
+    const int s = blockIdx.y;
+    const BatchRun run = runs[s];
+    if (run.phase != 1) return;
+    const BatchLaneScene& d = scenes[s];
+    const float* st = d.buf[ctl->k & 1];
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
+        if (d.mask[n]) {
+            if (run.samp == 0) d.acc[n] = 0.0;
+            continue;
+        }
+        double acc = run.samp == 0 ? 0.0 : d.acc[n];
+        for (int r = 0; r < R; ++r) acc += (double)st[((int64_t)(r >> 6) * d.HW + n) * 64 + (r & 63)];
+        d.acc[n] = acc;
+    }
+}
+
+// Phase transitions after sweep k (the test of the single-scene driver), then the work list of the scenes still
+// running (one workgroup).
+__global__ __launch_bounds__(256) void k_batchl_phase(const BatchLaneScene* scenes, BatchRun* runs, const int* order,
+                                                       int64_t* prefix, BatchLaneCtl* ctl, BatchCfg c, int n_scenes)
+{
+    const int k = ctl->k;
+    for (int s = threadIdx.x; s < n_scenes; s += 256) {
+        BatchRun run = runs[s];
+        if (run.phase == 0) {
+            bool stop = false;
+            if (c.stop_mode == 1) {
+                if (k >= c.n_fit + c.n_f && (k - c.n_fit) % c.n_f == 0)
+                    stop = batch_equilibrium(scenes[s].series, k, c.n_fit);
+                if (!stop && k >= c.n_max) {
+                    stop = true;
+                    run.converged = 0;
+                }
+            } else {
+                stop = k >= c.n_eq;
+            }
+            if (stop) {
+                run.phase = c.n_samp > 0 ? 1 : 2;
+                run.k_star = k;
+            }
+        } else if (run.phase == 1) {
+            run.samp += 1;
+            if (run.samp >= c.n_samp) run.phase = 2;
+        }
+        runs[s] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        int active = 0;
+        for (int i = 0; i < n_scenes; ++i) {
+            prefix[i] = acc;
+            const int s = order[i];
+            if (runs[s].phase < 2) {
+                acc += scenes[s].work;
+                ++active;
+            }
+        }
+        prefix[n_scenes] = acc;
+        ctl->n_active = active;
+    }
+}
+
+hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batchl_begin, dim3(1), dim3(64), 0, s, b.ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_batchl_sweep(b, grid, s)) != hipSuccess) return e;
+    if (b.cfg.energy) {
+        hipLaunchKernelGGL(k_batchl_energy_real, dim3(b.n, b.cfg.R), dim3(256), 0, s, b.scenes, b.runs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_batchl_energy_mean, dim3((b.n + 255) / 256), dim3(256), 0, s, b.scenes, b.runs, b.ctl,
+                           b.cfg.R, b.n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_batchl_accumulate, dim3(acc_blocks, b.n), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg.R);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batchl_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.ctl, b.cfg,
+                       b.n);
+    return hipGetLastError();
+}
+
 }  // namespace mpr

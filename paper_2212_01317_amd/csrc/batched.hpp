@@ -57,6 +57,49 @@ struct BatchDev {
     int n;
 };
 
+// ---- the batch on the realization-lane sweep (runs with 64 or more realizations) ----
+// One scene as the lane batch reads it: the arguments of its lane sweep (the sweep index is set per launch), its
+// window bits, temperature table, the two state buffers in the lane layout, and the per-scene reductions.
+struct BatchLaneScene {
+    RlArgs a;
+    const uint2* cells;
+    const TBand* tb;
+    float* buf[2];        // [G][HW][64]: state after an even / odd number of sweeps
+    double* acc;
+    const uint8_t* mask;
+    long long* epart;     // [R][nparts] energy partials (fixed point)
+    double* e_real;       // [R]
+    double* series;       // [cap + 1]
+    int64_t HW;
+    int64_t work;         // work items of one sweep (waves)
+    int nparts;           // nbands * nseg
+    double inv_norm;      // 1 / (J * number of bonds)
+};
+
+// Eight work queues, one per XCD: an XCD takes the items of its eighth of the work list in order, so adjacent
+// bands of a scene run on one XCD (their shared columns come from its L2 cache).
+struct BatchLaneCtl {
+    int k;
+    int n_active;
+    unsigned long long queue[8];
+};
+
+struct BatchLaneDev {
+    BatchLaneScene* scenes;
+    BatchRun* runs;
+    int* order;
+    int64_t* prefix;
+    BatchLaneCtl* ctl;
+    BatchCfg cfg;
+    int n;
+    int tm;               // temperature lookup of every scene's sweep (TM_ALIGNED / TM_TWO / TM_ANY)
+};
+
+// the persistent lane sweep of all running scenes (rl_sweep.hip)
+hipError_t launch_batchl_sweep(const BatchLaneDev& b, int grid, hipStream_t s);
+// one sweep of the lane batch: counter, sweep, energies, accumulation, phases and the next work list
+hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, hipStream_t s);
+
 hipError_t launch_batch_sweep(const BatchDev& b, int variant, int grid, hipStream_t s);
 hipError_t launch_batch_step(const BatchDev& b, int variant, int next_variant, int grid, int acc_blocks,
                              hipStream_t s);

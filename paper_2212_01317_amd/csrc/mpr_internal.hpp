@@ -132,6 +132,12 @@ struct RlGeom {
     int64_t n_items;     // waves per sweep: nbands * nseg * Rp / 64
 };
 RlGeom rl_geometry(int64_t H, int64_t W, int R);
+// the same with full-length row segments (kRlSegRows rows): the geometry of the batched form, whose scenes together
+// fill the device
+RlGeom rl_geometry_full(int64_t H, int64_t W, int R);
+// how the lane sweep finds a column's temperature for temperature blocks tb_w wide: 1 aligned with the bands, 2 at
+// most two temperature columns per window, 0 any (a division per column)
+int rl_tm(int tb_w);
 struct RlArgs {
     int H, W, R, Rp, Mw;
     int nbands, nseg, seg_rows;

@@ -29,6 +29,7 @@
 
 #include <type_traits>
 
+#include "batched.hpp"
 #include "metropolis.hpp"
 #include "mpr_internal.hpp"
 
@@ -212,9 +213,15 @@ struct RlWave {
         return a.tb_w == 1 ? x : (int)__umulhi((uint32_t)x, a.tb_w_inv);
     }
 
+    // (through the constant address space: a scalar load whatever the compiler can prove about aliasing)
     __device__ __forceinline__ uint2 row_bits(int y) const
     {
-        return cells[(int64_t)(y + 2) * a.nbands + band];
+        using CU = const __attribute__((address_space(4))) uint32_t;
+        const uint64_t ad = (uint64_t)(cells + ((int64_t)(y + 2) * a.nbands + band));
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ad);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ad >> 32));
+        const CU* p = (const CU*)(lo | hi << 32);
+        return make_uint2(p[0], p[1]);
     }
 
     // Requests the angles of the cells of row y that lie inside the grid (gap and sample cells alike: both state
@@ -598,6 +605,104 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
     if (ENERGY && w.lane < a.R) epart[(int64_t)w.lane * (a.nbands * a.nseg) + seg * a.nbands + w.band] = w.e_acc;
 }
 
+// The batched form on the lane sweep: one persistent launch per sweep in which every wave takes work items from the
+// queue of its XCD (workgroup g runs on XCD g % 8 and takes the items of the XCD's eighth of the work list, in order,
+// so that adjacent bands of a scene share that XCD's L2) until the queue is empty.  The work list numbers the items
+// (group of realizations, band, segment, as in k_sweep_rl) of the scenes still running, largest scenes first;
+// every scene sweeps with its own arguments (scene id, temperatures, buffers) and the batch's sweep index, so its
+// chains are those of its single-scene run.  The energy partials are written for the scenes that equilibrate.
+// The loop's own state (the XCD's item range, the sweep index) and what the energy store needs after an item (the
+// scene, segment and band) are kept in LDS and read back where needed, so that they hold no scalar registers while
+// the wave sweeps (the sweep itself needs all of them).
+struct BatchLaneLoop {
+    int64_t first, last;
+    int k, sidx, seg, band;
+};
+
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32)) << 32) |
+                     (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x));
+}
+
+template <int TM, bool ENERGY>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kRlWaves))) void k_batchl_sweep(
+    const BatchLaneScene* __restrict__ scenes, const BatchRun* __restrict__ runs, const int* __restrict__ order,
+    const int64_t* __restrict__ prefix, BatchLaneCtl* ctl, int n_scenes)
+{
+    __shared__ float sang[4 * (kRlBand + 4) * 64];
+    __shared__ BatchLaneLoop L;
+    volatile BatchLaneLoop& VL = L;
+    if (threadIdx.x == 0) {
+        const uint32_t xcd = blockIdx.x & 7u;
+        const int64_t N = prefix[n_scenes];
+        VL.first = N * (int64_t)xcd / 8;
+        VL.last = N * (int64_t)(xcd + 1) / 8;
+        VL.k = ctl->k;
+    }
+    __syncthreads();
+    for (;;) {
+        unsigned long long v = 0ull;
+        if (threadIdx.x == 0) v = atomicAdd(&ctl->queue[blockIdx.x & 7u], 1ull);
+        // lane 0's ticket, for the whole wave (a scalar value)
+        const int64_t item = uniform64(VL.first) + (int64_t)uniform64((int64_t)v);
+        if (item >= uniform64(VL.last)) break;
+        int lo = 0, hi = n_scenes;            // largest i with prefix[i] <= item
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (prefix[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int sidx = order[lo];
+        // the scene's descriptor through the constant address space: scalar loads (the kernel's stores cannot reach
+        // it), so its fields are scalar values
+        BatchLaneScene d;
+        {
+            using CU = const __attribute__((address_space(4))) uint32_t;
+            const uint64_t sad = (uint64_t)(scenes + sidx);
+            const CU* p = (const CU*)((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)sad) |
+                                      ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(sad >> 32))
+                                       << 32));
+            uint32_t wds[sizeof(BatchLaneScene) / 4];
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(BatchLaneScene) / 4); ++i) wds[i] = p[i];
+            __builtin_memcpy(&d, wds, sizeof(BatchLaneScene));
+        }
+        RlArgs a = d.a;
+        const int k = __builtin_amdgcn_readfirstlane(VL.k);
+        a.sweep = (uint32_t)k;
+        const uint32_t local = (uint32_t)(item - prefix[lo]);
+        const uint32_t per_group = (uint32_t)a.nbands * (uint32_t)a.nseg;
+        const uint32_t rg = local / per_group, rest = local % per_group;
+        const int64_t group = (int64_t)rg * ((int64_t)a.H * a.W * 256);
+        RlWave<kRlBand, TM, ENERGY, false> w{a, d.cells, d.tb, reinterpret_cast<const char*>(d.buf[(k - 1) & 1]) + group,
+                                             reinterpret_cast<char*>(d.buf[k & 1]) + group};
+        w.sang = sang;
+        w.band = (int)(rest % (uint32_t)a.nbands);
+        const int seg = (int)(rest / (uint32_t)a.nbands);
+        w.lane = (int)(rg * 64 + threadIdx.x);
+        w.lane4 = threadIdx.x * 4u;
+        w.real = a.real_offset + (uint32_t)w.lane;
+        w.x0 = w.band * kRlBand;
+        w.ys = seg * a.seg_rows;
+        w.ye = w.ys + a.seg_rows < a.H ? w.ys + a.seg_rows : a.H;
+        if (ENERGY && threadIdx.x == 0) {
+            VL.sidx = sidx;
+            VL.seg = seg;
+            VL.band = w.band;
+        }
+        w.run();
+        if (ENERGY) {
+            const int s2 = __builtin_amdgcn_readfirstlane(VL.sidx);
+            const BatchLaneScene& d2 = scenes[s2];
+            if (runs[s2].phase == 0 && w.lane < d2.a.R)
+                d2.epart[(int64_t)w.lane * d2.nparts + __builtin_amdgcn_readfirstlane(VL.seg) * d2.a.nbands +
+                         __builtin_amdgcn_readfirstlane(VL.band)] = w.e_acc;
+        }
+        // the LDS ring and the loop state are reused by the next item: one wave's LDS operations complete in order
+    }
+}
+
 // cells[(y + 2) * nbands + band] for y in [-2, H + 2): bit j of .x = (y, x0 - 2 + j) is a gap of the grid, of .y =
 // it is a sample.
 __global__ __launch_bounds__(256) void k_rl_cells(const uint8_t* __restrict__ mask, int H, int W, int nbands,
@@ -701,6 +806,19 @@ RlGeom rl_geometry(int64_t H, int64_t W, int R)
     return g;
 }
 
+RlGeom rl_geometry_full(int64_t H, int64_t W, int R)
+{
+    RlGeom g;
+    g.Rp = (R + 63) / 64 * 64;
+    g.nbands = (int)((W + kRlBand - 1) / kRlBand);
+    g.seg_rows = kRlSegRows;
+    g.nseg = (int)((H + g.seg_rows - 1) / g.seg_rows);
+    g.n_items = (int64_t)g.nbands * g.nseg * (g.Rp / 64);
+    return g;
+}
+
+int rl_tm(int tb_w) { return tb_w % kRlBand == 0 ? TM_ALIGNED : (tb_w >= kRlBand + 3 ? TM_TWO : TM_ANY); }
+
 hipError_t launch_rl_cells(const uint8_t* mask, int64_t H, int64_t W, uint2* cells, hipStream_t s)
 {
     const RlGeom g = rl_geometry(H, W, 64);
@@ -738,7 +856,7 @@ hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb,
                            float* dst, long long* epart, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    const int tm = a.tb_w % kRlBand == 0 ? TM_ALIGNED : (a.tb_w >= kRlBand + 3 ? TM_TWO : TM_ANY);
+    const int tm = rl_tm(a.tb_w);
     const dim3 grid((unsigned)a.n_items);
     const void* t = tbd ? static_cast<const void*>(tbd) : static_cast<const void*>(tb);
 #define MPR_RL_LAUNCH(TMV, EN, DI) \
@@ -758,6 +876,26 @@ hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb,
     }
 #undef MPR_RL_LAUNCH_TM
 #undef MPR_RL_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_batchl_sweep(const BatchLaneDev& b, int grid, hipStream_t s)
+{
+    const bool en = b.cfg.energy != 0;
+#define MPR_BL_LAUNCH(TMV, EN) \
+    hipLaunchKernelGGL((k_batchl_sweep<TMV, EN>), dim3(grid), dim3(64), 0, s, b.scenes, b.runs, b.order, b.prefix, \
+                       b.ctl, b.n)
+    if (b.tm == TM_ALIGNED) {
+        if (en) MPR_BL_LAUNCH(TM_ALIGNED, true);
+        else MPR_BL_LAUNCH(TM_ALIGNED, false);
+    } else if (b.tm == TM_TWO) {
+        if (en) MPR_BL_LAUNCH(TM_TWO, true);
+        else MPR_BL_LAUNCH(TM_TWO, false);
+    } else {
+        if (en) MPR_BL_LAUNCH(TM_ANY, true);
+        else MPR_BL_LAUNCH(TM_ANY, false);
+    }
+#undef MPR_BL_LAUNCH
     return hipGetLastError();
 }
 

@@ -37,6 +37,26 @@ def _scenes(lb=(16, 16)):
     return out
 
 
+@pytest.mark.parametrize("stop_mode", [M.STOP_AUTO, M.STOP_FIXED])
+def test_lane_batch_with_few_realizations_equals_single_scene(stop_mode):
+    """sweep_kernel = LANES sends a batch of 6 realizations (lanes 6 .. 63 idle) to the lane batch: every scene, down to
+    1 x 40 and 5 x 5, equals its single-scene call (which sweeps on the tile kernel)."""
+    scenes = _scenes()
+    cfg = M.SimConfig(n_real=6, init_mode=M.INIT_BLOCK_MEAN, stop_mode=stop_mode, n_eq=13, n_samp=2, n_max=150,
+                      seed=78, sweep_kernel=M.SWEEP_LANES)
+    print(f"[batched] lane batch, 6 realizations, stop_mode {stop_mode}", flush=True)
+    b = M.mpr_simulate_batched(scenes, cfg, want_energy=True)
+    assert b.tile_h == 0
+    for sc, out in zip(scenes, b.outputs):
+        c1 = M.SimConfig(**{**cfg.__dict__, "scene_id": sc["scene_id"], "sweep_kernel": M.SWEEP_AUTO})
+        single = M.mpr_simulate(sc["t"], sc["mask"], sc["T_blocks"], *sc["block"], c1)
+        assert out.sweeps == single.sweeps
+        assert out.converged == single.converged
+        assert np.array_equal(host(out.state), host(single.state))
+        assert np.array_equal(host(out.acc), host(single.acc))
+        assert np.array_equal(host(out.energy), host(single.energy))
+
+
 @pytest.mark.parametrize("stop_mode,tile_h", [(M.STOP_AUTO, 0), (M.STOP_AUTO, 16), (M.STOP_FIXED, 32)])
 def test_batched_equals_single_scene(stop_mode, tile_h):
     scenes = _scenes()
@@ -53,10 +73,10 @@ def test_batched_equals_single_scene(stop_mode, tile_h):
         assert np.array_equal(host(out.energy), host(single.energy))
 
 
-def test_batched_mixed_kernels_equal_single_scene():
-    """With 64 realizations, a scene large enough for the realization-lane sweep runs on its own inside the batched
-    call and the small ones form the persistent tile batch; every scene still equals its single-scene call, and
-    sweep_kernel = TILES (every scene in the tile batch) gives the same results."""
+def test_batched_lane_and_tile_batches_equal_single_scene():
+    """With 64 realizations every scene, large or small, runs in the persistent lane batch (one launch per sweep for
+    all scenes); sweep_kernel = TILES puts every scene in the persistent tile batch; every scene of either equals its
+    single-scene call."""
     shapes = [(1024, 800, 0.6, 11), (70, 130, 0.5, 12), (33, 57, 0.7, 13)]
     scenes = []
     for i, (H, W, p, seed) in enumerate(shapes):
@@ -66,11 +86,11 @@ def test_batched_mixed_kernels_equal_single_scene():
         T = np.random.default_rng(seed).uniform(0.02, 0.5, B).astype(np.float32)
         scenes.append(dict(t=dev(t), mask=dev(sc.mask), T_blocks=dev(T), block=(16, 16), scene_id=2000 + i))
     cfg = M.SimConfig(n_real=64, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_max=200, seed=5)
-    print("[batched] mixed kernels", flush=True)
+    print("[batched] lane batch and tile batch", flush=True)
     b = M.mpr_simulate_batched(scenes, cfg, want_energy=True)
     tiles = M.mpr_simulate_batched(scenes, M.SimConfig(**{**cfg.__dict__, "sweep_kernel": M.SWEEP_TILES}),
                                    want_energy=True)
-    assert b.tile_h in (16, 32) and tiles.tile_h in (16, 32)
+    assert b.tile_h == 0 and tiles.tile_h in (16, 32)
     for sc, out, out_t in zip(scenes, b.outputs, tiles.outputs):
         single = M.mpr_simulate(sc["t"], sc["mask"], sc["T_blocks"], *sc["block"],
                                 M.SimConfig(**{**cfg.__dict__, "scene_id": sc["scene_id"]}))
@@ -97,7 +117,7 @@ def test_batched_matches_oracle(kernel):
     """Every scene of a batched call with the automatic stop against the oracle run of that scene (its own scene_id,
     all 64 realizations): the same stopping sweep (or a marginal slope where they differ), the energy series within
     1e-5 per bond, states equal at >= 99.99 % of (realization, site), the prediction's mean |dphi| <= 1e-3 rad.
-    'auto' sends these small scenes to the persistent batch, 'lanes' to the realization-lane sweep."""
+    Both 'auto' (64 realizations) and 'lanes' run them in the persistent lane batch."""
     lb = (16, 16)
     R = 64
     host_scenes, scenes = [], []

@@ -87,32 +87,33 @@ def test_binding_refuses_cpu_tensors():
         _lib.mpr_map_angles(torch.zeros(4, 4), torch.ones(4, 4, dtype=torch.uint8))
 
 
-def test_batched_workspace_covers_both_kernels():
-    """Host-only size queries: a scene that the realization-lane sweep takes needs exactly its single-scene
-    workspace inside a batch; with sweep_kernel = TILES (or few realizations) the batch needs the persistent tile
-    batch's; a mixed batch needs the larger of the two."""
+def test_batched_workspace_follows_the_batch_kernel():
+    """Host-only size queries: with 64 realizations (or sweep_kernel = LANES) the batch runs on the persistent lane
+    sweep, whose workspace holds two lane-layout state buffers (realizations padded to 64) per scene, added over the
+    scenes; with fewer realizations, sweep_kernel = TILES, or scenes whose temperature blocks the lane sweep looks
+    up in different ways, the batch runs on the persistent tile kernel."""
     L = _lib.lib()
     auto = _lib.SimConfig(n_real=64).to_c()
     tiles = _lib.SimConfig(n_real=64, sweep_kernel=_lib.SWEEP_TILES).to_c()
     few = _lib.SimConfig(n_real=8).to_c()
+    few_tiles = _lib.SimConfig(n_real=8, sweep_kernel=_lib.SWEEP_TILES).to_c()
+    few_lanes = _lib.SimConfig(n_real=8, sweep_kernel=_lib.SWEEP_LANES).to_c()
     big, small = (1024, 800), (70, 130)
 
-    def batch(shapes):
+    def batch(shapes, lb=16):
         arr = (_lib.mpr_scene * len(shapes))()
-        for i, (H, W) in enumerate(shapes):
-            arr[i] = _lib.mpr_scene(H, W, 16, 16, i, None, None, None, None, None, None)
+        for i, sh in enumerate(shapes):
+            H, W = sh[:2]
+            b = sh[2] if len(sh) > 2 else lb
+            arr[i] = _lib.mpr_scene(H, W, b, b, i, None, None, None, None, None, None)
         return arr, len(shapes)
 
-    single_lanes = L.mpr_simulate_workspace_bytes(*big, 16, 16, ctypes.byref(auto))
-    single_tiles = L.mpr_simulate_workspace_bytes(*big, 16, 16, ctypes.byref(tiles))
-    assert single_lanes != single_tiles                      # the lane sweep takes the large scene
-    assert L.mpr_simulate_batched_workspace_bytes(*batch([big]), ctypes.byref(auto)) == single_lanes
-    tile_only = L.mpr_simulate_batched_workspace_bytes(*batch([big]), ctypes.byref(tiles))
-    assert tile_only > 0 and tile_only != single_lanes
-    small_only = L.mpr_simulate_batched_workspace_bytes(*batch([small]), ctypes.byref(auto))
-    assert small_only == L.mpr_simulate_batched_workspace_bytes(*batch([small]), ctypes.byref(tiles))
-    assert (L.mpr_simulate_batched_workspace_bytes(*batch([big, small]), ctypes.byref(auto))
-            == max(single_lanes, small_only))
-    assert (L.mpr_simulate_batched_workspace_bytes(*batch([big, small]), ctypes.byref(few))
-            == L.mpr_simulate_batched_workspace_bytes(*batch([big, small]),
-                                                      ctypes.byref(_lib.SimConfig(n_real=8, sweep_kernel=_lib.SWEEP_TILES).to_c())))
+    ws = lambda shapes, cfg: L.mpr_simulate_batched_workspace_bytes(*batch(shapes), ctypes.byref(cfg))
+    lane_bufs = lambda H, W: 2 * 64 * H * W * 4
+    assert ws([big], auto) >= lane_bufs(*big)
+    assert ws([big, small], auto) >= ws([big], auto) + lane_bufs(*small)
+    assert ws([big], tiles) != ws([big], auto)
+    assert ws([big, small], few) == ws([big, small], few_tiles)
+    assert ws([big, small], few_lanes) >= lane_bufs(*big) + lane_bufs(*small)
+    # 16-wide blocks take two temperature columns per window, 24-wide ones line up with the bands: tile batch
+    assert ws([big, (70, 130, 24)], auto) == ws([big, (70, 130, 24)], tiles)
