@@ -299,6 +299,54 @@ size_t mpr_probe_instruction_rates_workspace_bytes(void);
 mpr_status mpr_probe_instruction_rates(double* cost_out, int32_t n_out, double* add_ns_out, void* workspace,
                                        size_t ws_bytes, void* stream);
 
+/* ---- The 3D lattice (the extension to three dimensions that Sec. 4 names) ----
+ * A D x H x W grid, site n = (z H + y) W + x; the Hamiltonian of Eq. (1) over the six nearest neighbours of the simple
+ * cubic lattice (open boundaries); checkerboard colour (x + y + z) % 2; T-blocks of lb_d x lb_h x lb_w sites (ceil
+ * division, numbered (bz nby + by) nbx + bx).  The random stream of a site is the plane's with the row index z H + y
+ * in place of y.  Sides 1 .. 65535 with (D H) ceil(W / 4) < 2^32 (MPR_ERR_SHAPE otherwise); blocks >= 1 on every side.
+ *
+ * mpr_calibrate_temperature3d: Eq. (2) per 3D block (every site owns the bonds to its +x, +y and +z neighbour; a bond
+ * between two samples counts for the block of its owner), then the energy matching and the median fill of
+ * mpr_calibrate_temperature with a matching curve of the cubic lattice (mpr_reference_curve3d).  t[D*H*W], mask
+ * [D*H*W] (device); curve_T / curve_e[n_curve] (device, double); T_out[B] (device, float); e_blocks_out[B] (double)
+ * and nbonds_out[B] (int32) optional (NULL).  MPR_ERR_NO_SAMPLE_BONDS when no two samples are neighbours.
+ * Synchronises the stream.  Workspace: mpr_calibrate3d_workspace_bytes. */
+size_t mpr_calibrate3d_workspace_bytes(int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w);
+mpr_status mpr_calibrate_temperature3d(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W,
+                                       int32_t lb_d, int32_t lb_h, int32_t lb_w, float q, float J,
+                                       const double* curve_T, const double* curve_e, int32_t n_curve, float* T_out,
+                                       double* e_blocks_out, int32_t* nbonds_out, void* workspace, size_t ws_bytes,
+                                       void* stream);
+
+/* mpr_reference_curve3d: the matching curve of the cubic lattice (the 3D counterpart of mpr_reference_curve): the
+ * equilibrium energy per bond of the unconditional model at J = 1 on a periodic L x L x L lattice (3 L^3 bonds), for
+ * each temperature T_grid[i] (device, float).  Chain i starts from t = 1/2, runs n_therm sweeps (colour 0, then 1),
+ * then averages over n_meas sweeps; the chains use the reference-lattice stream (tag 2, realization i, scene 0) with
+ * the row index z L + y.  e_out[nT] (device, double).  L even, 2 .. 512; nT 1 .. 65535.  Asynchronous.  Workspace:
+ * mpr_reference_curve3d_workspace_bytes (the nT L^3 chain states and the energy partial sums). */
+size_t mpr_reference_curve3d_workspace_bytes(int32_t nT, int32_t L);
+mpr_status mpr_reference_curve3d(float q, const float* T_grid, int32_t nT, int32_t L, int32_t n_therm, int32_t n_meas,
+                                 uint64_t seed, double* e_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* mpr_simulate3d: the conditional simulation of mpr_simulate on the 3D grid, with block temperatures and the single
+ * checkerboard only (cfg->t_mode MPR_T_BLOCK, cfg->order MPR_ORDER_SC, cfg->coupling MPR_COUPLING_ISOTROPIC;
+ * MPR_ERR_INVALID_ARG otherwise).  Start (block mean of the 3D block's samples, the global sample mean for a block
+ * without samples, or a uniform draw, tag 1), the sweeps k = 1, 2, ... (colour 0 then colour 1, a gap site's update
+ * over its in-grid neighbours among the six), the energy per bond e(k) over all (D-1)HW + D(H-1)W + DH(W-1) bonds,
+ * the FIXED and AUTO stopping rules, the n_samp sampling sweeps and the accumulator are those of mpr_simulate.
+ * t[D*H*W], mask[D*H*W], T_blocks[B] (device, float).  Outputs: state[n_real*D*H*W] (device, float; in: ignored,
+ * out: final states), acc_out[D*H*W] (device, double), energy_out[k* + 1] (device, double, optional NULL; size
+ * n_max + 1 for AUTO, n_eq + 1 for FIXED), *sweeps_done_out = k* (host, optional).  The chains run in place in a
+ * realization-lane copy of the state held in the workspace (n_real rounded up to 64, times D H W floats).  FIXED is
+ * asynchronous; AUTO synchronises the stream at every check; MPR_WARN_NOT_CONVERGED when n_max is reached.
+ * Workspace: mpr_simulate3d_workspace_bytes.  Calls with the same arguments give bit-identical results. */
+size_t mpr_simulate3d_workspace_bytes(int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w,
+                                      const mpr_sim_config* cfg);
+mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W, const float* T_blocks,
+                          int32_t lb_d, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, float* state,
+                          double* acc_out, double* energy_out, int32_t* sweeps_done_out, void* workspace,
+                          size_t ws_bytes, void* stream);
+
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* mpr_last_error(void);
 

@@ -14,7 +14,8 @@ from .autograd import MPRFunction
 from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL, MprError, SimConfig, SimOutput, lib,
                    mpr_block_stats, mpr_calibrate_temperature, mpr_calibrate_temperature_noalloc, mpr_calibrate_directional, mpr_map_angles, mpr_predict, mpr_reference_curve,
                    mpr_simulate, mpr_sweep, mpr_validate, mpr_block_energy, mpr_temperature_grad,
-                   mpr_simulate_batched, BatchOutput, mpr_probe_instruction_rates, mpr_sst_temperatures)
+                   mpr_simulate_batched, BatchOutput, mpr_probe_instruction_rates, mpr_sst_temperatures,
+                   mpr_calibrate_temperature3d, mpr_reference_curve3d, mpr_simulate3d)
 
 __all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "COUPLING_ISOTROPIC", "COUPLING_DIRECTIONAL", "MprError", "SimConfig", "SimOutput",
            "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_calibrate_temperature_noalloc",
@@ -22,7 +23,8 @@ __all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK
            "mpr_predict",
            "mpr_reference_curve", "mpr_simulate", "mpr_sweep", "mpr_validate", "default_T_grid", "reference_curve", "predict",
            "Prediction", "CURVE_SPEC", "MPRFunction", "mpr_block_energy", "mpr_temperature_grad",
-           "mpr_simulate_batched", "BatchOutput", "mpr_probe_instruction_rates", "mpr_sst_temperatures"]
+           "mpr_simulate_batched", "BatchOutput", "mpr_probe_instruction_rates", "mpr_sst_temperatures",
+           "mpr_calibrate_temperature3d", "mpr_reference_curve3d", "mpr_simulate3d"]
 
 # The matching curve used by default: 121 temperatures log-spaced over [1e-3, 1e2] (24 per decade), periodic
 # 128 x 128 lattice, 1000 sweeps to equilibrate and 2000 to average, fixed seed.

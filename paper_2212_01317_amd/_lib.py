@@ -131,6 +131,14 @@ _SIGS = {
     "mpr_sst_temperatures_workspace_bytes": ([_i64, _i64], _sz),
     "mpr_sst_temperatures": ([_vp, _i64, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "mpr_probe_instruction_rates": ([_vp, _i32, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_calibrate3d_workspace_bytes": ([_i64, _i64, _i64, _i32, _i32, _i32], _sz),
+    "mpr_calibrate_temperature3d": ([_vp, _vp, _i64, _i64, _i64, _i32, _i32, _i32, _f32, _f32, _vp, _vp, _i32, _vp,
+                                     _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_reference_curve3d_workspace_bytes": ([_i32, _i32], _sz),
+    "mpr_reference_curve3d": ([_f32, _vp, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "mpr_simulate3d_workspace_bytes": ([_i64, _i64, _i64, _i32, _i32, _i32, ctypes.POINTER(mpr_sim_config)], _sz),
+    "mpr_simulate3d": ([_vp, _vp, _i64, _i64, _i64, _vp, _i32, _i32, _i32, ctypes.POINTER(mpr_sim_config), _vp, _vp,
+                        _vp, ctypes.POINTER(_i32), _vp, _sz, _vp], ctypes.c_int),
 }
 
 
@@ -321,6 +329,79 @@ def mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, state=None, want
     k = _i32(0)
     st = _check(lib().mpr_simulate(_p(t), _p(mask), H, W, _p(T_blocks), lb_h, lb_w, ctypes.byref(c), _p(state),
                                    _p(acc), _p(energy), ctypes.byref(k), _p(ws), ws.numel(), _stream()),
+                allow_warn=True)
+    ks = int(k.value)
+    en = energy[: ks + 1] if energy is not None else torch.empty(0, dtype=torch.float64, device=dev)
+    return SimOutput(state=state, acc=acc, energy=en, sweeps=ks, converged=(st == MPR_OK))
+
+
+def _dhw(x):
+    if x.dim() != 3:
+        raise ValueError("expected a [D, H, W] tensor")
+    return int(x.shape[0]), int(x.shape[1]), int(x.shape[2])
+
+
+def _blocks3(D, H, W, lb_d, lb_h, lb_w):
+    return -(-D // lb_d), -(-H // lb_h), -(-W // lb_w)
+
+
+def mpr_reference_curve3d(T_grid: torch.Tensor, L: int = 32, n_therm: int = 500, n_meas: int = 1000, seed: int = 0,
+                          q: float = 0.5):
+    """Matching curve of the cubic lattice: equilibrium energy per bond on a periodic L^3 lattice per temperature."""
+    _dev(T_grid, torch.float32, "T_grid")
+    nT = int(T_grid.numel())
+    e = torch.empty(nT, dtype=torch.float64, device=T_grid.device)
+    ws = _ws(lib().mpr_reference_curve3d_workspace_bytes(nT, L), T_grid.device)
+    _check(lib().mpr_reference_curve3d(q, _p(T_grid), nT, L, n_therm, n_meas, seed, _p(e), _p(ws), ws.numel(),
+                                       _stream()))
+    return e
+
+
+def mpr_calibrate_temperature3d(t, mask, lb_d, lb_h, lb_w, curve_T, curve_e, q=0.5, J=1.0):
+    """Per-3D-block temperatures (T, e_b, n_b), each [nbz, nby, nbx]."""
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(curve_T, torch.float64, "curve_T")
+    _dev(curve_e, torch.float64, "curve_e")
+    D, H, W = _dhw(t)
+    shp = _blocks3(D, H, W, lb_d, lb_h, lb_w)
+    dev = t.device
+    T = torch.empty(shp, dtype=torch.float32, device=dev)
+    eb = torch.empty(shp, dtype=torch.float64, device=dev)
+    nb = torch.empty(shp, dtype=torch.int32, device=dev)
+    ws = _ws(lib().mpr_calibrate3d_workspace_bytes(D, H, W, lb_d, lb_h, lb_w), dev)
+    _check(lib().mpr_calibrate_temperature3d(_p(t), _p(mask), D, H, W, lb_d, lb_h, lb_w, q, J, _p(curve_T),
+                                             _p(curve_e), int(curve_T.numel()), _p(T), _p(eb), _p(nb), _p(ws),
+                                             ws.numel(), _stream()))
+    return T, eb, nb
+
+
+def mpr_simulate3d(t, mask, T_blocks, lb_d, lb_h, lb_w, cfg: SimConfig, state=None, want_energy=True,
+                   workspace: torch.Tensor | None = None) -> SimOutput:
+    """Conditional simulation of a [D, H, W] scene; state [n_real, D, H, W], acc [D, H, W]."""
+    _dev(t, torch.float32, "t")
+    _dev(mask, torch.uint8, "mask")
+    _dev(T_blocks, torch.float32, "T_blocks")
+    D, H, W = _dhw(t)
+    nb = _blocks3(D, H, W, lb_d, lb_h, lb_w)
+    if T_blocks.numel() != nb[0] * nb[1] * nb[2]:
+        raise ValueError(f"T_blocks has {T_blocks.numel()} entries, the grid has {nb[0] * nb[1] * nb[2]} blocks")
+    dev = t.device
+    c = cfg.to_c()
+    if state is None:
+        state = torch.empty((cfg.n_real, D, H, W), dtype=torch.float32, device=dev)
+    else:
+        _dev(state, torch.float32, "state")
+        if tuple(state.shape) != (cfg.n_real, D, H, W):
+            raise ValueError("state must be [n_real, D, H, W]")
+    acc = torch.empty((D, H, W), dtype=torch.float64, device=dev)
+    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    energy = torch.empty(cap, dtype=torch.float64, device=dev) if want_energy else None
+    need = lib().mpr_simulate3d_workspace_bytes(D, H, W, lb_d, lb_h, lb_w, ctypes.byref(c))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    k = _i32(0)
+    st = _check(lib().mpr_simulate3d(_p(t), _p(mask), D, H, W, _p(T_blocks), lb_d, lb_h, lb_w, ctypes.byref(c),
+                                     _p(state), _p(acc), _p(energy), ctypes.byref(k), _p(ws), ws.numel(), _stream()),
                 allow_warn=True)
     ks = int(k.value)
     en = energy[: ks + 1] if energy is not None else torch.empty(0, dtype=torch.float64, device=dev)

@@ -1614,3 +1614,333 @@ mpr_status mpr_sst_temperatures(const float* T_blocks, int64_t H, int64_t W, int
 }
 
 }  // extern "C"
+
+// ---- the 3D lattice (the extension to three dimensions of Sec. 4) ----
+namespace {
+
+mpr_status check_grid3(int64_t D, int64_t H, int64_t W)
+{
+    if (D < 1 || H < 1 || W < 1 || D > 65535 || H > 65535 || W > 65535)
+        return fail(MPR_ERR_SHAPE, "3D grid %lld x %lld x %lld: sides must be in 1 .. 65535", (long long)D, (long long)H,
+                    (long long)W);
+    if ((D * H) * ((W + 3) / 4) >= ((int64_t)1 << 32))
+        return fail(MPR_ERR_SHAPE, "3D grid too large for the 32-bit random-stream counter");
+    return MPR_OK;
+}
+
+mpr_status check_blocks3(int32_t lb_d, int32_t lb_h, int32_t lb_w)
+{
+    if (lb_d < 1 || lb_h < 1 || lb_w < 1) return fail(MPR_ERR_SHAPE, "3D blocks: every side must be >= 1");
+    return MPR_OK;
+}
+
+struct Cal3Ws {
+    double *S, *Ts;
+    int *N, *No;
+    unsigned* n_have;
+};
+size_t cal3_ws(Carve& c, int64_t B, Cal3Ws* w)
+{
+    Cal3Ws x;
+    x.S = c.take<double>(B);
+    x.Ts = c.take<double>(B);
+    x.N = c.take<int>(B);
+    x.No = c.take<int>(B);
+    x.n_have = c.take<unsigned>(1);
+    if (w) *w = x;
+    return c.used;
+}
+
+struct Sim3Ws {
+    Cal3Ws st;
+    float* gmean;
+    mpr::TBand* tp;
+    uint32_t* cells;
+    float* lanes;        // [G][n][64]
+    long long* epart;    // [R][max(nparts, energy3 parts)]
+    double* e_real;
+    double* series;
+};
+struct Geom3 {
+    int nbands, nzseg, zseg, Rp;
+    int64_t n_all, B;
+    int nparts;
+};
+Geom3 geom3(int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w, int R)
+{
+    Geom3 g;
+    g.nbands = (int)((W + mpr::kB3 - 1) / mpr::kB3);
+    g.zseg = mpr::kZSeg3;
+    g.nzseg = (int)((D + g.zseg - 1) / g.zseg);
+    g.Rp = (R + 63) / 64 * 64;
+    g.n_all = D * H * W;
+    g.B = mpr::lat3_blocks(D, H, W, lb_d, lb_h, lb_w);
+    g.nparts = (int)(H * g.nbands * g.nzseg);
+    return g;
+}
+size_t sim3_ws(Carve& c, int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w,
+               const mpr_sim_config* cfg, Sim3Ws* w)
+{
+    const int R = cfg->n_real > 0 ? cfg->n_real : 1;
+    const Geom3 g = geom3(D, H, W, lb_d, lb_h, lb_w, R);
+    Sim3Ws x;
+    cal3_ws(c, g.B, &x.st);
+    x.gmean = c.take<float>(1);
+    x.tp = c.take<mpr::TBand>(g.B);
+    x.cells = c.take<uint32_t>(D * H * g.nbands);
+    x.lanes = c.take<float>((int64_t)g.Rp * g.n_all);
+    const int64_t np = std::max<int64_t>(g.nparts, mpr::energy3_parts(D, H, W));
+    x.epart = c.take<long long>(np * R);
+    x.e_real = c.take<double>(R);
+    const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
+    x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
+    if (w) *w = x;
+    return c.used;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mpr_calibrate3d_workspace_bytes(int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w)
+{
+    if (D < 1 || H < 1 || W < 1 || lb_d < 1 || lb_h < 1 || lb_w < 1) return 0;
+    Carve c{nullptr, 0, 0};
+    return cal3_ws(c, mpr::lat3_blocks(D, H, W, lb_d, lb_h, lb_w), nullptr);
+}
+
+mpr_status mpr_calibrate_temperature3d(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W,
+                                       int32_t lb_d, int32_t lb_h, int32_t lb_w, float q, float J,
+                                       const double* curve_T, const double* curve_e, int32_t n_curve, float* T_out,
+                                       double* e_blocks_out, int32_t* nbonds_out, void* workspace, size_t ws_bytes,
+                                       void* stream)
+{
+    mpr_status st = check_grid3(D, H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks3(lb_d, lb_h, lb_w)) != MPR_OK) return st;
+    if (!t || !mask || !curve_T || !curve_e || !T_out)
+        return fail(MPR_ERR_INVALID_ARG, "mpr_calibrate_temperature3d: NULL pointer");
+    if (n_curve < 1) return fail(MPR_ERR_INVALID_ARG, "n_curve must be >= 1");
+    if (!(q > 0.0f && q <= 0.5f) || !(J > 0.0f)) return fail(MPR_ERR_INVALID_ARG, "need 0 < q <= 1/2 and J > 0");
+    st = check_ws(workspace, ws_bytes, mpr_calibrate3d_workspace_bytes(D, H, W, lb_d, lb_h, lb_w));
+    if (st != MPR_OK) return st;
+    const int64_t B = mpr::lat3_blocks(D, H, W, lb_d, lb_h, lb_w);
+    Carve c{static_cast<char*>(workspace), 0, ws_bytes};
+    Cal3Ws w;
+    cal3_ws(c, B, &w);
+    hipStream_t s = S(stream);
+    MPR_HIP(mpr::launch_block_stats3(t, mask, D, H, W, lb_d, lb_h, lb_w, 2.0 * mpr::kPi * (double)q, (double)J, w.S,
+                                     w.N, w.Ts, w.No, s));
+    MPR_HIP(mpr::launch_calibrate(w.S, w.N, B, (double)J, curve_T, curve_e, n_curve, T_out, e_blocks_out, nbonds_out,
+                                  w.n_have, s));
+    unsigned n_have = 0;
+    MPR_HIP(hipMemcpyAsync(&n_have, w.n_have, sizeof n_have, hipMemcpyDeviceToHost, s));
+    MPR_HIP(hipStreamSynchronize(s));
+    if (n_have == 0)
+        return fail(MPR_ERR_NO_SAMPLE_BONDS, "no pair of neighbouring samples: the temperature cannot be estimated");
+    return ok();
+}
+
+size_t mpr_reference_curve3d_workspace_bytes(int32_t nT, int32_t L)
+{
+    if (nT < 1 || L < 2) return 0;
+    Carve c{nullptr, 0, 0};
+    c.take<float>((int64_t)nT * L * L * L);
+    c.take<double>((int64_t)mpr::ref3_energy_parts(L) * nT);
+    c.take<double>(nT);
+    return c.used;
+}
+
+mpr_status mpr_reference_curve3d(float q, const float* T_grid, int32_t nT, int32_t L, int32_t n_therm, int32_t n_meas,
+                                 uint64_t seed, double* e_out, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!(q > 0.0f && q <= 0.5f)) return fail(MPR_ERR_INVALID_ARG, "need 0 < q <= 1/2");
+    if (nT < 1 || nT > 65535) return fail(MPR_ERR_INVALID_ARG, "nT must be in 1 .. 65535");
+    if (L < 2 || L > 512 || (L & 1)) return fail(MPR_ERR_SHAPE, "L must be even and in 2 .. 512");
+    if (n_therm < 0 || n_meas < 1) return fail(MPR_ERR_INVALID_ARG, "need n_therm >= 0 and n_meas >= 1");
+    if (!T_grid || !e_out) return fail(MPR_ERR_INVALID_ARG, "mpr_reference_curve3d: NULL pointer");
+    mpr_status st = check_ws(workspace, ws_bytes, mpr_reference_curve3d_workspace_bytes(nT, L));
+    if (st != MPR_OK) return st;
+    Carve c{static_cast<char*>(workspace), 0, ws_bytes};
+    float* state = c.take<float>((int64_t)nT * L * L * L);
+    const int nparts = mpr::ref3_energy_parts(L);
+    double* part = c.take<double>((int64_t)nparts * nT);
+    double* esum = c.take<double>(nT);
+    hipStream_t s = S(stream);
+    MPR_HIP(mpr::launch_ref_fill(state, (int64_t)nT * L * L * L, 0.5f, s));
+    const uint32_t key0 = (uint32_t)(seed & 0xffffffffu), key1 = (uint32_t)(seed >> 32);
+    const double two_pi_q = 2.0 * mpr::kPi * (double)q;
+    const double inv_norm = 1.0 / (3.0 * (double)L * (double)L * (double)L);
+    for (int32_t k = 1; k <= n_therm + n_meas; ++k) {
+        for (int colour = 0; colour < 2; ++colour)
+            MPR_HIP(mpr::launch_ref3_half(state, T_grid, nT, L, (uint32_t)k, colour, q, mpr::kDeltaE3, key0, key1,
+                                          two_pi_q, s));
+        if (k > n_therm) {
+            MPR_HIP(mpr::launch_ref3_energy(state, L, nT, q, part, nparts, s));
+            MPR_HIP(mpr::launch_ref_accumulate(part, nparts, nT, inv_norm, esum, k == n_therm + 1 ? 1 : 0, s));
+        }
+    }
+    MPR_HIP(mpr::launch_ref_finish(esum, nT, (double)n_meas, e_out, s));
+    return ok();
+}
+
+size_t mpr_simulate3d_workspace_bytes(int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t lb_h, int32_t lb_w,
+                                      const mpr_sim_config* cfg)
+{
+    if (!cfg || D < 1 || H < 1 || W < 1 || lb_d < 1 || lb_h < 1 || lb_w < 1) return 0;
+    Carve c{nullptr, 0, 0};
+    return sim3_ws(c, D, H, W, lb_d, lb_h, lb_w, cfg, nullptr);
+}
+
+mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_t H, int64_t W, const float* T_blocks,
+                          int32_t lb_d, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg, float* state,
+                          double* acc_out, double* energy_out, int32_t* sweeps_done_out, void* workspace,
+                          size_t ws_bytes, void* stream)
+{
+    mpr_status st = check_grid3(D, H, W);
+    if (st != MPR_OK) return st;
+    if ((st = check_blocks3(lb_d, lb_h, lb_w)) != MPR_OK) return st;
+    if (!cfg) return fail(MPR_ERR_INVALID_ARG, "cfg is NULL");
+    if (!t || !mask || !T_blocks || !state || !acc_out) return fail(MPR_ERR_INVALID_ARG, "mpr_simulate3d: NULL pointer");
+    const mpr_sim_config& c = *cfg;
+    if ((st = check_sim_config(c)) != MPR_OK) return st;
+    if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
+        return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
+    if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)
+        return fail(MPR_ERR_INVALID_ARG, "unknown stop_mode %d", c.stop_mode);
+    if (c.n_samp < 0) return fail(MPR_ERR_INVALID_ARG, "n_samp must be >= 0");
+    if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 0) return fail(MPR_ERR_INVALID_ARG, "n_eq must be >= 0");
+    if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
+        return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
+    if (c.t_mode != MPR_T_BLOCK || c.order != MPR_ORDER_SC || c.coupling != MPR_COUPLING_ISOTROPIC)
+        return fail(MPR_ERR_INVALID_ARG, "the 3D lattice runs block temperatures, the single checkerboard and one "
+                                         "coupling");
+    st = check_ws(workspace, ws_bytes, mpr_simulate3d_workspace_bytes(D, H, W, lb_d, lb_h, lb_w, cfg));
+    if (st != MPR_OK) return st;
+    hipStream_t s = S(stream);
+    Carve cv{static_cast<char*>(workspace), 0, ws_bytes};
+    Sim3Ws w;
+    sim3_ws(cv, D, H, W, lb_d, lb_h, lb_w, cfg, &w);
+    const int R = c.n_real;
+    const Geom3 g = geom3(D, H, W, lb_d, lb_h, lb_w, R);
+    const uint32_t key0 = (uint32_t)(c.seed & 0xffffffffu), key1 = (uint32_t)(c.seed >> 32);
+    const int nbx = (int)((W + lb_w - 1) / lb_w), nby = (int)((H + lb_h - 1) / lb_h);
+
+    if (c.init_mode == MPR_INIT_BLOCK_MEAN) {
+        MPR_HIP(mpr::launch_block_stats3(t, mask, D, H, W, lb_d, lb_h, lb_w, 2.0 * mpr::kPi * (double)c.q, (double)c.J,
+                                         w.st.S, w.st.N, w.st.Ts, w.st.No, s));
+        MPR_HIP(mpr::launch_global_mean(w.st.Ts, w.st.No, g.B, w.gmean, s));
+    }
+    mpr::Init3Args ia;
+    ia.state = state;
+    ia.t = t;
+    ia.mask = mask;
+    ia.Ts = w.st.Ts;
+    ia.No = w.st.No;
+    ia.gmean = w.gmean;
+    ia.D = D;
+    ia.H = H;
+    ia.W = W;
+    ia.lb_d = lb_d;
+    ia.lb_h = lb_h;
+    ia.lb_w = lb_w;
+    ia.nbx = nbx;
+    ia.nby = nby;
+    ia.R = R;
+    ia.real_offset = (uint32_t)c.real_offset;
+    ia.scene = c.scene_id;
+    ia.key0 = key0;
+    ia.key1 = key1;
+    ia.mode = c.init_mode;
+    MPR_HIP(mpr::launch_init3(ia, s));
+    MPR_HIP(mpr::launch_tpairs(T_blocks, g.B, c.J, mpr::kDeltaE3 * c.J, w.tp, s));
+    const int64_t nbonds = (W - 1) * H * D + W * (H - 1) * D + W * H * (D - 1);
+    const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
+    const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
+    if (need_energy) {
+        const int nfull = mpr::energy3_parts(D, H, W);
+        MPR_HIP(mpr::launch_energy3_full(state, D, H, W, R, c.q, w.epart, nfull, s));
+        MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, inv_norm, w.e_real, w.series, s));
+    }
+    MPR_HIP(mpr::launch_cells3(mask, D, H, W, g.nbands, w.cells, s));
+    MPR_HIP(mpr::launch_rl_to_lanes(state, g.n_all, R, w.lanes, nullptr, s));
+
+    mpr::Lat3Args a{};
+    a.D = (int)D;
+    a.H = (int)H;
+    a.W = (int)W;
+    a.R = R;
+    a.Rp = g.Rp;
+    a.Mw = (int)((W + 3) / 4);
+    a.nbands = g.nbands;
+    a.nzseg = g.nzseg;
+    a.zseg = g.zseg;
+    a.lb_d = lb_d;
+    a.lb_h = lb_h;
+    a.lb_w = lb_w;
+    a.nbx = nbx;
+    a.nby = nby;
+    a.lbw_inv = lb_w > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)lb_w - 1) / (uint64_t)lb_w) : 0u;
+    a.real_offset = (uint32_t)c.real_offset;
+    a.scene = c.scene_id;
+    a.key0 = key0;
+    a.key1 = key1;
+    a.q = c.q;
+    a.J = c.J;
+    a.delta_e = mpr::kDeltaE3 * c.J;
+    a.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
+    a.Jd = (double)c.J;
+    // one sweep: colour 0, then colour 1, each as the launches over the even and the odd rows
+    auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
+        a.sweep = k;
+        for (int colour = 0; colour < 2; ++colour) {
+            a.colour = colour;
+            for (int ypar = 0; ypar < 2; ++ypar) {
+                a.ypar = ypar;
+                a.nrows = (int)((H - ypar + 1) / 2);
+                const hipError_t e = mpr::launch_sweep3(a, w.cells, w.tp, w.lanes,
+                                                        energy && colour == 1 ? w.epart : nullptr, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (energy) return mpr::launch_energy_reduce(w.epart, g.nparts, R, inv_norm, w.e_real, w.series + k, s);
+        return hipSuccess;
+    };
+
+    const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
+    int32_t k = 0;
+    bool converged = true;
+    double e0 = 0.0;
+    std::vector<double> window;
+    if (c.stop_mode == MPR_STOP_AUTO) {
+        MPR_HIP(hipMemcpyAsync(&e0, w.series, sizeof(double), hipMemcpyDeviceToHost, s));
+        window.resize((size_t)c.n_fit);
+    }
+    while (k < cap) {
+        ++k;
+        MPR_HIP(sweep((uint32_t)k, need_energy));
+        if (c.stop_mode == MPR_STOP_AUTO) {
+            if (k >= c.n_fit + c.n_f && (k - c.n_fit) % c.n_f == 0) {
+                MPR_HIP(hipMemcpyAsync(window.data(), w.series + (k - c.n_fit + 1), sizeof(double) * c.n_fit,
+                                       hipMemcpyDeviceToHost, s));
+                MPR_HIP(hipStreamSynchronize(s));
+                if (equilibrium_reached(e0, window.data(), c.n_fit)) break;
+            }
+            if (k == c.n_max) converged = false;
+        }
+    }
+    const int32_t k_star = k;
+    if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(acc_out, 0, sizeof(double) * (size_t)g.n_all, s));
+    for (int32_t si = 1; si <= c.n_samp; ++si) {
+        MPR_HIP(sweep((uint32_t)(k_star + si), false));
+        MPR_HIP(mpr::launch_rl_accumulate(w.lanes, mask, g.n_all, R, si == 1 ? 1 : 0, acc_out, s));
+    }
+    MPR_HIP(mpr::launch_rl_from_lanes(w.lanes, g.n_all, R, state, s));
+    if (energy_out && need_energy)
+        MPR_HIP(hipMemcpyAsync(energy_out, w.series, sizeof(double) * (size_t)(k_star + 1), hipMemcpyDeviceToDevice, s));
+    if (sweeps_done_out) *sweeps_done_out = k_star;
+    if (!converged) return fail(MPR_WARN_NOT_CONVERGED, "equilibrium test not met after n_max = %d sweeps", c.n_max);
+    return ok();
+}
+
+}  // extern "C"
