@@ -100,6 +100,8 @@ def _declare(L: ctypes.CDLL) -> None:
     L.orc_ols_slope.restype = _dbl
     L.orc_stop_check.argtypes = [_f64p, _i32, _i32, _i32]
     L.orc_stop_check.restype = ctypes.c_int
+    L.orc_stop_check_chains.argtypes = [_f64p, _i32, _i32, _i32, _i32, _u8p]
+    L.orc_stop_check_chains.restype = ctypes.c_int
     L.orc_simulate.argtypes = [_f32p, _u8p, _i64, _i64, _f32p, _i32, _i32, _flt, _flt, _i32, _i32, _i32, _i32,
                                _i32, _i32, _i32, _i32, _i32, _u64, _u32, _i32, _i32, _i32, _f32p, _f64p, _f64p,
                                ctypes.POINTER(_i32)]
@@ -295,6 +297,14 @@ def stop_check(e, k, n_fit=20, n_f=5) -> bool:
     return bool(lib().orc_stop_check(_c(e, np.float64), k, n_fit, n_f))
 
 
+def stop_check_chains(ser, k, passed, n_fit=20, n_f=5) -> bool:
+    """Per-chain test at sweep k: ser[j, r] is chain r's energy after sweep j (j = 0 .. k); `passed` (uint8 [R])
+    holds the chains that have passed and is updated in place."""
+    ser = _c(ser, np.float64)
+    assert passed.dtype == np.uint8 and passed.flags["C_CONTIGUOUS"] and passed.size == ser.shape[1]
+    return bool(lib().orc_stop_check_chains(ser, ser.shape[1], k, n_fit, n_f, passed))
+
+
 @dataclass
 class SimConfig:
     q: float = 0.5
@@ -302,7 +312,7 @@ class SimConfig:
     n_real: int = 1
     real_offset: int = 0
     init_mode: int = 1          # 0 random start (MPR), 1 block-mean start (SV-MPR)
-    stop_mode: int = 0          # 0 fixed n_eq, 1 automatic equilibrium test
+    stop_mode: int = 0          # 0 fixed n_eq, 1 automatic equilibrium test, 2 the same per chain
     n_eq: int = 50
     n_samp: int = 1
     n_fit: int = 20
@@ -331,7 +341,7 @@ def simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, parallel: bool = Fal
     R = cfg.n_real
     state = np.zeros((R, H, W), np.float32)
     acc = np.zeros((H, W), np.float64)
-    ncap = (cfg.n_max if cfg.stop_mode == 1 else cfg.n_eq) + 1
+    ncap = (cfg.n_max if cfg.stop_mode != 0 else cfg.n_eq) + 1
     en = np.zeros(ncap, np.float64)
     conv = _i32(0)
     k = lib(parallel).orc_simulate(t, mask, H, W, _c(T_blocks, np.float32).ravel(), lb_h, lb_w, cfg.q, cfg.J, R,
@@ -459,7 +469,7 @@ def simulate3(t, mask, T_blocks, lb_d, lb_h, lb_w, cfg: SimConfig, parallel: boo
     R = cfg.n_real
     state = np.zeros((R, D, H, W), np.float32)
     acc = np.zeros((D, H, W), np.float64)
-    ncap = (cfg.n_max if cfg.stop_mode == 1 else cfg.n_eq) + 1
+    ncap = (cfg.n_max if cfg.stop_mode != 0 else cfg.n_eq) + 1
     en = np.zeros(ncap, np.float64)
     conv = _i32(0)
     k = lib(parallel).orc_simulate3(t, mask, D, H, W, _c(T_blocks, np.float32).ravel(), lb_d, lb_h, lb_w, cfg.q,

@@ -543,12 +543,38 @@ int orc_stop_check(const double* e, int32_t k, int32_t n_fit, int32_t n_f)
     return beta * sigma0 <= 0.0;
 }
 
+/* The per-chain variant of the test (a reading of Sec. 3.3 / 3.4: the energy of Fig. 9 is that of one simulation of
+ * the whole grid, averaged over realizations only for the figure).  ser[j * R + r] is chain r's own whole-grid
+ * energy after sweep j (j = 0 .. k).  At a check point every chain that has not yet passed applies the test of
+ * orc_stop_check to its own series, and a chain that passes stays passed (passed[r] = 1: its equilibrium sweep is
+ * that check); the scene stops at the first check where every chain has passed, so its k* is the largest of the
+ * chains' own equilibrium sweeps.  Returns 1 then, 0 otherwise (also when k is not a check point). */
+int orc_stop_check_chains(const double* ser, int32_t R, int32_t k, int32_t n_fit, int32_t n_f, uint8_t* passed)
+{
+    if (k < n_fit + n_f || (k - n_fit) % n_f != 0) return 0;
+    double* y = (double*)malloc(sizeof(double) * (size_t)n_fit);
+    int all = 1;
+    for (int32_t r = 0; r < R; ++r) {
+        if (!passed[r]) {
+            for (int32_t j = 0; j < n_fit; ++j) y[j] = ser[(int64_t)(k - n_fit + 1 + j) * R + r];
+            double beta = orc_ols_slope(y, n_fit);
+            double d = ser[(int64_t)k * R + r] - ser[r];
+            double sigma0 = (d > 0.0) - (d < 0.0);
+            if (beta * sigma0 <= 0.0) passed[r] = 1;
+        }
+        all = all && passed[r];
+    }
+    free(y);
+    return all;
+}
+
 /* ------------------------------------------------------------------------------------------------------------
  * Full conditional simulation of one scene (Sec. 2.1 / 2.2.2 / 3.3 / 3.4), all realizations in lockstep:
  *   1. start: gap sites get the block mean of the observed t (SV-MPR, Sec. 3.3; reading: a block without samples
  *      gets the global observed mean) or a uniform draw from the init stream (MPR, random start);
  *   2. e(0), then sweeps k = 1, 2, ... each followed by the realization-averaged whole-grid energy e(k);
- *      FIXED mode stops after n_eq sweeps, AUTO mode applies orc_stop_check and the cap n_max;
+ *      FIXED mode stops after n_eq sweeps, AUTO mode applies orc_stop_check to e(k) and the cap n_max, the
+ *      per-chain AUTO mode (stop_mode 2) applies orc_stop_check_chains to every realization's own energy series;
  *   3. n_samp further sweeps (continuing the sweep counter), after each of which the gap values of every
  *      realization are added to acc (Sec. 2.1: the prediction is the mean of the conditional distribution).
  * t: mapped angles (observed sites used); state: [R][H][W] out; acc: [H][W] out (only gap sites accumulate);
@@ -557,7 +583,8 @@ int orc_stop_check(const double* e, int32_t k, int32_t n_fit, int32_t n_f)
  * ---------------------------------------------------------------------------------------------------------- */
 int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks,
                      int32_t lb_h, int32_t lb_w, float q, float J, int32_t R, int32_t real_offset,
-                     int32_t init_mode /* 0 random, 1 block mean */, int32_t stop_mode /* 0 fixed, 1 auto */,
+                     int32_t init_mode /* 0 random, 1 block mean */,
+                     int32_t stop_mode /* 0 fixed, 1 auto, 2 auto per chain */,
                      int32_t n_eq, int32_t n_samp, int32_t n_fit, int32_t n_f, int32_t n_max, uint64_t seed,
                      uint32_t scene, int32_t t_per_site /* 0: T_blocks per block, 1: T_blocks[H*W] per site */,
                      int32_t order /* 0: single checkerboard, 1: double checkerboard over the lb_h x lb_w blocks */,
@@ -615,13 +642,18 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
     }
     for (int64_t n = 0; n < HW; ++n) acc[n] = 0.0;
 
-    int32_t k_cap = stop_mode == 1 ? n_max : n_eq;
+    int32_t k_cap = stop_mode != 0 ? n_max : n_eq;
     double* e_r = (double*)malloc(sizeof(double) * (size_t)R);
+    /* per-chain mode: every chain's series, [k][R], and the chains that have passed */
+    double* ser = stop_mode == 2 ? (double*)malloc(sizeof(double) * (size_t)R * (size_t)(k_cap + 1)) : NULL;
+    uint8_t* passed = stop_mode == 2 ? (uint8_t*)calloc((size_t)R, 1) : NULL;
 #pragma omp parallel for schedule(static)
     for (int32_t r = 0; r < R; ++r) e_r[r] = orc_energy(state + (int64_t)r * HW, H, W, q, J);
     double e0 = 0.0;
     for (int32_t r = 0; r < R; ++r) e0 += e_r[r];
     energy[0] = e0 / (double)R;
+    if (ser)
+        for (int32_t r = 0; r < R; ++r) ser[r] = e_r[r];
     int32_t k = 0;
     *converged = 1;
     while (k < k_cap) {
@@ -643,9 +675,14 @@ int32_t orc_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, 
         double ek = 0.0;
         for (int32_t r = 0; r < R; ++r) ek += e_r[r];
         energy[k] = ek / (double)R;
+        if (ser)
+            for (int32_t r = 0; r < R; ++r) ser[(int64_t)k * R + r] = e_r[r];
         if (stop_mode == 1 && orc_stop_check(energy, k, n_fit, n_f)) break;
-        if (stop_mode == 1 && k == n_max) *converged = 0;
+        if (stop_mode == 2 && orc_stop_check_chains(ser, R, k, n_fit, n_f, passed)) break;
+        if (stop_mode != 0 && k == n_max) *converged = 0;
     }
+    free(ser);
+    free(passed);
     int32_t k_star = k;
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
 #pragma omp parallel for schedule(static)
@@ -1066,13 +1103,17 @@ int32_t orc_simulate3(const float* t, const uint8_t* mask, int64_t D, int64_t H,
         }
     }
     for (int64_t n = 0; n < n_all; ++n) acc[n] = 0.0;
-    int32_t k_cap = stop_mode == 1 ? n_max : n_eq;
+    int32_t k_cap = stop_mode != 0 ? n_max : n_eq;
     double* e_r = (double*)malloc(sizeof(double) * (size_t)R);
+    double* ser = stop_mode == 2 ? (double*)malloc(sizeof(double) * (size_t)R * (size_t)(k_cap + 1)) : NULL;
+    uint8_t* passed = stop_mode == 2 ? (uint8_t*)calloc((size_t)R, 1) : NULL;
 #pragma omp parallel for schedule(static)
     for (int32_t r = 0; r < R; ++r) e_r[r] = orc_energy3(state + (int64_t)r * n_all, D, H, W, q, J);
     double e0 = 0.0;
     for (int32_t r = 0; r < R; ++r) e0 += e_r[r];
     energy[0] = e0 / (double)R;
+    if (ser)
+        for (int32_t r = 0; r < R; ++r) ser[r] = e_r[r];
     int32_t k = 0;
     *converged = 1;
     while (k < k_cap) {
@@ -1087,9 +1128,14 @@ int32_t orc_simulate3(const float* t, const uint8_t* mask, int64_t D, int64_t H,
         double ek = 0.0;
         for (int32_t r = 0; r < R; ++r) ek += e_r[r];
         energy[k] = ek / (double)R;
+        if (ser)
+            for (int32_t r = 0; r < R; ++r) ser[(int64_t)k * R + r] = e_r[r];
         if (stop_mode == 1 && orc_stop_check(energy, k, n_fit, n_f)) break;
-        if (stop_mode == 1 && k == n_max) *converged = 0;
+        if (stop_mode == 2 && orc_stop_check_chains(ser, R, k, n_fit, n_f, passed)) break;
+        if (stop_mode != 0 && k == n_max) *converged = 0;
     }
+    free(ser);
+    free(passed);
     int32_t k_star = k;
     for (int32_t s_i = 1; s_i <= n_samp; ++s_i) {
 #pragma omp parallel for schedule(static)

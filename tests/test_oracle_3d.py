@@ -204,3 +204,19 @@ def test_calibration3_recovers_temperature_on_complete_field(orc):
         s = orc.simulate3(np.zeros((D, H, W), np.float32), free, np.array([T0], np.float32), D, H, W, cfg).state[0]
         T, _, _ = orc.calibrate_temperature3(s, np.ones((D, H, W), np.uint8), D, H, W, Tg.astype(np.float64), ce)
         assert abs(T.ravel()[0] / T0 - 1.0) < 0.15
+
+
+def test_simulate3_per_chain_stop_is_the_latest_chain(orc):
+    """The per-chain test on the 3D grid: the scene stops at the latest of the chains' own sweeps (each chain run
+    alone with the plain test), and a chain's state equals that chain run alone for as many sweeps."""
+    t, m = _scene3(6, 7, 8, 0.5, 21)
+    T = np.full((1, 1, 1), 0.1, np.float32)
+    ks = [orc.simulate3(t, m, T, 6, 7, 8, SimConfig(n_real=1, real_offset=r, init_mode=0, stop_mode=1, n_fit=6,
+                                                     n_f=2, n_max=200, n_samp=0, seed=2)).k_star for r in range(4)]
+    both = orc.simulate3(t, m, T, 6, 7, 8, SimConfig(n_real=4, init_mode=0, stop_mode=2, n_fit=6, n_f=2, n_max=200,
+                                                      n_samp=1, seed=2))
+    assert len(set(ks)) > 1 and both.k_star == max(ks)
+    for r in (0, 3):
+        alone = orc.simulate3(t, m, T, 6, 7, 8, SimConfig(n_real=1, real_offset=r, init_mode=0, stop_mode=0,
+                                                           n_eq=both.k_star, n_samp=1, seed=2))
+        assert np.array_equal(alone.state[0], both.state[r])

@@ -453,6 +453,71 @@ def test_stop_rule_sequences(orc):
     assert not orc.stop_check(const, 27)
 
 
+def _first_stop_chains(orc, ser, n_max):
+    passed = np.zeros(ser.shape[1], np.uint8)
+    for k in range(1, n_max + 1):
+        if orc.stop_check_chains(ser[: k + 1], k, passed):
+            return k, passed
+    return n_max, passed
+
+
+def test_stop_rule_per_chain_sequences(orc):
+    """The per-chain test (each chain's own series; a chain that passed stays passed; the scene stops when all
+    have): one chain is the plain test; the scene's sweep is the latest of the chains' own; the latch matters; and
+    chains drifting in opposite directions never stop although their mean is flat from the start."""
+    n_max = 200
+    k = np.arange(n_max + 1)
+    const = np.full(n_max + 1, -0.9)
+    dec = 1.0 - 0.01 * k
+    flat = np.where(k <= 40, 1.0 - 0.01 * k, 0.6)
+    inc = np.minimum(-0.99 + 0.001 * k, -0.95)
+    for seq, want in ((const, 25), (dec, n_max), (flat, 60), (inc, 60)):
+        assert _first_stop_chains(orc, seq[:, None], n_max)[0] == want == _first_stop(orc, seq, n_max)
+    ks, passed = _first_stop_chains(orc, np.stack([const, flat, inc], axis=1), n_max)
+    assert ks == 60 and passed.tolist() == [1, 1, 1]
+    # chain 0 passes at 25 and then drifts away again; with the latch the scene still stops when chain 1 passes
+    late = np.where(k <= 25, -0.9, -0.9 + 0.01 * (k - 25))
+    assert _first_stop(orc, late, n_max) == 25
+    assert _first_stop_chains(orc, np.stack([late, flat], axis=1), n_max)[0] == 60
+    # two chains relaxing in opposite directions forever: the mean is constant (the plain test stops at the first
+    # check), the per-chain test never stops
+    a, b = 1.0 - 0.01 * k, -1.0 + 0.01 * k
+    assert _first_stop(orc, (a + b) / 2, n_max) == 25
+    ks, passed = _first_stop_chains(orc, np.stack([a, b], axis=1), n_max)
+    assert ks == n_max and passed.tolist() == [0, 0]
+    # not a check point: nothing changes
+    p0 = np.zeros(1, np.uint8)
+    assert not orc.stop_check_chains(const[:28, None], 27, p0) and p0[0] == 0
+
+
+def test_simulate_per_chain_stop_is_the_latest_chain(orc):
+    """Chains are independent: run alone (one realization, real_offset r, plain test) chain r stops at its own k_r;
+    run together with the per-chain test the scene stops at max_r k_r, and every chain's final state is that chain
+    run alone for the same number of sweeps."""
+    from oracle import SimConfig
+    sc = __import__("paper_2212_01317_amd.synth", fromlist=["x"]).random_small(24, 20, 0.5, seed=4)
+    t, _ = orc.map_angles(sc.z_obs, sc.mask)
+    T = np.array([0.08], np.float32)
+    R = 5
+    ks = []
+    for r in range(R):
+        one = orc.simulate(t, sc.mask, T, 24, 20, SimConfig(n_real=1, real_offset=r, init_mode=0, stop_mode=1,
+                                                            n_fit=8, n_f=3, n_max=300, n_samp=0, seed=6))
+        ks.append(one.k_star)
+    both = orc.simulate(t, sc.mask, T, 24, 20, SimConfig(n_real=R, init_mode=0, stop_mode=2, n_fit=8, n_f=3,
+                                                         n_max=300, n_samp=2, seed=6))
+    assert len(set(ks)) > 1                       # the chains do differ
+    assert both.k_star == max(ks) and both.converged
+    for r in range(R):
+        alone = orc.simulate(t, sc.mask, T, 24, 20, SimConfig(n_real=1, real_offset=r, init_mode=0, stop_mode=0,
+                                                              n_eq=both.k_star, n_samp=2, seed=6))
+        assert np.array_equal(alone.state[0], both.state[r])
+    # one chain: the per-chain test is the plain test
+    one2 = orc.simulate(t, sc.mask, T, 24, 20, SimConfig(n_real=1, real_offset=2, init_mode=0, stop_mode=2, n_fit=8,
+                                                         n_f=3, n_max=300, n_samp=0, seed=6))
+    assert one2.k_star == ks[2]
+
+
 def test_simulate_auto_mode_stops_at_check_point(orc):
     from oracle import SimConfig
     sc = __import__("paper_2212_01317_amd.synth", fromlist=["x"]).random_small(20, 24, 0.4, seed=1)
