@@ -50,7 +50,7 @@ typedef enum {
 } mpr_status;
 
 enum { MPR_INIT_RANDOM = 0, MPR_INIT_BLOCK_MEAN = 1 };
-enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1 };
+enum { MPR_STOP_FIXED = 0, MPR_STOP_AUTO = 1, MPR_STOP_AUTO_CHAIN = 2 };
 enum { MPR_T_BLOCK = 0, MPR_T_SITE = 1 };
 enum { MPR_ORDER_SC = 0, MPR_ORDER_DC = 1 };
 enum { MPR_SWEEP_AUTO = 0, MPR_SWEEP_TILES = 1, MPR_SWEEP_LANES = 2 };
@@ -63,7 +63,9 @@ typedef struct {
     int32_t n_real;       /* number of realizations R (independent chains), 1 .. 65535 */
     int32_t real_offset;  /* global index of realization 0 (for splitting the realizations over calls) */
     int32_t init_mode;    /* MPR_INIT_BLOCK_MEAN (SV-MPR, Sec. 3.3) or MPR_INIT_RANDOM (MPR) */
-    int32_t stop_mode;    /* MPR_STOP_AUTO (Sec. 3.4 equilibrium test) or MPR_STOP_FIXED (n_eq sweeps) */
+    int32_t stop_mode;    /* MPR_STOP_AUTO (Sec. 3.4 equilibrium test on the realization-averaged energy),
+                             MPR_STOP_AUTO_CHAIN (the same test on every realization's own energy; the scene stops
+                             once every chain has passed once), or MPR_STOP_FIXED (n_eq sweeps) */
     int32_t n_eq;         /* FIXED: number of equilibration sweeps */
     int32_t n_samp;       /* sampling sweeps S after equilibrium, each accumulated into the mean */
     int32_t n_fit;        /* AUTO: memory length of the energy series (paper default 20) */
@@ -181,12 +183,15 @@ mpr_status mpr_calibrate_directional(const float* t, const uint8_t* mask, int64_
  *   realization-averaged whole-grid energy per bond e(k) is recorded (e(0) before the first sweep).
  *   FIXED: k* = n_eq.  AUTO: at k = n_fit + j n_f the ordinary least-squares slope beta of the last n_fit energies
  *   is taken; equilibrium when beta * sign(e(k) - e(0)) <= 0; the cap n_max gives MPR_WARN_NOT_CONVERGED.
+ *   AUTO_CHAIN (a reading of Sec. 3.3 / 3.4 in which the energy series is that of one simulation): the same test on
+ *   each realization's own series e_r(k) at the same check points; a chain that passes stays passed, and k* is the
+ *   first check at which every chain has passed.
  *   Then n_samp sampling sweeps (k* + 1 ...), after each of which every realization's gap angles are added to
  *   acc_out in realization order (FP64; samples' entries are 0).
  * The workspace holds a second state buffer of n_real*H*W floats (the sweep reads one buffer and writes the other).
  * Outputs: state[n_real*H*W] (float; in: ignored, out: final states), acc_out[H*W] (double), energy_out[k* + 1]
  * (double, optional NULL; size n_max + 1 for AUTO, n_eq + 1 for FIXED), *sweeps_done_out = k* (host, optional).
- * FIXED mode is asynchronous; AUTO synchronises the stream at every check.  Workspace:
+ * FIXED mode is asynchronous; AUTO and AUTO_CHAIN synchronise the stream at every check.  Workspace:
  * mpr_simulate_workspace_bytes.  Calls with the same arguments give bit-identical results. */
 size_t mpr_simulate_workspace_bytes(int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const mpr_sim_config* cfg);
 mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t W, const float* T_blocks,

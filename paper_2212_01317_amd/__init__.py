@@ -11,13 +11,13 @@ from dataclasses import dataclass
 import torch
 
 from .autograd import MPRFunction
-from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL, MprError, SimConfig, SimOutput, lib,
+from ._lib import (INIT_BLOCK_MEAN, INIT_RANDOM, STOP_AUTO, STOP_AUTO_CHAIN, STOP_FIXED, T_BLOCK, T_SITE, ORDER_SC, ORDER_DC, SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES, COUPLING_ISOTROPIC, COUPLING_DIRECTIONAL, MprError, SimConfig, SimOutput, lib,
                    mpr_block_stats, mpr_calibrate_temperature, mpr_calibrate_temperature_noalloc, mpr_calibrate_directional, mpr_map_angles, mpr_predict, mpr_reference_curve,
                    mpr_simulate, mpr_sweep, mpr_validate, mpr_block_energy, mpr_temperature_grad,
                    mpr_simulate_batched, BatchOutput, mpr_probe_instruction_rates, mpr_sst_temperatures,
                    mpr_calibrate_temperature3d, mpr_reference_curve3d, mpr_simulate3d)
 
-__all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "COUPLING_ISOTROPIC", "COUPLING_DIRECTIONAL", "MprError", "SimConfig", "SimOutput",
+__all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_AUTO_CHAIN", "STOP_FIXED", "T_BLOCK", "T_SITE", "ORDER_SC", "ORDER_DC", "SWEEP_AUTO", "SWEEP_TILES", "SWEEP_LANES", "COUPLING_ISOTROPIC", "COUPLING_DIRECTIONAL", "MprError", "SimConfig", "SimOutput",
            "lib", "mpr_block_stats", "mpr_calibrate_temperature", "mpr_calibrate_temperature_noalloc",
            "mpr_calibrate_directional", "mpr_map_angles",
            "mpr_predict",

@@ -20,7 +20,7 @@ _STATUS = {0: "MPR_OK", 1: "MPR_ERR_INVALID_ARG", 2: "MPR_ERR_SHAPE", 3: "MPR_ER
            4: "MPR_ERR_NO_SAMPLE_BONDS", 5: "MPR_ERR_NONFINITE_INPUT", 6: "MPR_ERR_WORKSPACE_TOO_SMALL",
            7: "MPR_ERR_HIP", 8: "MPR_WARN_NOT_CONVERGED"}
 INIT_RANDOM, INIT_BLOCK_MEAN = 0, 1
-STOP_FIXED, STOP_AUTO = 0, 1
+STOP_FIXED, STOP_AUTO, STOP_AUTO_CHAIN = 0, 1, 2
 T_BLOCK, T_SITE = 0, 1
 ORDER_SC, ORDER_DC = 0, 1
 SWEEP_AUTO, SWEEP_TILES, SWEEP_LANES = 0, 1, 2
@@ -322,7 +322,7 @@ def mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg: SimConfig, state=None, want
         if tuple(state.shape) != (cfg.n_real, H, W):
             raise ValueError("state must be [n_real, H, W]")
     acc = torch.empty((H, W), dtype=torch.float64, device=dev)
-    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    cap = (cfg.n_max if cfg.stop_mode != STOP_FIXED else cfg.n_eq) + 1
     energy = torch.empty(cap, dtype=torch.float64, device=dev) if want_energy else None
     need = lib().mpr_simulate_workspace_bytes(H, W, lb_h, lb_w, ctypes.byref(c))
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
@@ -395,7 +395,7 @@ def mpr_simulate3d(t, mask, T_blocks, lb_d, lb_h, lb_w, cfg: SimConfig, state=No
         if tuple(state.shape) != (cfg.n_real, D, H, W):
             raise ValueError("state must be [n_real, D, H, W]")
     acc = torch.empty((D, H, W), dtype=torch.float64, device=dev)
-    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    cap = (cfg.n_max if cfg.stop_mode != STOP_FIXED else cfg.n_eq) + 1
     energy = torch.empty(cap, dtype=torch.float64, device=dev) if want_energy else None
     need = lib().mpr_simulate3d_workspace_bytes(D, H, W, lb_d, lb_h, lb_w, ctypes.byref(c))
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
@@ -538,7 +538,7 @@ def mpr_simulate_batched(scenes, cfg: SimConfig, tile_h: int = 0, want_energy: b
     n = len(scenes)
     arr = (mpr_scene * n)()
     outs = []
-    cap = (cfg.n_max if cfg.stop_mode == STOP_AUTO else cfg.n_eq) + 1
+    cap = (cfg.n_max if cfg.stop_mode != STOP_FIXED else cfg.n_eq) + 1
     for i, sc in enumerate(scenes):
         t, mask, T = sc["t"], sc["mask"], sc["T_blocks"]
         _dev(t, torch.float32, "t")

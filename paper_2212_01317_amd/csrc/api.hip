@@ -168,6 +168,8 @@ size_t cal_ws(Carve& c, const mpr::StatsGeom& g, CalWs* w)
 
 int fused_tiles(int64_t H, int64_t W, int R);
 
+bool auto_stop(int32_t stop_mode) { return stop_mode == MPR_STOP_AUTO || stop_mode == MPR_STOP_AUTO_CHAIN; }
+
 struct SimWs {
     StatsWs st;
     double* Ts;
@@ -177,6 +179,7 @@ struct SimWs {
     long long* epart;   // [R][max(ntiles, nfull)]
     double* e_real;     // [R]
     double* series;     // [cap + 1]
+    double* hist;       // per-chain stop: every realization's energy after each sweep, [cap + 1][R]
     float* alt;         // [R][H][W] second state buffer (fused sweep)
     mpr::TBandDir* tpd; // directional coupling: per-block table
     float* rl[2];       // [HW][Rp] state buffers of the realization-lane sweep
@@ -200,8 +203,9 @@ size_t sim_ws(Carve& c, int64_t H, int64_t W, int32_t lb_h, int32_t lb_w, const 
     if (rl && (int64_t)rg.nbands * rg.nseg > np) np = (int64_t)rg.nbands * rg.nseg;
     x.epart = c.take<long long>(np * R);
     x.e_real = c.take<double>(R);
-    const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
+    const int64_t cap = auto_stop(cfg->stop_mode) ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
+    x.hist = cfg->stop_mode == MPR_STOP_AUTO_CHAIN ? c.take<double>(((cap > 0 ? cap : 0) + 1) * R) : nullptr;
     x.alt = rl ? nullptr : c.take<float>(R * H * W);
     x.tpd = cfg->coupling == MPR_COUPLING_DIRECTIONAL ? c.take<mpr::TBandDir>(nblocks_of(H, W, lb_h, lb_w)) : nullptr;
     x.rl[0] = rl ? c.take<float>(H * W * rg.Rp) : nullptr;
@@ -261,6 +265,43 @@ bool equilibrium_reached(double e0, const double* window, int n_fit)
     const double sigma0 = (double)((d > 0.0) - (d < 0.0));
     return beta * sigma0 <= 0.0;
 }
+
+// The per-chain form of the test: every realization applies it to its own energy series, a realization that has
+// passed stays passed, and the scene is in equilibrium once all have passed.  The host keeps e_r(0) and the latch;
+// at a check the last n_fit rows of the [k][R] history come over (hist = the device history).
+struct ChainStop {
+    int R = 0, n_fit = 0;
+    std::vector<double> e0, win, y;
+    std::vector<uint8_t> passed;
+    hipError_t start(const double* hist, int R_, int n_fit_, hipStream_t s)
+    {
+        R = R_;
+        n_fit = n_fit_;
+        e0.resize((size_t)R);
+        win.resize((size_t)R * n_fit);
+        y.resize((size_t)n_fit);
+        passed.assign((size_t)R, 0);
+        return hipMemcpyAsync(e0.data(), hist, sizeof(double) * (size_t)R, hipMemcpyDeviceToHost, s);
+    }
+    // the check at sweep k (synchronises the stream)
+    hipError_t check(const double* hist, int k, hipStream_t s, bool* all)
+    {
+        hipError_t e = hipMemcpyAsync(win.data(), hist + (int64_t)(k - n_fit + 1) * R, sizeof(double) * win.size(),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        bool a = true;
+        for (int r = 0; r < R; ++r) {
+            if (!passed[(size_t)r]) {
+                for (int j = 0; j < n_fit; ++j) y[(size_t)j] = win[(size_t)j * R + r];
+                if (equilibrium_reached(e0[(size_t)r], y.data(), n_fit)) passed[(size_t)r] = 1;
+            }
+            a = a && passed[(size_t)r];
+        }
+        *all = a;
+        return hipSuccess;
+    }
+};
 
 mpr_status check_sim_config(const mpr_sim_config& c)
 {
@@ -814,11 +855,11 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     if ((st = check_sim_config(c)) != MPR_OK) return st;
     if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
         return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
-    if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)
+    if (c.stop_mode != MPR_STOP_FIXED && !auto_stop(c.stop_mode))
         return fail(MPR_ERR_INVALID_ARG, "unknown stop_mode %d", c.stop_mode);
     if (c.n_samp < 0) return fail(MPR_ERR_INVALID_ARG, "n_samp must be >= 0");
     if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 0) return fail(MPR_ERR_INVALID_ARG, "n_eq must be >= 0");
-    if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
+    if (auto_stop(c.stop_mode) && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
     if ((c.sweep_kernel == MPR_SWEEP_LANES || c.coupling == MPR_COUPLING_DIRECTIONAL) && (H >= 65536 || W >= 65536))
         return fail(MPR_ERR_SHAPE, "the realization-lane sweep (and the directional coupling) needs sides below 65536");
@@ -869,7 +910,7 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
         MPR_HIP(mpr::launch_tpairs(T_blocks, t_count(H, W, lb_h, lb_w, cfg), c.J, mpr::kDeltaE * c.J, w.tp, s));
     }
 
-    const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
+    const bool need_energy = auto_stop(c.stop_mode) || energy_out != nullptr;
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
     const int nfull = mpr::energy_full_parts(H, W);
     if (need_energy) {
@@ -953,24 +994,39 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     };
     auto current = [&]() -> float* { return dc ? state : runner.current(); };
 
-    const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
+    const int32_t cap = auto_stop(c.stop_mode) ? c.n_max : c.n_eq;
     int32_t k = 0;
     bool converged = true;
     double e0 = 0.0;
     std::vector<double> window;
+    const bool per_chain = c.stop_mode == MPR_STOP_AUTO_CHAIN;
+    ChainStop chains;
     if (c.stop_mode == MPR_STOP_AUTO) {
         MPR_HIP(hipMemcpyAsync(&e0, w.series, sizeof(double), hipMemcpyDeviceToHost, s));
         window.resize((size_t)c.n_fit);
     }
+    if (per_chain) {
+        MPR_HIP(hipMemcpyAsync(w.hist, w.e_real, sizeof(double) * (size_t)R, hipMemcpyDeviceToDevice, s));
+        MPR_HIP(chains.start(w.hist, R, c.n_fit, s));
+    }
     while (k < cap) {
         ++k;
         MPR_HIP(sweep((uint32_t)k, need_energy));
-        if (c.stop_mode == MPR_STOP_AUTO) {
+        if (per_chain)
+            MPR_HIP(hipMemcpyAsync(w.hist + (int64_t)k * R, w.e_real, sizeof(double) * (size_t)R,
+                                   hipMemcpyDeviceToDevice, s));
+        if (auto_stop(c.stop_mode)) {
             if (k >= c.n_fit + c.n_f && (k - c.n_fit) % c.n_f == 0) {
-                MPR_HIP(hipMemcpyAsync(window.data(), w.series + (k - c.n_fit + 1), sizeof(double) * c.n_fit,
-                                       hipMemcpyDeviceToHost, s));
-                MPR_HIP(hipStreamSynchronize(s));
-                if (equilibrium_reached(e0, window.data(), c.n_fit)) break;
+                bool done = false;
+                if (per_chain) {
+                    MPR_HIP(chains.check(w.hist, k, s, &done));
+                } else {
+                    MPR_HIP(hipMemcpyAsync(window.data(), w.series + (k - c.n_fit + 1), sizeof(double) * c.n_fit,
+                                           hipMemcpyDeviceToHost, s));
+                    MPR_HIP(hipStreamSynchronize(s));
+                    done = equilibrium_reached(e0, window.data(), c.n_fit);
+                }
+                if (done) break;
             }
             if (k == c.n_max) converged = false;
         }
@@ -1083,6 +1139,9 @@ static mpr_status check_batched(const mpr_scene* scenes, int32_t n_scenes, const
         return fail(MPR_ERR_INVALID_ARG, "the batched form runs one temperature per block (isotropic coupling)");
     if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
         return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
+    if (c.stop_mode == MPR_STOP_AUTO_CHAIN)
+        return fail(MPR_ERR_INVALID_ARG, "the batched form runs MPR_STOP_FIXED or MPR_STOP_AUTO (the per-chain test "
+                                         "is available in mpr_simulate and mpr_simulate3d)");
     if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)
         return fail(MPR_ERR_INVALID_ARG, "unknown stop_mode %d", c.stop_mode);
     if (c.n_samp < 0) return fail(MPR_ERR_INVALID_ARG, "n_samp must be >= 0");
@@ -1660,6 +1719,7 @@ struct Sim3Ws {
     long long* epart;    // [R][max(nparts, energy3 parts)]
     double* e_real;
     double* series;
+    double* hist;        // per-chain stop: [cap + 1][R]
 };
 struct Geom3 {
     int nbands, nzseg, zseg, Rp;
@@ -1692,8 +1752,9 @@ size_t sim3_ws(Carve& c, int64_t D, int64_t H, int64_t W, int32_t lb_d, int32_t 
     const int64_t np = std::max<int64_t>(g.nparts, mpr::energy3_parts(D, H, W));
     x.epart = c.take<long long>(np * R);
     x.e_real = c.take<double>(R);
-    const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
+    const int64_t cap = auto_stop(cfg->stop_mode) ? cfg->n_max : cfg->n_eq;
     x.series = c.take<double>((cap > 0 ? cap : 0) + 1);
+    x.hist = cfg->stop_mode == MPR_STOP_AUTO_CHAIN ? c.take<double>(((cap > 0 ? cap : 0) + 1) * R) : nullptr;
     if (w) *w = x;
     return c.used;
 }
@@ -1806,11 +1867,11 @@ mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_
     if ((st = check_sim_config(c)) != MPR_OK) return st;
     if (c.init_mode != MPR_INIT_RANDOM && c.init_mode != MPR_INIT_BLOCK_MEAN)
         return fail(MPR_ERR_INVALID_ARG, "unknown init_mode %d", c.init_mode);
-    if (c.stop_mode != MPR_STOP_FIXED && c.stop_mode != MPR_STOP_AUTO)
+    if (c.stop_mode != MPR_STOP_FIXED && !auto_stop(c.stop_mode))
         return fail(MPR_ERR_INVALID_ARG, "unknown stop_mode %d", c.stop_mode);
     if (c.n_samp < 0) return fail(MPR_ERR_INVALID_ARG, "n_samp must be >= 0");
     if (c.stop_mode == MPR_STOP_FIXED && c.n_eq < 0) return fail(MPR_ERR_INVALID_ARG, "n_eq must be >= 0");
-    if (c.stop_mode == MPR_STOP_AUTO && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
+    if (auto_stop(c.stop_mode) && (c.n_fit < 2 || c.n_f < 1 || c.n_max < 1))
         return fail(MPR_ERR_INVALID_ARG, "AUTO needs n_fit >= 2, n_f >= 1, n_max >= 1");
     if (c.t_mode != MPR_T_BLOCK || c.order != MPR_ORDER_SC || c.coupling != MPR_COUPLING_ISOTROPIC)
         return fail(MPR_ERR_INVALID_ARG, "the 3D lattice runs block temperatures, the single checkerboard and one "
@@ -1856,7 +1917,7 @@ mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_
     MPR_HIP(mpr::launch_tpairs(T_blocks, g.B, c.J, mpr::kDeltaE3 * c.J, w.tp, s));
     const int64_t nbonds = (W - 1) * H * D + W * (H - 1) * D + W * H * (D - 1);
     const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
-    const bool need_energy = c.stop_mode == MPR_STOP_AUTO || energy_out != nullptr;
+    const bool need_energy = auto_stop(c.stop_mode) || energy_out != nullptr;
     if (need_energy) {
         const int nfull = mpr::energy3_parts(D, H, W);
         MPR_HIP(mpr::launch_energy3_full(state, D, H, W, R, c.q, w.epart, nfull, s));
@@ -1907,24 +1968,39 @@ mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_
         return hipSuccess;
     };
 
-    const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
+    const int32_t cap = auto_stop(c.stop_mode) ? c.n_max : c.n_eq;
     int32_t k = 0;
     bool converged = true;
     double e0 = 0.0;
     std::vector<double> window;
+    const bool per_chain = c.stop_mode == MPR_STOP_AUTO_CHAIN;
+    ChainStop chains;
     if (c.stop_mode == MPR_STOP_AUTO) {
         MPR_HIP(hipMemcpyAsync(&e0, w.series, sizeof(double), hipMemcpyDeviceToHost, s));
         window.resize((size_t)c.n_fit);
     }
+    if (per_chain) {
+        MPR_HIP(hipMemcpyAsync(w.hist, w.e_real, sizeof(double) * (size_t)R, hipMemcpyDeviceToDevice, s));
+        MPR_HIP(chains.start(w.hist, R, c.n_fit, s));
+    }
     while (k < cap) {
         ++k;
         MPR_HIP(sweep((uint32_t)k, need_energy));
-        if (c.stop_mode == MPR_STOP_AUTO) {
+        if (per_chain)
+            MPR_HIP(hipMemcpyAsync(w.hist + (int64_t)k * R, w.e_real, sizeof(double) * (size_t)R,
+                                   hipMemcpyDeviceToDevice, s));
+        if (auto_stop(c.stop_mode)) {
             if (k >= c.n_fit + c.n_f && (k - c.n_fit) % c.n_f == 0) {
-                MPR_HIP(hipMemcpyAsync(window.data(), w.series + (k - c.n_fit + 1), sizeof(double) * c.n_fit,
-                                       hipMemcpyDeviceToHost, s));
-                MPR_HIP(hipStreamSynchronize(s));
-                if (equilibrium_reached(e0, window.data(), c.n_fit)) break;
+                bool done = false;
+                if (per_chain) {
+                    MPR_HIP(chains.check(w.hist, k, s, &done));
+                } else {
+                    MPR_HIP(hipMemcpyAsync(window.data(), w.series + (k - c.n_fit + 1), sizeof(double) * c.n_fit,
+                                           hipMemcpyDeviceToHost, s));
+                    MPR_HIP(hipStreamSynchronize(s));
+                    done = equilibrium_reached(e0, window.data(), c.n_fit);
+                }
+                if (done) break;
             }
             if (k == c.n_max) converged = false;
         }

@@ -27,7 +27,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import INIT_BLOCK_MEAN, INIT_RANDOM, ORDER_DC, mpr_validate, predict, reference_curve
+from . import INIT_BLOCK_MEAN, INIT_RANDOM, ORDER_DC, STOP_AUTO, STOP_AUTO_CHAIN, mpr_validate, predict, reference_curve
 from . import synth
 
 METHODS = ("MPR", "BST", "SST")
@@ -43,6 +43,7 @@ class Setting:
     n_s: int = 5                # SST smoothing passes (the paper's tables use 5)
     n_max: int = 1000
     seed: int = 0
+    stop_mode: int = STOP_AUTO  # STOP_AUTO: the test on the realization-averaged energy; STOP_AUTO_CHAIN: per chain
 
 
 def masks_for(H: int, W: int, p: float, M: int, seed: int):
@@ -56,7 +57,8 @@ def masks_for(H: int, W: int, p: float, M: int, seed: int):
 
 def predict_method(method: str, z: torch.Tensor, mask: torch.Tensor, s: Setting, curve, scene_id: int):
     H, W = int(z.shape[0]), int(z.shape[1])
-    common = dict(n_real=s.n_real, n_samp=s.n_samp, n_max=s.n_max, seed=s.seed, scene_id=scene_id, curve=curve)
+    common = dict(n_real=s.n_real, n_samp=s.n_samp, n_max=s.n_max, seed=s.seed, scene_id=scene_id, curve=curve,
+                  stop_mode=s.stop_mode)
     if method == "MPR":
         return predict(z, mask, block=(H, W), init_mode=INIT_RANDOM, **common)
     if method == "BST":
@@ -85,8 +87,8 @@ def variants(methods, s0: Setting, blocks, ns):
 
 def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda",
         blocks=None, ns=None):
-    """Rows {p, method, block, n_s, MAAE, MRASE, t_ms, sweeps} for every p and variant; the same masks for every
-    variant."""
+    """Rows {p, method, block, n_s, MAAE, MRASE, t_ms, sweeps, k_star} for every p and variant (sweeps: mean of
+    k* + n_samp; k_star: mean k*); the same masks for every variant."""
     s0 = setting or Setting()
     blocks = list(blocks) if blocks else [s0.block]
     ns = list(ns) if ns else [s0.n_s]
@@ -98,7 +100,7 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
     for p in ps:
         masks = masks_for(H, W, float(p), M, s0.seed)
         for method, s in variants(methods, s0, blocks, ns):
-            aae, rase, times, sweeps = [], [], [], []
+            aae, rase, times, sweeps, kst = [], [], [], [], []
             for m, mk in enumerate(masks):
                 mask = torch.from_numpy(mk).to(dev)
                 ev = (1 - mask).contiguous()
@@ -112,9 +114,12 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
                 aae.append(float(e[0]))
                 rase.append(float(e[1]))
                 sweeps.append(pr.sim.sweeps + s.n_samp)
+                kst.append(pr.sim.sweeps)
             rows.append(dict(p=float(p), method=method, block=None if method == "MPR" else s.block,
                              n_s=s.n_s if method == "SST" else None, MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
-                             t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)), M=M, L=[H, W]))
+                             t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)),
+                             k_star=float(np.mean(kst)), stop="chain" if s.stop_mode == STOP_AUTO_CHAIN else "mean",
+                             n_real=s.n_real, M=M, L=[H, W]))
     return rows
 
 
@@ -130,6 +135,8 @@ def main():
     ap.add_argument("--field", choices=("skewed", "ns", "aniso"), default="skewed")
     ap.add_argument("--field-seed", type=int, default=synth.seed_for(6, synth.ROLE_FIELD))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--stop", choices=("mean", "chain"), default="mean",
+                    help="equilibrium test on the realization-averaged energy (mean) or on every chain's own (chain)")
     a = ap.parse_args()
     if a.field == "skewed":
         field = synth.skewed_field(a.L, a.field_seed)
@@ -138,7 +145,8 @@ def main():
     else:
         field = synth.ns_field(a.L, a.L, 4, (2.0, 32.0), np.random.default_rng(a.field_seed)).astype(np.float32)
     rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
-               Setting(n_real=a.n_real, seed=a.seed), blocks=[int(b) for b in a.blocks.split(",")],
+               Setting(n_real=a.n_real, seed=a.seed,
+                       stop_mode=STOP_AUTO_CHAIN if a.stop == "chain" else STOP_AUTO), blocks=[int(b) for b in a.blocks.split(",")],
                ns=[int(n) for n in a.ns.split(",")])
     for r in rows:
         print(json.dumps(r), flush=True)
