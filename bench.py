@@ -66,7 +66,7 @@ HBM_PEAK_GBS = 8000.0
 # The simulation sweeps with the realization-lane kernel when R >= 64 (one realization per lane), else with the
 # fused tile kernel; the sources each kernel is built from, for matching a committed counter summary.
 SWEEP_SOURCES = {
-    "k_sweep_rl": ("rl_sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp"),
+    "k_sweep_rl": ("rl_sweep.hip", "batched.hpp", "metropolis.hpp", "philox.hpp", "philox_lane.hpp", "mpr_internal.hpp"),
     "k_sweep_fused": ("sweep_body.hpp", "sweep.hip", "metropolis.hpp", "philox.hpp", "mpr_internal.hpp"),
 }
 
@@ -338,6 +338,8 @@ def main():
         out["directional"] = bench_directional(sc, cT, ce, dev, state, R, lb, cfg, n_gap, errs)
         del state
         torch.cuda.empty_cache()
+        out["lattice3d"] = bench_lattice3d(dev, R, head["roofline"]["launch_ms"], L * L)
+        torch.cuda.empty_cache()
         out["batched"] = bench_batched(extras_inputs[0], cT, ce, dev)
         torch.cuda.empty_cache()
         out["gradient"] = bench_gradient(extras_inputs[1], cT, ce, dev)
@@ -425,6 +427,55 @@ def bench_sst(sc, cT, ce, dev, state, R, lb, cfg, n_gap, bst_errs):
     return {"workload": "headline input, SST with r_s = 1, n_s = 5 (one temperature per site), AUTO, 1 sampling sweep",
             "seconds_per_step": el, "sweeps": sim.sweeps + c_sst.n_samp, "updates_per_s": upd / el,
             "aae": float(e[0]), "rase": float(e[1]), "bst_aae": float(bst_errs[0]), "bst_rase": float(bst_errs[1])}
+
+
+def bench_lattice3d(dev, R, plane_sweep_ms, plane_sites):
+    """The 3D lattice (the extension to three dimensions of Sec. 4) at the plane's site count: 256^3 GRF stand-in,
+    60 % of the sites removed uniformly, 32^3 temperature blocks calibrated on a matching curve of the cubic
+    lattice, R realizations.  Time of one sweep with its energy (as under the automatic stop), by HIP events around
+    two fixed-length simulations of the same start, against the plane's sweep at the same site count."""
+    import numpy as np
+    import torch
+
+    import paper_2212_01317_amd as mpr
+    from paper_2212_01317_amd import synth
+    L, lb = 256, (32, 32, 32)
+    t0 = time.time()
+    f, m = synth.config3d(L, 0.6)
+    log(f"[bench] 3D workload generated in {time.time() - t0:.1f}s")
+    z = torch.from_numpy(f * m).to(dev)
+    mask = torch.from_numpy(m).to(dev)
+    t2, _ = mpr.mpr_map_angles(z.view(L * L, L), mask.view(L * L, L))
+    t = t2.view(L, L, L)
+    cT = torch.from_numpy(np.geomspace(1e-3, 1e2, 41).astype(np.float32)).to(dev)
+    ce = mpr.mpr_reference_curve3d(cT, L=32, n_therm=300, n_meas=300, seed=1)
+    T, _, _ = mpr.mpr_calibrate_temperature3d(t, mask, *lb, cT.double(), ce)
+    n_gap = int((m == 0).sum())
+    state = torch.empty((R, L, L, L), dtype=torch.float32, device=dev)
+
+    def timed(n):
+        c = mpr.SimConfig(n_real=R, init_mode=mpr.INIT_BLOCK_MEAN, stop_mode=mpr.STOP_FIXED, n_eq=n, n_samp=0,
+                          seed=synth.seed_for(7, synth.ROLE_PHILOX))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mpr.mpr_simulate3d(t, mask, T, *lb, c, state=state, want_energy=True)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    timed(2)
+    ns = 10
+    t_sweep = (timed(2 + ns) - timed(2)) / ns
+    del state
+    torch.cuda.empty_cache()
+    log(f"[bench] 3D: {L}^3 R={R}: sweep {t_sweep * 1e3:.3f} ms -> {R * n_gap / t_sweep:.3e} upd/s, "
+        f"{t_sweep * 1e3 / plane_sweep_ms:.2f}x the plane's sweep at {plane_sites} sites")
+    return {"workload": f"{L}^3 GRF (xi=8), p=0.6 uniform gaps, {lb[0]}^3 T-blocks, {R} realizations, six neighbours",
+            "sites": L ** 3, "gap_sites": n_gap, "sweep_ms": t_sweep * 1e3, "updates_per_s": R * n_gap / t_sweep,
+            "plane_sweep_ms_same_sites": plane_sweep_ms, "plane_sites": plane_sites,
+            "time_ratio_vs_plane": t_sweep * 1e3 / plane_sweep_ms,
+            "mean_T": float(T.double().mean())}
 
 
 def bench_batched(scenes, cT, ce, dev):

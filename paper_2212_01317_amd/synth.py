@@ -251,6 +251,26 @@ def skewed_field(L: int, seed: int, sigma: float = 0.79) -> np.ndarray:
     return np.exp(sigma * g).astype(np.float32)
 
 
+def grf3(D: int, H: int, W: int, xi: float, rng: np.random.Generator) -> np.ndarray:
+    """Standardised stationary GRF with covariance exp(-r/xi) on a periodic D x H x W grid (circulant, negative
+    eigenvalues clipped): the stand-in field of the 3D lattice."""
+    ds = [np.minimum(np.arange(M), M - np.arange(M)).astype(np.float64) for M in (D, H, W)]
+    r = np.sqrt(ds[0][:, None, None] ** 2 + ds[1][None, :, None] ** 2 + ds[2][None, None, :] ** 2)
+    lam = np.clip(np.fft.rfftn(np.exp(-r / xi)).real, 0.0, None)
+    del r
+    f = np.fft.irfftn(np.sqrt(lam) * np.fft.rfftn(rng.standard_normal((D, H, W))), s=(D, H, W))
+    return ((f - f.mean()) / max(f.std(), 1e-300)).astype(np.float32)
+
+
+def config3d(L: int = 256, p: float = 0.6):
+    """The 3D lattice at the site count of the 4096^2 plane: an L^3 GRF (xi = 8), a fraction p of the sites removed
+    uniformly.  Returns (field, mask) as float32 / uint8 [L, L, L]."""
+    rng = np.random.default_rng(seed_for(7, ROLE_FIELD))
+    f = grf3(L, L, L, 8.0, rng)
+    m = (np.random.default_rng(seed_for(7, ROLE_MASK)).random((L, L, L)) >= p).astype(np.uint8)
+    return f, m
+
+
 def random_small(H: int, W: int, p: float, seed: int, xi: float = 4.0) -> Scene:
     """A small GRF scene with uniform removal, for parity tests of ragged shapes."""
     rng = np.random.default_rng(seed)
