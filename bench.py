@@ -138,6 +138,8 @@ def parse():
     ap.add_argument("--other-p-steps", type=int, default=2)
     ap.add_argument("--profile-sweeps", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and gradient measurements")
+    ap.add_argument("--lattice3d-only", action="store_true",
+                    help="run only the 3D-lattice leg and print its object (for profiling its kernels)")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--sweep-kernel", choices=("auto", "tiles", "lanes"), default="auto",
                     help="sweep kernel of the simulation (auto: the library's choice)")
@@ -262,7 +264,7 @@ def main():
     log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={args.p}, gaps={int((sc.mask == 0).sum())}")
     extras_inputs = None
     other_p = [float(x) for x in args.other_p.split(",") if x.strip()] if args.profile_sweeps == 0 else []
-    if not args.no_extras and args.profile_sweeps == 0:
+    if not args.no_extras and args.profile_sweeps == 0 and not args.lattice3d_only:
         # generated before the GPU is touched (worker processes are started from a process without a GPU context)
         t0 = time.time()
         scenes4 = synth.config4_scenes(args.batch_scenes, workers=min(16, os.cpu_count() or 1))
@@ -271,6 +273,9 @@ def main():
         log(f"[bench] batched and gradient workloads generated in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.lattice3d_only:
+        print(json.dumps({"lattice3d": bench_lattice3d(dev, R, float("nan"), L * L)}), flush=True)
+        return
     state = torch.empty((R, L, L), dtype=torch.float32, device=dev)
     kchoice = {"auto": mpr.SWEEP_AUTO, "tiles": mpr.SWEEP_TILES, "lanes": mpr.SWEEP_LANES}[args.sweep_kernel]
     kernel = sweep_kernel(R, args.sweep_kernel)
