@@ -1951,18 +1951,15 @@ mpr_status mpr_simulate3d(const float* t, const uint8_t* mask, int64_t D, int64_
     a.delta_e = mpr::kDeltaE3 * c.J;
     a.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
     a.Jd = (double)c.J;
-    // one sweep: colour 0, then colour 1, each as the launches over the even and the odd rows
+    // one sweep: colour 0, then colour 1, each one launch over all rows (row tiles of kNW3 rows)
+    a.nrows = (int)((H + mpr::kNW3 - 1) / mpr::kNW3);
     auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
         a.sweep = k;
         for (int colour = 0; colour < 2; ++colour) {
             a.colour = colour;
-            for (int ypar = 0; ypar < 2; ++ypar) {
-                a.ypar = ypar;
-                a.nrows = (int)((H - ypar + 1) / 2);
-                const hipError_t e = mpr::launch_sweep3(a, w.cells, w.tp, w.lanes,
-                                                        energy && colour == 1 ? w.epart : nullptr, s);
-                if (e != hipSuccess) return e;
-            }
+            const hipError_t e = mpr::launch_sweep3(a, w.cells, w.tp, w.lanes,
+                                                    energy && colour == 1 ? w.epart : nullptr, s);
+            if (e != hipSuccess) return e;
         }
         if (energy) return mpr::launch_energy_reduce(w.epart, g.nparts, R, inv_norm, w.e_real, w.series + k, s);
         return hipSuccess;

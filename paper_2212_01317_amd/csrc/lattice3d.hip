@@ -97,26 +97,37 @@ __device__ __noinline__ bool exact3_site(const char* base, int64_t off, int64_t 
     return exact64_6(tp, to, nb, nu, nl, nr, nd, nf, present, two_pi_q, J, T, ui * 5.9604644775390625e-8f);
 }
 
-// YC = (y + colour) mod 2 of the launch's rows.
-template <int YC, bool ENERGY>
+// One wave of a workgroup of kNW3 waves that own the consecutive rows y0 .. y0 + kNW3 - 1 (wave w: row y0 + w) of
+// one band, plane segment and group of realizations.  Rows y +- 1 of the current plane, at the columns the wave
+// updates, are those rows' colour-(1 - c) cells, which this half-sweep does not change: each wave publishes its own
+// row's colour-(1 - c) (cos, sin) of the next plane in LDS, and the first and last waves also load and publish the
+// rows just outside the tile (y0 - 1, y0 + kNW3).  LDS exchange: xch[buffer = plane & 1][slot][k][lane] of
+// (cos, sin), slot 0 = row y0 - 1, slot w + 1 = row y0 + w, slot kNW3 + 1 = row y0 + kNW3; k indexes the four
+// columns x0 + 2k + PX of the row below or above, whose PX is the reader's.  A wave's column parity PX = (x + y + z
+// + c) mod 2 relative to x0 depends on YC = (y + c) mod 2, a template argument of its methods; the two forms are
+// dispatched per wave and per step.
+template <bool ENERGY>
 struct Wave3 {
     Lat3Args a;
     const uint32_t* cells;             // [(D H) nbands] gap bits of the window columns of each row
     const TBand* tb;
     char* S;                           // this wave's group of realizations
-    int y, band, x0, zs, ze;
-    uint32_t lane4, real;
+    float2* xch;                       // LDS exchange of the workgroup
+    int y, band, x0, zs, ze, wslot;
+    uint32_t lane4, lane, real;
     PhiloxLane pl;
     RoundKeys rk;
     int64_t wrow, wplane;              // bytes per grid row and per plane
     int64_t orow;                      // byte offset of (plane 0, row y, window column 0) in the group
+    int64_t hoff;                      // byte offset of the halo row from row y (0: this wave loads no halo row)
+    int hslot;                         // its exchange slot
     uint32_t colmask;                  // window columns inside the grid
     float c[4][kW3], s[4][kW3];        // row y of four planes by slot (plane & 3)
     float ang[4][kW3];                 // the same as loaded (live from the request to the arrival only)
     uint32_t gap[4];                   // gap bits of row y of the slot's plane
     uint32_t ngap;                     // gap bits of the plane last requested
-    float au[kH3], ad[kH3];            // rows y - 1 and y + 1 of the next plane at its updated columns, as loaded
-    float cu[kH3], su[kH3], cd[kH3], sd[kH3];   // their (cos, sin) for the current plane
+    float ah[kH3];                     // the halo row of the plane last requested, at the halo columns
+    float cu[kH3], su[kH3], cd[kH3], sd[kH3];   // rows y - 1 and y + 1 of the current plane at its updated columns
     long long e_acc;
 
     __device__ __forceinline__ float ld(int64_t off, int j) const
@@ -128,6 +139,10 @@ struct Wave3 {
         *reinterpret_cast<float*>(S + off + j * 256 + lane4) = v;
     }
     __device__ __forceinline__ int64_t plane_off(int z) const { return orow + (int64_t)z * wplane; }
+    __device__ __forceinline__ float2& xe(int buf, int slot, int k) const
+    {
+        return xch[((buf * (kNW3 + 2) + slot) * kH3 + k) * 64 + lane];
+    }
 
     // row y of plane z (inside the grid or not) into slot SL; its gap bits
     template <int SL>
@@ -178,52 +193,55 @@ struct Wave3 {
         }
     }
 
-    // rows y - 1 and y + 1 of plane z at its updated columns (window columns PX + 1, PX + 3, ...)
-    template <int PX>
-    __device__ __forceinline__ void request_ud(int z)
+    // publishes the (cos, sin) of row y of the plane in slot SL at the columns its neighbour rows update there (the
+    // columns of parity 1 - PX, PX this row's parity on that plane)
+    template <int SL, int PX>
+    __device__ __forceinline__ void publish(int buf) const
     {
-        const int64_t off = plane_off(z);
-        const bool up = y > 0, dn = y + 1 < a.H;
-        if (up && dn && colmask == (1u << kW3) - 1u) {
 #pragma unroll
-            for (int k = 0; k < kH3; ++k) {
-                au[k] = ld(off - wrow, 2 * k + PX + 1);
-                ad[k] = ld(off + wrow, 2 * k + PX + 1);
-            }
+        for (int k = 0; k < kH3; ++k) xe(buf, wslot, k) = make_float2(c[SL][2 * k + 2 - PX], s[SL][2 * k + 2 - PX]);
+    }
+
+    // the halo row of plane z at this wave's updated columns there (parity PX)
+    template <int PX>
+    __device__ __forceinline__ void request_halo(int z)
+    {
+        if (z < 0 || z >= a.D) return;
+        const int64_t off = plane_off(z) + hoff;
+        if (colmask == (1u << kW3) - 1u) {
+#pragma unroll
+            for (int k = 0; k < kH3; ++k) ah[k] = ld(off, 2 * k + PX + 1);
         } else {
 #pragma unroll
-            for (int k = 0; k < kH3; ++k) {
-                const int j = 2 * k + PX + 1;
-                const bool okc = (colmask >> j) & 1u;
-                au[k] = (up && okc) ? ld(off - wrow, j) : __builtin_nondeterministic_value(0.0f);
-                ad[k] = (dn && okc) ? ld(off + wrow, j) : __builtin_nondeterministic_value(0.0f);
-            }
+            for (int k = 0; k < kH3; ++k)
+                ah[k] = ((colmask >> (2 * k + PX + 1)) & 1u) ? ld(off, 2 * k + PX + 1)
+                                                               : __builtin_nondeterministic_value(0.0f);
+        }
+    }
+    template <int PX>
+    __device__ __forceinline__ void arrive_halo(int z, int buf)
+    {
+        const bool inz = z >= 0 && z < a.D;
+#pragma unroll
+        for (int k = 0; k < kH3; ++k) {
+            const float t = a.q * ah[k];
+            float cv = cos_rev(t), sv = sin_rev(t);
+            if (!inz || !((colmask >> (2 * k + PX + 1)) & 1u)) cv = sv = 0.0f;
+            xe(buf, hslot, k) = make_float2(cv, sv);
+            ah[k] = __builtin_nondeterministic_value(0.0f);
         }
     }
 
-    template <int PX>
-    __device__ __forceinline__ void arrive_ud()
+    // rows y - 1 and y + 1 of the plane in buffer buf, from the exchange
+    __device__ __forceinline__ void read_nb(int buf)
     {
 #pragma unroll
         for (int k = 0; k < kH3; ++k) {
-            const float tu = a.q * au[k], td = a.q * ad[k];
-            cu[k] = cos_rev(tu);
-            su[k] = sin_rev(tu);
-            cd[k] = cos_rev(td);
-            sd[k] = sin_rev(td);
-        }
-        if (y == 0) {
-#pragma unroll
-            for (int k = 0; k < kH3; ++k) cu[k] = su[k] = 0.0f;
-        }
-        if (y + 1 >= a.H) {
-#pragma unroll
-            for (int k = 0; k < kH3; ++k) cd[k] = sd[k] = 0.0f;
-        }
-        if (colmask != (1u << kW3) - 1u) {
-#pragma unroll
-            for (int k = 0; k < kH3; ++k)
-                if (!((colmask >> (2 * k + PX + 1)) & 1u)) cu[k] = su[k] = cd[k] = sd[k] = 0.0f;
+            const float2 u = xe(buf, wslot - 1, k), d = xe(buf, wslot + 1, k);
+            cu[k] = u.x;
+            su[k] = u.y;
+            cd[k] = d.x;
+            sd[k] = d.y;
         }
     }
 
@@ -281,7 +299,7 @@ struct Wave3 {
 
     // the colour of the launch on plane z (slot S0): the pairs of the updated columns, then the energy of the
     // colour-1 sample sites
-    template <int S0>
+    template <int S0, int YC>
     __device__ __forceinline__ void plane(int z)
     {
         constexpr int SP = (S0 + 3) & 3, SN = (S0 + 1) & 3;
@@ -317,84 +335,148 @@ struct Wave3 {
         }
     }
 
-    // one step (S0 = z & 3): plane z + 1 and rows y +- 1 of plane z arrive, plane z + 2 and rows y +- 1 of plane
-    // z + 1 are requested, then plane z is updated
-    template <int S0>
+    // one step (S0 = z & 3): plane z + 1 arrives and is published with the halo row of plane z + 1, plane z + 2
+    // and the halo row of plane z + 2 are requested, rows y +- 1 of plane z come from the exchange, then plane z
+    // is updated.  The caller ends the step with a barrier.
+    template <int S0, int YC>
     __device__ __forceinline__ void step(int z)
     {
         constexpr int SN = (S0 + 1) & 3, S2 = (S0 + 2) & 3;
         constexpr int PX = (YC + S0) & 1, PXN = (YC + S0 + 1) & 1;
         arrive<SN>(z + 1);
-        arrive_ud<PX>();
+        publish<SN, PXN>((z + 1) & 1);
+        if (hoff != 0) {
+            if (z + 1 < ze) arrive_halo<PXN>(z + 1, (z + 1) & 1);
+            if (z + 2 < ze) request_halo<PX>(z + 2);
+        }
         if (z + 2 <= ze) request<S2>(z + 2);
-        if (z + 1 < ze) request_ud<PXN>(z + 1);
-        plane<S0>(z);
+        read_nb(z & 1);
+        plane<S0, YC>(z);
     }
 
-    __device__ __forceinline__ void run()
+    // planes zs - 1 (slot 3) and zs (slot 0) in the window and published with the halo row of plane zs, plane zs + 1
+    // and the halo row of plane zs + 1 requested; the caller then waits at the barrier
+    template <int YC>
+    __device__ __forceinline__ void start()
     {
-        e_acc = 0;
-        pl = philox_lane(real, a.sweep, a.key0, a.key1);
-        rk = round_keys(a.key0, a.key1);
-        wrow = (int64_t)a.W * 256;
-        wplane = (int64_t)a.H * wrow;
-        orow = ((int64_t)y * a.W + (x0 - 1)) * 256;
-        colmask = 0u;
-        for (int j = 0; j < kW3; ++j) {
-            const int x = x0 - 1 + j;
-            if (x >= 0 && x < a.W) colmask |= 1u << j;
-        }
-        colmask = __builtin_amdgcn_readfirstlane(colmask);
-        // planes zs - 1 (slot 3) and zs (slot 0) in the window, plane zs + 1 and rows y +- 1 of plane zs requested
+        constexpr int PX0 = YC & 1, PX1 = (YC + 1) & 1;      // zs is a multiple of 4
         request<3>(zs - 1);
         arrive<3>(zs - 1);
         request<0>(zs);
         arrive<0>(zs);
+        publish<0, PX0>(zs & 1);
+        if (hoff != 0) {
+            request_halo<PX0>(zs);
+            arrive_halo<PX0>(zs, zs & 1);
+            if (zs + 1 < ze) request_halo<PX1>(zs + 1);
+        }
         request<1>(zs + 1);
-        request_ud<(YC + 0) & 1>(zs);
+    }
+
+    // the wave's whole segment: the start, then one step per plane, each followed by the workgroup's barrier (the
+    // exchange of plane z + 1 is complete at the barrier after step z)
+    template <int YC>
+    __device__ __forceinline__ void run()
+    {
+        start<YC>();
+        __syncthreads();
         for (int zb = zs; zb < ze; zb += 4) {
-            step<0>(zb);
+            step<0, YC>(zb);
+            __syncthreads();
             if (zb + 1 >= ze) break;
-            step<1>(zb + 1);
+            step<1, YC>(zb + 1);
+            __syncthreads();
             if (zb + 2 >= ze) break;
-            step<2>(zb + 2);
+            step<2, YC>(zb + 2);
+            __syncthreads();
             if (zb + 3 >= ze) break;
-            step<3>(zb + 3);
+            step<3, YC>(zb + 3);
+            __syncthreads();
         }
     }
 };
 
-template <int YC, bool ENERGY>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep3(
+// One launch is one colour of a sweep over all rows: workgroups of kNW3 waves (consecutive rows), work items
+// (row tile, band, plane segment, group of realizations).
+template <bool ENERGY>
+__global__ __launch_bounds__(64 * kNW3) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep3(
     Lat3Args a, const uint32_t* __restrict__ cells, const TBand* __restrict__ tb, float* state,
     long long* __restrict__ epart)
 {
+    __shared__ float2 xch[2 * (kNW3 + 2) * kH3 * 64];
     // XCD-aware order: workgroup g runs on XCD g % 8; consecutive items (adjacent bands) go to the same XCD.
     const uint32_t N = (uint32_t)a.nrows * (uint32_t)a.nbands * (uint32_t)a.nzseg * (uint32_t)(a.Rp / 64);
     const uint32_t g = blockIdx.x, xcd = g & 7u, k = g >> 3;
     const uint32_t per = N >> 3, rem = N & 7u;
     const uint32_t item = xcd < rem ? xcd * (per + 1u) + k : rem * (per + 1u) + (xcd - rem) * per + k;
-    if (item >= N) return;
+    if (item >= N) return;                           // the whole workgroup (item is the same for its waves)
     const uint32_t band = item % (uint32_t)a.nbands;
     uint32_t rest = item / (uint32_t)a.nbands;
     const uint32_t zseg = rest % (uint32_t)a.nzseg;
     rest /= (uint32_t)a.nzseg;
-    const uint32_t row = rest % (uint32_t)a.nrows;
+    const uint32_t tile = rest % (uint32_t)a.nrows;
     const uint32_t rg = rest / (uint32_t)a.nrows;
     const int64_t n_all = (int64_t)a.D * a.H * a.W;
-    Wave3<YC, ENERGY> w{a, cells, tb, reinterpret_cast<char*>(state) + (int64_t)rg * n_all * 256};
-    w.y = a.ypar + 2 * (int)row;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    Wave3<ENERGY> w{a, cells, tb, reinterpret_cast<char*>(state) + (int64_t)rg * n_all * 256, xch};
+    const int y0 = (int)tile * kNW3;
+    w.y = y0 + wv;
     w.band = (int)band;
     w.x0 = (int)band * kB3;
     w.zs = (int)zseg * a.zseg;
     w.ze = w.zs + a.zseg < a.D ? w.zs + a.zseg : a.D;
-    w.lane4 = threadIdx.x * 4u;
-    const int lane = (int)(rg * 64 + threadIdx.x);
+    w.wslot = wv + 1;
+    w.lane = threadIdx.x & 63u;
+    w.lane4 = w.lane * 4u;
+    const int lane = (int)(rg * 64 + w.lane);
     w.real = a.real_offset + (uint32_t)lane;
-    w.run();
-    if (ENERGY && lane < a.R)
-        epart[(int64_t)lane * ((int64_t)a.H * a.nbands * a.nzseg) + ((int64_t)w.y * a.nbands + band) * a.nzseg + zseg] =
-            w.e_acc;
+    const bool active = w.y < a.H;
+    const int yc = (w.y + a.colour) & 1;
+    // this wave's exchange slots start at zero in both buffers (rows outside the grid stay zero)
+    const float2 zero2 = make_float2(0.0f, 0.0f);
+    w.hoff = 0;
+    w.hslot = 0;
+#pragma unroll
+    for (int kk = 0; kk < kH3; ++kk) w.xe(0, w.wslot, kk) = w.xe(1, w.wslot, kk) = zero2;
+    if (wv == 0) {
+#pragma unroll
+        for (int kk = 0; kk < kH3; ++kk) w.xe(0, 0, kk) = w.xe(1, 0, kk) = zero2;
+    }
+    if (wv == kNW3 - 1) {
+#pragma unroll
+        for (int kk = 0; kk < kH3; ++kk) w.xe(0, kNW3 + 1, kk) = w.xe(1, kNW3 + 1, kk) = zero2;
+    }
+    w.e_acc = 0;
+    __syncthreads();                                 // the zeroed slots before any publication
+    if (active) {
+        w.pl = philox_lane(w.real, a.sweep, a.key0, a.key1);
+        w.rk = round_keys(a.key0, a.key1);
+        w.wrow = (int64_t)a.W * 256;
+        w.wplane = (int64_t)a.H * w.wrow;
+        w.orow = ((int64_t)w.y * a.W + (w.x0 - 1)) * 256;
+        w.colmask = 0u;
+        for (int j = 0; j < kW3; ++j) {
+            const int x = w.x0 - 1 + j;
+            if (x >= 0 && x < a.W) w.colmask |= 1u << j;
+        }
+        w.colmask = __builtin_amdgcn_readfirstlane(w.colmask);
+        if (wv == 0 && y0 > 0) {
+            w.hoff = -w.wrow;
+            w.hslot = 0;
+        }
+        if (wv == kNW3 - 1 && y0 + kNW3 < a.H) {
+            w.hoff = w.wrow;
+            w.hslot = kNW3 + 1;
+        }
+        // every wave of the workgroup passes the same number of barriers: one after the start and one per plane
+        if (yc) w.template run<1>();
+        else w.template run<0>();
+    } else {
+        for (int z = w.zs - 1; z < w.ze; ++z) __syncthreads();
+    }
+    if (ENERGY && active && lane < a.R)
+        epart[(int64_t)lane * ((int64_t)a.H * a.nbands * a.nzseg) + ((int64_t)w.y * a.nbands + band) * a.nzseg +
+              zseg] = w.e_acc;
 }
 
 // gap bits of each row's window columns (x0 - 1 .. x0 + kB3)
@@ -642,15 +724,9 @@ hipError_t launch_sweep3(const Lat3Args& a, const uint32_t* cells, const TBand* 
 {
     const int64_t N = (int64_t)a.nrows * a.nbands * a.nzseg * (a.Rp / 64);
     if (N <= 0) return hipSuccess;
-    const int yc = (a.ypar + a.colour) & 1;
     const dim3 grid((unsigned)N);
-    if (yc == 0) {
-        if (epart) hipLaunchKernelGGL((k_sweep3<0, true>), grid, dim3(64), 0, s, a, cells, tb, state, epart);
-        else hipLaunchKernelGGL((k_sweep3<0, false>), grid, dim3(64), 0, s, a, cells, tb, state, epart);
-    } else {
-        if (epart) hipLaunchKernelGGL((k_sweep3<1, true>), grid, dim3(64), 0, s, a, cells, tb, state, epart);
-        else hipLaunchKernelGGL((k_sweep3<1, false>), grid, dim3(64), 0, s, a, cells, tb, state, epart);
-    }
+    if (epart) hipLaunchKernelGGL((k_sweep3<true>), grid, dim3(64 * kNW3), 0, s, a, cells, tb, state, epart);
+    else hipLaunchKernelGGL((k_sweep3<false>), grid, dim3(64 * kNW3), 0, s, a, cells, tb, state, epart);
     return hipGetLastError();
 }
 

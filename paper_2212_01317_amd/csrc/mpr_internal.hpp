@@ -169,10 +169,10 @@ hipError_t launch_sweep_rl(const RlArgs& a, const uint2* cells, const TBand* tb,
 constexpr float kDeltaE3 = 2.75e-5f;
 constexpr int kB3 = 8;           // owned columns of a wave of the 3D sweep (16 would need more than 256 VGPRs)
 constexpr int kZSeg3 = 64;       // planes of a wave's segment
+constexpr int kNW3 = 4;          // waves (consecutive rows) of a workgroup of the 3D sweep
 struct Lat3Args {
     int D, H, W, R, Rp, Mw, nbands, nzseg, zseg;
-    int ypar;                    // the launch's rows: y = ypar, ypar + 2, ...
-    int nrows;                   // how many
+    int nrows;                   // row tiles of kNW3 rows
     int lb_d, lb_h, lb_w, nbx, nby;
     uint32_t lbw_inv;            // ceil(2^32 / lb_w) for lb_w > 1
     uint32_t sweep, real_offset, scene, key0, key1;
@@ -206,8 +206,8 @@ hipError_t launch_energy3_full(const float* state, int64_t D, int64_t H, int64_t
 // gap bits of each row's window columns: [(D H) nbands]
 hipError_t launch_cells3(const uint8_t* mask, int64_t D, int64_t H, int64_t W, int nbands, uint32_t* cells,
                          hipStream_t s);
-// one half-sweep (colour a.colour, rows of parity a.ypar) of the lane-layout state [G][n][64], in place; with epart
-// set, the fixed-point energy of each wave's colour-1 sites goes to epart[r][(y * nbands + band) * nzseg + zseg]
+// one half-sweep (colour a.colour, all rows) of the lane-layout state [G][n][64], in place; with epart set, the
+// fixed-point energy of each row's colour-1 sites goes to epart[r][(y * nbands + band) * nzseg + zseg]
 hipError_t launch_sweep3(const Lat3Args& a, const uint32_t* cells, const TBand* tb, float* state, long long* epart,
                          hipStream_t s);
 // the matching curve of the cubic lattice: periodic L^3, one chain per temperature
