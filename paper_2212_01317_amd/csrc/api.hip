@@ -14,6 +14,7 @@
 
 #include "batched.hpp"
 #include "mpr.h"
+#include "lattice3d.hpp"
 #include "mpr_internal.hpp"
 
 using mpr::Carve;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "metropolis.hpp"
+#include "lattice3d.hpp"
 #include "mpr_internal.hpp"
 #include "philox_lane.hpp"
 
