@@ -107,9 +107,21 @@ __device__ __noinline__ bool exact3_site(const char* base, int64_t off, int64_t 
 // columns x0 + 2k + PX of the row below or above, whose PX is the reader's.  A wave's column parity PX = (x + y + z
 // + c) mod 2 relative to x0 depends on YC = (y + c) mod 2, a template argument of its methods; the two forms are
 // dispatched per wave and per step.
+// The launch arguments the plane loop reads (the others are used before the loop only), so that the loop keeps no
+// more scalar registers than it needs: the exact decision's FP64 constants are recomputed from q and J there as
+// the host computes them (2 pi q and J as doubles), the FP32 tolerance of T = 0 is kDeltaE3 J as on the host, the
+// temperature block row is advanced plane by plane instead of divided, and the counter word of the sweep's colour
+// is formed once.
+struct Lat3Loop {
+    int D, H, W, nbands, Mw, lb_w, lb_d;
+    uint32_t lbw_inv, w3k1;
+    float q, J, delta_e;
+    int64_t bz_stride;                 // temperature blocks per block plane: nby nbx
+};
+
 template <bool ENERGY>
 struct Wave3 {
-    Lat3Args a;
+    Lat3Loop a;
     const uint32_t* cells;             // [(D H) nbands] gap bits of the window columns of each row
     const TBand* tb;
     char* S;                           // this wave's group of realizations
@@ -123,6 +135,8 @@ struct Wave3 {
     int64_t hoff;                      // byte offset of the halo row from row y (0: this wave loads no halo row)
     int hslot;                         // its exchange slot
     uint32_t colmask;                  // window columns inside the grid
+    int bzc, bzr;                      // temperature block plane of the current plane, and the plane's place in it
+    int64_t byx;                       // (y / lb_h) nbx: the row's offset inside a block plane
     float c[4][kW3], s[4][kW3];        // row y of four planes by slot (plane & 3)
     float ang[4][kW3];                 // the same as loaded (live from the request to the arrival only)
     uint32_t gap[4];                   // gap bits of row y of the slot's plane
@@ -287,7 +301,7 @@ struct Wave3 {
             int xb = x0;
             asm volatile("" : "+s"(xb));
             const bool ex = exact3_site(S, off + j * 256 + lane4, wrow, wplane, xb - 1 + j, y, z, a.D, a.H, a.W, tp,
-                                        ui, a.two_pi_q, a.Jd, T.T);
+                                        ui, 2.0 * kPi * (double)a.q, (double)a.J, T.T);
             r = need ? (ex ? -1.0f : 1.0f) : r;
         }
         const bool acc = r < 0.0f;
@@ -306,8 +320,8 @@ struct Wave3 {
         constexpr int SP = (S0 + 3) & 3, SN = (S0 + 1) & 3;
         constexpr int PX = (YC + S0) & 1;              // (x + y + z + colour) even <=> x - x0 = PX mod 2
         const int64_t off = plane_off(z);
-        const int64_t brow = ((int64_t)(z / a.lb_d) * a.nby + y / a.lb_h) * a.nbx;
-        const uint32_t w3k1 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)a.colour) ^ a.key1;
+        const int64_t brow = (int64_t)bzc * a.bz_stride + byx;
+        const uint32_t w3k1 = a.w3k1;
         const uint32_t base = (uint32_t)(z * a.H + y) * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
         int xb = x0;
         asm volatile("" : "+s"(xb));
@@ -353,6 +367,10 @@ struct Wave3 {
         if (z + 2 <= ze) request<S2>(z + 2);
         read_nb(z & 1);
         plane<S0, YC>(z);
+        if (++bzr == a.lb_d) {
+            bzr = 0;
+            ++bzc;
+        }
     }
 
     // planes zs - 1 (slot 3) and zs (slot 0) in the window and published with the halo row of plane zs, plane zs + 1
@@ -419,7 +437,21 @@ __global__ __launch_bounds__(64 * kNW3) __attribute__((amdgpu_waves_per_eu(2, 2)
     const uint32_t rg = rest / (uint32_t)a.nrows;
     const int64_t n_all = (int64_t)a.D * a.H * a.W;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    Wave3<ENERGY> w{a, cells, tb, reinterpret_cast<char*>(state) + (int64_t)rg * n_all * 256, xch};
+    Lat3Loop la;
+    la.D = a.D;
+    la.H = a.H;
+    la.W = a.W;
+    la.nbands = a.nbands;
+    la.Mw = a.Mw;
+    la.lb_w = a.lb_w;
+    la.lb_d = a.lb_d;
+    la.lbw_inv = a.lbw_inv;
+    la.w3k1 = ctr_word3(a.scene, TAG_SWEEP, (uint32_t)a.colour) ^ a.key1;
+    la.q = a.q;
+    la.J = a.J;
+    la.delta_e = kDeltaE3 * a.J;
+    la.bz_stride = (int64_t)a.nby * a.nbx;
+    Wave3<ENERGY> w{la, cells, tb, reinterpret_cast<char*>(state) + (int64_t)rg * n_all * 256, xch};
     const int y0 = (int)tile * kNW3;
     w.y = y0 + wv;
     w.band = (int)band;
@@ -461,6 +493,9 @@ __global__ __launch_bounds__(64 * kNW3) __attribute__((amdgpu_waves_per_eu(2, 2)
             if (x >= 0 && x < a.W) w.colmask |= 1u << j;
         }
         w.colmask = __builtin_amdgcn_readfirstlane(w.colmask);
+        w.bzc = w.zs / a.lb_d;
+        w.bzr = w.zs % a.lb_d;
+        w.byx = (int64_t)(w.y / a.lb_h) * a.nbx;
         if (wv == 0 && y0 > 0) {
             w.hoff = -w.wrow;
             w.hslot = 0;
