@@ -322,7 +322,7 @@ struct Wave3 {
         const int64_t off = plane_off(z);
         const int64_t brow = (int64_t)bzc * a.bz_stride + byx;
         const uint32_t w3k1 = a.w3k1;
-        const uint32_t base = (uint32_t)(z * a.H + y) * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
+        const uint32_t base = ((uint32_t)z * (uint32_t)a.H + (uint32_t)y) * (uint32_t)a.Mw + (uint32_t)(x0 / 4);
         int xb = x0;
         asm volatile("" : "+s"(xb));
         int e = 0;

@@ -96,6 +96,7 @@ def test_reference_curve3d_parity():
     (9, 1, 1, (2, 1, 1), 64, 0.5, False, 0),       # one column along z
     (1, 1, 9, (1, 1, 4), 64, 0.5, False, 0),       # one row along x
     (2, 2, 2, (2, 2, 2), 64, 0.5, False, 0),
+    (6, 11, 13, (2, 3, 1), 64, 0.5, False, 1),     # one-column blocks (every column its own temperature)
 ])
 def test_simulate3d_fixed_matches_oracle(D, H, W, lb, R, p, zero, init):
     t, m = _scene3(D, H, W, p, seed=D * 100 + H * 10 + W)
