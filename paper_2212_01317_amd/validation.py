@@ -86,9 +86,10 @@ def variants(methods, s0: Setting, blocks, ns):
 
 
 def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None = None, device="cuda",
-        blocks=None, ns=None):
+        blocks=None, ns=None, on_row=None):
     """Rows {p, method, block, n_s, MAAE, MRASE, t_ms, sweeps, k_star} for every p and variant (sweeps: mean of
-    k* + n_samp; k_star: mean k*); the same masks for every variant."""
+    k* + n_samp; k_star: mean k*); the same masks for every variant; on_row(row), if given, is called with each
+    row as soon as it is complete."""
     s0 = setting or Setting()
     blocks = list(blocks) if blocks else [s0.block]
     ns = list(ns) if ns else [s0.n_s]
@@ -120,6 +121,8 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
                              t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)),
                              k_star=float(np.mean(kst)), stop="chain" if s.stop_mode == STOP_AUTO_CHAIN else "mean",
                              n_real=s.n_real, M=M, L=[H, W]))
+            if on_row is not None:
+                on_row(rows[-1])        # each row as soon as it is complete
     return rows
 
 
@@ -144,12 +147,10 @@ def main():
         field = synth.grf_aniso(a.L, a.L, 16.0, 2.0, np.random.default_rng(a.field_seed)).astype(np.float32)
     else:
         field = synth.ns_field(a.L, a.L, 4, (2.0, 32.0), np.random.default_rng(a.field_seed)).astype(np.float32)
-    rows = run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
-               Setting(n_real=a.n_real, seed=a.seed,
-                       stop_mode=STOP_AUTO_CHAIN if a.stop == "chain" else STOP_AUTO), blocks=[int(b) for b in a.blocks.split(",")],
-               ns=[int(n) for n in a.ns.split(",")])
-    for r in rows:
-        print(json.dumps(r), flush=True)
+    run(field, [float(x) for x in a.p.split(",")], a.M, a.methods.split(","),
+        Setting(n_real=a.n_real, seed=a.seed, stop_mode=STOP_AUTO_CHAIN if a.stop == "chain" else STOP_AUTO),
+        blocks=[int(b) for b in a.blocks.split(",")], ns=[int(n) for n in a.ns.split(",")],
+        on_row=lambda r: print(json.dumps(r), flush=True))
 
 
 if __name__ == "__main__":
