@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpr.so")
-SOURCES = ["api.hip", "kernels.hip", "sweep.hip", "rl_sweep.hip", "grad.hip", "batched.hip", "rates.hip", "dc.hip",
-           "lattice3d.hip"]
+SOURCES = ["api.hip", "kernels.hip", "sweep.hip", "rl_sweep.hip", "rl_start.hip", "grad.hip", "batched.hip", "rates.hip",
+           "dc.hip", "lattice3d.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -16,6 +16,7 @@
 #include "mpr.h"
 #include "lattice3d.hpp"
 #include "mpr_internal.hpp"
+#include "rl_start.hpp"
 
 using mpr::Carve;
 
@@ -902,7 +903,11 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     ia.key0 = key0;
     ia.key1 = key1;
     ia.mode = c.init_mode;
-    MPR_HIP(mpr::launch_init(ia, s));
+    // the realization-lane sweep starts straight in its two lane buffers (both hold the samples); the final state
+    // moves back into `state`
+    const bool rl = use_rl(H, W, cfg);
+    if (rl) MPR_HIP(mpr::launch_rl_init(ia, mpr::rl_geometry(H, W, R).Rp, w.rl[0], w.rl[1], s));
+    else MPR_HIP(mpr::launch_init(ia, s));
     const bool directional = c.coupling == MPR_COUPLING_DIRECTIONAL;
     if (directional) {
         MPR_HIP(mpr::launch_tpairs_directional(T_blocks, nblocks_of(H, W, lb_h, lb_w), c.J, mpr::kDeltaE * c.J,
@@ -915,7 +920,8 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
     const int nfull = mpr::energy_full_parts(H, W);
     if (need_energy) {
-        MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
+        if (rl) MPR_HIP(mpr::launch_rl_energy_full(w.rl[0], H, W, R, c.q, w.epart, nfull, s));
+        else MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
         MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series, s));
     }
     // double checkerboard: in place in `state`, energy of the whole grid after the sweep
@@ -942,9 +948,7 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     da.delta_e = mpr::kDeltaE * c.J;
     da.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
     da.Jd = (double)c.J;
-    // realization-lane sweep: the start moves into two [HW][Rp] buffers (both hold the samples), sweeps alternate
-    // between them, and the final state moves back into `state`
-    const bool rl = use_rl(H, W, cfg);
+    // realization-lane sweep: sweeps alternate between the two [HW][Rp] buffers
     mpr::RlArgs ra{};
     int rl_cur = 0;
     if (rl) {
@@ -973,7 +977,6 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
         ra.two_pi_q = 2.0 * mpr::kPi * (double)c.q;
         ra.Jd = (double)c.J;
         MPR_HIP(mpr::launch_rl_cells(mask, H, W, w.cells, s));
-        MPR_HIP(mpr::launch_rl_to_lanes(state, HW, R, w.rl[0], w.rl[1], s));
     }
     const int rl_parts = rl ? ra.nbands * ra.nseg : 0;
     auto sweep = [&](uint32_t k, bool energy) -> hipError_t {
@@ -1457,20 +1460,19 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         ia.key0 = key0;
         ia.key1 = key1;
         ia.mode = c.init_mode;
-        MPR_HIP(mpr::launch_init(ia, s));
+        const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
+        MPR_HIP(mpr::launch_rl_init(ia, rg.Rp, w.buf0[i], w.buf1[i], s));    // the start straight into both lane buffers
         MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
         const int64_t HW = sc.H * sc.W;
         const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
         const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
-            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
+            MPR_HIP(mpr::launch_rl_energy_full(w.buf0[i], sc.H, sc.W, R, c.q, w.epart[i], nfull, s));
             MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
         }
         if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, s));
         MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], s));
-        MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], s));
-        const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
         mpr::BatchLaneScene& d = hs[i];
         mpr::RlArgs& ra = d.a;
         ra = mpr::RlArgs{};
