@@ -117,3 +117,40 @@ def test_batched_workspace_follows_the_batch_kernel():
     assert ws([big, small], few_lanes) >= lane_bufs(*big) + lane_bufs(*small)
     # 16-wide blocks take two temperature columns per window, 24-wide ones line up with the bands: tile batch
     assert ws([big, (70, 130, 24)], auto) == ws([big, (70, 130, 24)], tiles)
+
+
+def test_3d_arguments_rejected_before_device_work():
+    """The 3D entry points check shapes, blocks, the configuration and the workspace on the host first."""
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(0x1000)
+    cfg = _lib.SimConfig(n_real=64, stop_mode=_lib.STOP_FIXED, n_eq=2).to_c()
+    for D, H, W in ((0, 4, 4), (4, 0, 4), (4, 4, 70000), (65535, 65535, 64)):
+        st = L.mpr_simulate3d(dummy, dummy, D, H, W, dummy, 2, 2, 2, ctypes.byref(cfg), dummy, dummy, None, None,
+                              dummy, 1 << 40, None)
+        assert st == 2, (D, H, W)
+    st = L.mpr_simulate3d(dummy, dummy, 4, 4, 4, dummy, 0, 2, 2, ctypes.byref(cfg), dummy, dummy, None, None, dummy,
+                          1 << 40, None)
+    assert st == 2                                   # a block side below 1
+    for kw in (dict(t_mode=_lib.T_SITE), dict(order=_lib.ORDER_DC), dict(coupling=_lib.COUPLING_DIRECTIONAL),
+               dict(stop_mode=5), dict(stop_mode=_lib.STOP_AUTO_CHAIN, n_fit=1)):
+        c = _lib.SimConfig(n_real=64, **kw).to_c()
+        st = L.mpr_simulate3d(dummy, dummy, 4, 4, 4, dummy, 2, 2, 2, ctypes.byref(c), dummy, dummy, None, None, dummy,
+                              1 << 40, None)
+        assert st == 1, kw
+    need = L.mpr_simulate3d_workspace_bytes(4, 4, 4, 2, 2, 2, ctypes.byref(cfg))
+    assert need >= 64 * 64 * 4                        # the lane copy of the state
+    st = L.mpr_simulate3d(dummy, dummy, 4, 4, 4, dummy, 2, 2, 2, ctypes.byref(cfg), dummy, dummy, None, None, dummy,
+                          need - 1, None)
+    assert st == 6
+    assert L.mpr_reference_curve3d(0.5, dummy, 4, 7, 10, 10, 0, dummy, dummy, 1 << 40, None) == 2   # odd L
+    assert L.mpr_calibrate_temperature3d(dummy, dummy, 4, 4, 4, 2, 2, 2, 0.5, 1.0, dummy, dummy, 0, dummy, None,
+                                         None, dummy, 1 << 40, None) == 1                          # no curve points
+
+
+def test_per_chain_stop_workspace_holds_the_history():
+    L = _lib.lib()
+    a = _lib.SimConfig(n_real=256, stop_mode=_lib.STOP_AUTO, n_max=1000).to_c()
+    b = _lib.SimConfig(n_real=256, stop_mode=_lib.STOP_AUTO_CHAIN, n_max=1000).to_c()
+    wa = L.mpr_simulate_workspace_bytes(512, 512, 32, 32, ctypes.byref(a))
+    wb = L.mpr_simulate_workspace_bytes(512, 512, 32, 32, ctypes.byref(b))
+    assert wb - wa >= 1001 * 256 * 8
