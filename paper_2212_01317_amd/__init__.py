@@ -24,7 +24,8 @@ __all__ = ["INIT_BLOCK_MEAN", "INIT_RANDOM", "STOP_AUTO", "STOP_AUTO_CHAIN", "ST
            "mpr_reference_curve", "mpr_simulate", "mpr_sweep", "mpr_validate", "default_T_grid", "reference_curve", "predict",
            "Prediction", "CURVE_SPEC", "MPRFunction", "mpr_block_energy", "mpr_temperature_grad",
            "mpr_simulate_batched", "BatchOutput", "mpr_probe_instruction_rates", "mpr_sst_temperatures",
-           "mpr_calibrate_temperature3d", "mpr_reference_curve3d", "mpr_simulate3d"]
+           "mpr_calibrate_temperature3d", "mpr_reference_curve3d", "mpr_simulate3d", "predict3d", "reference_curve3d",
+           "CURVE3_SPEC"]
 
 # The matching curve used by default: 121 temperatures log-spaced over [1e-3, 1e2] (24 per decade), periodic
 # 128 x 128 lattice, 1000 sweeps to equilibrate and 2000 to average, fixed seed.
@@ -47,6 +48,26 @@ def reference_curve(q: float = 0.5, device="cuda", spec: dict | None = None):
     if key not in _curve_cache:
         Tg = default_T_grid(device) if spec is None or "T_grid" not in sp else sp["T_grid"]
         e = mpr_reference_curve(Tg, L=sp["L"], n_therm=sp["n_therm"], n_meas=sp["n_meas"], seed=sp["seed"], q=q)
+        _curve_cache[key] = (Tg.to(torch.float64), e)
+    return _curve_cache[key]
+
+
+# The matching curve of the cubic lattice used by predict3d by default: 41 temperatures log-spaced over [1e-3, 1e2]
+# (8 per decade), periodic 32^3 lattice, 500 sweeps to equilibrate and 1000 to average, fixed seed.
+CURVE3_SPEC = dict(L=32, n_therm=500, n_meas=1000, seed=2212013170, decades=(-3, 2), per_decade=8)
+
+
+def reference_curve3d(q: float = 0.5, device="cuda", spec: dict | None = None):
+    """(curve_T float64, curve_e float64) of the cubic lattice on the device, computed once per (q, spec) by
+    mpr_reference_curve3d."""
+    sp = dict(CURVE3_SPEC if spec is None else spec)
+    key = ("3d", float(q), str(torch.device(device)), tuple(sorted((k, str(v)) for k, v in sp.items())))
+    if key not in _curve_cache:
+        lo, hi = sp["decades"]
+        n = (hi - lo) * sp["per_decade"] + 1
+        Tg = torch.tensor([10.0 ** (lo + i / sp["per_decade"]) for i in range(n)], dtype=torch.float32,
+                          device=device)
+        e = mpr_reference_curve3d(Tg, L=sp["L"], n_therm=sp["n_therm"], n_meas=sp["n_meas"], seed=sp["seed"], q=q)
         _curve_cache[key] = (Tg.to(torch.float64), e)
     return _curve_cache[key]
 
@@ -90,3 +111,25 @@ def predict(z: torch.Tensor, mask: torch.Tensor, block=(32, 32), n_real: int = 1
     sim = mpr_simulate(t, mask, T_blocks, lb_h, lb_w, cfg)
     zhat = mpr_predict(sim.acc, z, mask, n_real * n_samp, rng)
     return Prediction(zhat=zhat, T=T_blocks, sim=sim, range=rng)
+
+
+def predict3d(z: torch.Tensor, mask: torch.Tensor, block=(32, 32, 32), n_real: int = 100, *, q: float = 0.5,
+              J: float = 1.0, init_mode: int = INIT_BLOCK_MEAN, stop_mode: int = STOP_AUTO, n_eq: int = 50,
+              n_samp: int = 1, n_fit: int = 20, n_f: int = 5, n_max: int = 1000, seed: int = 0, scene_id: int = 0,
+              curve=None, T_blocks: torch.Tensor | None = None) -> Prediction:
+    """Fill the gaps (mask == 0) of a [D, H, W] grid on the 3D lattice (the extension to three dimensions named in
+    Sec. 4): the Sec. 2.1 map over the whole grid, temperatures per lb_d x lb_h x lb_w block from the cubic lattice's
+    matching curve, the conditional simulation and the conditional mean.  The map, the prediction and their range
+    are those of the plane, applied to the flattened grid."""
+    D, H, W = (int(v) for v in z.shape)
+    lb = tuple(int(v) for v in block)
+    t2, rng = mpr_map_angles(z.reshape(D * H, W), mask.reshape(D * H, W))
+    t = t2.view(D, H, W)
+    if T_blocks is None:
+        cT, ce = reference_curve3d(q, z.device) if curve is None else curve
+        T_blocks, _, _ = mpr_calibrate_temperature3d(t, mask, *lb, cT, ce, q, J)
+    cfg = SimConfig(q=q, J=J, n_real=n_real, init_mode=init_mode, stop_mode=stop_mode, n_eq=n_eq, n_samp=n_samp,
+                    n_fit=n_fit, n_f=n_f, n_max=n_max, seed=seed, scene_id=scene_id)
+    sim = mpr_simulate3d(t, mask, T_blocks, *lb, cfg)
+    zhat = mpr_predict(sim.acc.view(D * H, W), z.reshape(D * H, W), mask.reshape(D * H, W), n_real * n_samp, rng)
+    return Prediction(zhat=zhat.view(D, H, W), T=T_blocks, sim=sim, range=rng)

@@ -206,3 +206,32 @@ def test_fullsize_3d_sampled_realizations():
         print(f"3D realization {r}: state agreement {frac:.7f}", flush=True)
         assert frac >= 0.9999
         assert abs(e0 - o.energy[0]) <= 1e-5
+
+
+def test_predict3d_matches_the_oracle_pipeline():
+    """predict3d (map, 3D calibration, simulation, conditional mean) against the oracle's steps on the same inputs:
+    temperatures equal or one ulp apart, and, on the GPU's temperatures, the same stopping sweep and prediction bit
+    for bit."""
+    import paper_2212_01317_amd as P
+    D, H, W, lb = 10, 12, 14, (5, 6, 7)
+    rng = np.random.default_rng(31)
+    z = (rng.standard_normal((D, H, W)) * 3 + 10).astype(np.float32)
+    m = (rng.random((D, H, W)) >= 0.5).astype(np.uint8)
+    zi = z.copy()
+    zi[m == 0] = np.nan
+    Tc = np.geomspace(1e-3, 1e2, 21).astype(np.float32)
+    ec = oracle.reference_curve3(Tc, L=8, n_therm=30, n_meas=40, seed=3)
+    cT, ce = Tc.astype(np.float64), ec
+    pr = P.predict3d(dev(zi), dev(m), block=lb, n_real=64, stop_mode=M.STOP_AUTO, n_fit=6, n_f=3, n_max=60, n_samp=2,
+                     seed=11, curve=(dev(cT), dev(ce)))
+    t2, rg = oracle.map_angles(zi.reshape(D * H, W), m.reshape(D * H, W))
+    t = t2.reshape(D, H, W)
+    To, _, _ = oracle.calibrate_temperature3(t, m, *lb, cT, ce)
+    Tg = host(pr.T)
+    d = np.abs(Tg.ravel().view(np.int32).astype(np.int64) - np.asarray(To, np.float32).ravel().view(np.int32))
+    assert np.all(d <= 1)                       # the block sums are FP64 in another order: equal or one ulp apart
+    o = oracle.simulate3(t, m, Tg, *lb, OCfg(n_real=64, init_mode=1, stop_mode=1, n_fit=6, n_f=3, n_max=60,
+                                                 n_samp=2, seed=11))
+    assert pr.sim.sweeps == o.k_star
+    zo = oracle.predict(o.acc.reshape(D * H, W), zi.reshape(D * H, W), m.reshape(D * H, W), 128, rg)
+    assert np.array_equal(host(pr.zhat).reshape(D * H, W), zo)
