@@ -258,7 +258,7 @@ def grf3(D: int, H: int, W: int, xi: float, rng: np.random.Generator) -> np.ndar
     r = np.sqrt(ds[0][:, None, None] ** 2 + ds[1][None, :, None] ** 2 + ds[2][None, None, :] ** 2)
     lam = np.clip(np.fft.rfftn(np.exp(-r / xi)).real, 0.0, None)
     del r
-    f = np.fft.irfftn(np.sqrt(lam) * np.fft.rfftn(rng.standard_normal((D, H, W))), s=(D, H, W))
+    f = np.fft.irfftn(np.sqrt(lam) * np.fft.rfftn(rng.standard_normal((D, H, W))), s=(D, H, W), axes=(0, 1, 2))
     return ((f - f.mean()) / max(f.std(), 1e-300)).astype(np.float32)
 
 
