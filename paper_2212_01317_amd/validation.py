@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import dataclasses
 import json
+import sys
 import time
 from dataclasses import dataclass
 
@@ -46,12 +47,15 @@ class Setting:
     stop_mode: int = STOP_AUTO  # STOP_AUTO: the test on the realization-averaged energy; STOP_AUTO_CHAIN: per chain
 
 
-def masks_for(H: int, W: int, p: float, M: int, seed: int):
-    """M masks (1 = sample) removing round(p H W) pixels uniformly; mask m depends only on (seed, p, m)."""
+def masks_for(H: int, W: int, p: float, M: int, seed: int, progress=None):
+    """M masks (1 = sample) removing round(p H W) pixels uniformly; mask m depends only on (seed, p, m).
+    progress(m), if given, is called after each mask (large grids take seconds per mask)."""
     out = []
     for m in range(M):
         rng = np.random.default_rng([seed, int(round(p * 1000)), m])
         out.append(synth.uniform_mask(H, W, int(round(p * H * W)), rng))
+        if progress is not None:
+            progress(m)
     return out
 
 
@@ -99,7 +103,10 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
     curve = reference_curve(0.5, dev)
     rows = []
     for p in ps:
-        masks = masks_for(H, W, float(p), M, s0.seed)
+        big = H * W >= (1 << 24)
+        masks = masks_for(H, W, float(p), M, s0.seed,
+                          progress=(lambda m: print(f"[validation] p={p}: mask {m + 1}/{M}", file=sys.stderr,
+                                                    flush=True)) if big else None)
         for method, s in variants(methods, s0, blocks, ns):
             aae, rase, times, sweeps, kst = [], [], [], [], []
             for m, mk in enumerate(masks):
