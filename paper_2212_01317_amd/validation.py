@@ -123,6 +123,8 @@ def run(field: np.ndarray, ps, M: int, methods=METHODS, setting: Setting | None 
                 rase.append(float(e[1]))
                 sweeps.append(pr.sim.sweeps + s.n_samp)
                 kst.append(pr.sim.sweeps)
+                if big and (m + 1) % 10 == 0:
+                    print(f"[validation] p={p} {method}: {m + 1}/{M} predictions", file=sys.stderr, flush=True)
             rows.append(dict(p=float(p), method=method, block=None if method == "MPR" else s.block,
                              n_s=s.n_s if method == "SST" else None, MAAE=float(np.mean(aae)), MRASE=float(np.mean(rase)),
                              t_ms=1e3 * float(np.mean(times)), sweeps=float(np.mean(sweeps)),
