@@ -85,8 +85,9 @@ typedef struct {
                              the same chains bit for bit.  MPR_SWEEP_TILES (1): tiles of sites in LDS, lanes =
                              sites; MPR_SWEEP_LANES (2): state with the realization innermost, lanes = 64
                              realizations of one site (sides below 65536); MPR_SWEEP_AUTO (0, zero-initialised):
-                             LANES when R >= 64 and the grid gives at least 2048 waves, else TILES.  mpr_sweep and
-                             the batched form use TILES. */
+                             LANES when R >= 64 and the grid gives at least 2048 waves, else TILES.  mpr_sweep uses
+                             TILES; the batched form uses LANES for every scene when R >= 64 (or LANES is asked
+                             for) and its scenes share one temperature-lookup form, else TILES. */
     int32_t coupling;     /* MPR_COUPLING_ISOTROPIC (0, zero-initialised): one temperature per block.
                              MPR_COUPLING_DIRECTIONAL (1): the directional exchange interaction suggested in Sec. 4,
                              kept local to blocks: T_blocks[2*B] holds Tx of every block (its horizontal bonds) and
@@ -237,18 +238,20 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
 /* Batched simulation (a project addition): many scenes of different sizes and gap fractions, each with n_real
  * realizations.  Each scene follows exactly the arithmetic of mpr_simulate with cfg->scene_id replaced by its own
  * scene_id (its own stopping test and sampling sweeps), so its results are bit-identical to a single-scene call.
- * Scenes for which mpr_simulate would take the realization-lane sweep (cfg->sweep_kernel AUTO with n_real >= 64 and
- * a grid that fills the device, or LANES) are run one after the other as such calls; the others are advanced
- * together by one persistent sweep kernel per sweep that takes (scene, tile, realization chunk) work items from a
- * device work queue, largest scenes first (cfg->sweep_kernel = TILES sends every scene there).  Their sweeps are
- * replayed from a HIP graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph
- * replay.  tile_h: 16 or 32 (tile height of that kernel; results do not depend on it), or 0 to time one sweep with
- * each and keep the faster (*tile_h_used_out reports the choice, 0 when no scene ran on it).
+ * All scenes are advanced together by one persistent sweep kernel per sweep that takes work items from device work
+ * queues, largest scenes first: with n_real >= 64 (cfg->sweep_kernel AUTO or LANES; or any n_real with LANES), the
+ * realization-lane sweep over (scene, realization group, band, row segment) items from eight queues, one per XCD,
+ * provided every scene's sides are below 65536 and all scenes share one temperature-lookup form (their lb_w all
+ * multiples of the 12-column band, all at least 15 wide, or all otherwise); else (or with TILES) the tile sweep over
+ * (scene, tile, realization chunk) items.  The sweeps, energies, stopping tests and sampling are replayed from a HIP
+ * graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph replay.  The
+ * per-chain stopping test (MPR_STOP_AUTO_CHAIN) is refused (MPR_ERR_INVALID_ARG).  tile_h: 16 or 32 (tile height of
+ * the tile sweep; results do not depend on it), or 0 to time one sweep with each and keep the faster
+ * (*tile_h_used_out reports the choice, 0 when the lane sweep ran).
  * sweeps_done_out[n_scenes] (host, optional): k* per scene; converged_out[n_scenes] (host, optional): 1 where the scene
  * met the equilibrium test (or ran FIXED), 0 where AUTO reached n_max without it (the call then returns
- * MPR_WARN_NOT_CONVERGED).  Workspace: mpr_simulate_batched_workspace_bytes (for the
- * persistent batch a second state buffer per scene plus small per-scene arrays; the largest single-scene workspace
- * of the other scenes; the same memory serves both). */
+ * MPR_WARN_NOT_CONVERGED).  Workspace: mpr_simulate_batched_workspace_bytes (lane sweep: two lane buffers per
+ * scene plus small per-scene arrays; tile sweep: a second state buffer per scene plus small per-scene arrays). */
 typedef struct {
     int64_t H, W;             /* grid of this scene */
     int32_t lb_h, lb_w;       /* its temperature blocks */
