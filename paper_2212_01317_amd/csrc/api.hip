@@ -1460,19 +1460,22 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         ia.key0 = key0;
         ia.key1 = key1;
         ia.mode = c.init_mode;
-        const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
-        MPR_HIP(mpr::launch_rl_init(ia, rg.Rp, w.buf0[i], w.buf1[i], s));    // the start straight into both lane buffers
+        // (the start goes through the [R][H][W] state here: with many small scenes the per-site kernels of the
+        // plane layout keep more of the device busy than the lane-layout start, which is written for large grids)
+        MPR_HIP(mpr::launch_init(ia, s));
         MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
         const int64_t HW = sc.H * sc.W;
         const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
         const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
-            MPR_HIP(mpr::launch_rl_energy_full(w.buf0[i], sc.H, sc.W, R, c.q, w.epart[i], nfull, s));
+            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
             MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
         }
         if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, s));
         MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], s));
+        MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], s));
+        const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
         mpr::BatchLaneScene& d = hs[i];
         mpr::RlArgs& ra = d.a;
         ra = mpr::RlArgs{};
