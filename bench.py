@@ -138,9 +138,13 @@ def parse():
     ap.add_argument("--other-p-steps", type=int, default=2)
     ap.add_argument("--profile-sweeps", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and gradient measurements")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched 256-scene measurement (for kernel traces of the batched sweep)")
     ap.add_argument("--lattice3d-only", action="store_true",
                     help="run only the 3D-lattice leg and print its object (for profiling its kernels)")
     ap.add_argument("--batch-scenes", type=int, default=256)
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes generating the batched scenes (1: in this process, e.g. under a profiler)")
     ap.add_argument("--sweep-kernel", choices=("auto", "tiles", "lanes"), default="auto",
                     help="sweep kernel of the simulation (auto: the library's choice)")
     return ap.parse_args()
@@ -264,10 +268,10 @@ def main():
     log(f"[bench] workload generated in {time.time() - t0:.1f}s: {L}x{L}, p={args.p}, gaps={int((sc.mask == 0).sum())}")
     extras_inputs = None
     other_p = [float(x) for x in args.other_p.split(",") if x.strip()] if args.profile_sweeps == 0 else []
-    if not args.no_extras and args.profile_sweeps == 0 and not args.lattice3d_only:
+    if (not args.no_extras or args.batched_only) and args.profile_sweeps == 0 and not args.lattice3d_only:
         # generated before the GPU is touched (worker processes are started from a process without a GPU context)
         t0 = time.time()
-        scenes4 = synth.config4_scenes(args.batch_scenes, workers=min(16, os.cpu_count() or 1))
+        scenes4 = synth.config4_scenes(args.batch_scenes, workers=max(1, min(args.gen_workers, os.cpu_count() or 1)))
         sc5 = synth.config5()
         extras_inputs = (scenes4, sc5)
         log(f"[bench] batched and gradient workloads generated in {time.time() - t0:.1f}s")
@@ -275,6 +279,12 @@ def main():
     dev = torch.device("cuda", 0)
     if args.lattice3d_only:
         print(json.dumps({"lattice3d": bench_lattice3d(dev, R, float("nan"), L * L)}), flush=True)
+        return
+    if args.batched_only:
+        cT, ce = mpr.reference_curve(0.5, dev)
+        rates, _ = mpr.mpr_probe_instruction_rates(dev)
+        a_upd, a_site, _ = algorithmic_costs(rates)
+        print(json.dumps({"batched": bench_batched(extras_inputs[0], cT, ce, dev, a_upd, a_site)}), flush=True)
         return
     state = torch.empty((R, L, L), dtype=torch.float32, device=dev)
     kchoice = {"auto": mpr.SWEEP_AUTO, "tiles": mpr.SWEEP_TILES, "lanes": mpr.SWEEP_LANES}[args.sweep_kernel]
@@ -345,7 +355,8 @@ def main():
         torch.cuda.empty_cache()
         out["lattice3d"] = bench_lattice3d(dev, R, head["roofline"]["launch_ms"], L * L)
         torch.cuda.empty_cache()
-        out["batched"] = bench_batched(extras_inputs[0], cT, ce, dev)
+        out["batched"] = bench_batched(extras_inputs[0], cT, ce, dev, head["roofline"]["a_update"],
+                                       head["roofline"]["a_site"])
         torch.cuda.empty_cache()
         out["gradient"] = bench_gradient(extras_inputs[1], cT, ce, dev)
     if not args.no_cpu_baseline:
@@ -483,9 +494,12 @@ def bench_lattice3d(dev, R, plane_sweep_ms, plane_sites):
             "mean_T": float(T.double().mean())}
 
 
-def bench_batched(scenes, cT, ce, dev):
+def bench_batched(scenes, cT, ce, dev, a_upd, a_site):
     """Config 4: 256 scenes of uneven size and gap fraction, 64 realizations each, automatic stopping, in one
-    batched call; then the same scenes through one single-scene call each (bit-identical results, so equal MAE)."""
+    batched call; then the same scenes through one single-scene call each (bit-identical results, so equal MAE).
+    The ALU fraction of each is the sweeps' lane-operations (A_update per update, A_site per site and sweep, priced
+    as for the headline kernel) over the whole call's time: a lower bound on the sweep kernel's own fraction, since
+    the call also holds the per-sweep energy, test and sampling kernels and the host's reads between chunks."""
     import numpy as np
     import torch
 
@@ -507,6 +521,8 @@ def bench_batched(scenes, cT, ce, dev):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     upd = sum(R * g * (o.sweeps + cfg.n_samp) for g, o in zip(gaps, b.outputs))
+    ops = sum(R * (o.sweeps + cfg.n_samp) * (g * a_upd + sc.z_true.size * a_site)
+              for g, o, sc in zip(gaps, b.outputs, scenes))
     maes = []
     for it, o in zip(items, b.outputs):
         zh = mpr.mpr_predict(o.acc, it["z"], it["mask"], R, it["rng"])
@@ -532,7 +548,10 @@ def bench_batched(scenes, cT, ce, dev):
                         f"16x16 T-blocks, {R} realizations each, automatic stopping, 1 sampling sweep",
             "sites": sites, "updates": upd, "seconds": t_batch, "updates_per_s": upd / t_batch,
             "single_scene_seconds": t_single, "single_scene_updates_per_s": upd / t_single,
-            "speedup_vs_single_scene": t_single / t_batch, "mean_validation_mae": float(np.mean(maes)),
+            "speedup_vs_single_scene": t_single / t_batch,
+            "alu_frac_of_call": ops / t_batch / PEAK_LANE_OPS,
+            "alu_frac_of_call_single_scene": ops / t_single / PEAK_LANE_OPS,
+            "mean_validation_mae": float(np.mean(maes)),
             "mean_validation_mae_single_scene": float(np.mean(maes1)),
             "max_abs_mae_difference_vs_single_scene": float(np.max(np.abs(np.array(maes) - np.array(maes1))))}
 

@@ -606,8 +606,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
         const uint32_t per_group = (uint32_t)a.nbands * (uint32_t)a.nseg;
         const uint32_t rg = local / per_group, rest = local % per_group;
         const int64_t group = (int64_t)rg * ((int64_t)a.H * a.W * 256);
-        RlWave<kRlBand, TM, ENERGY, false> w{a, d.cells, d.tb, reinterpret_cast<const char*>(d.buf[(k - 1) & 1]) + group,
-                                             reinterpret_cast<char*>(d.buf[k & 1]) + group};
+        // sweep k reads buf[(k - 1) & 1] and writes buf[k & 1], chosen by a select: an index into the descriptor's
+        // array would place the whole descriptor in scratch memory
+        const bool odd = (k & 1) != 0;
+        float* const src = odd ? d.buf[0] : d.buf[1];
+        float* const dst = odd ? d.buf[1] : d.buf[0];
+        RlWave<kRlBand, TM, ENERGY, false> w{a, d.cells, d.tb, reinterpret_cast<const char*>(src) + group,
+                                             reinterpret_cast<char*>(dst) + group};
         w.sang = sang;
         w.band = (int)(rest % (uint32_t)a.nbands);
         const int seg = (int)(rest / (uint32_t)a.nbands);
