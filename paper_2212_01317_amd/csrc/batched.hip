@@ -125,24 +125,95 @@ __global__ __launch_bounds__(256) void k_batch_energy_mean(const BatchScene* sce
     d.series[ctl->k] = sum / (double)c.R;
 }
 
+// The sampling scenes of this sweep, for every workgroup of a grid that shares out their sites: the scenes are listed
+// 256 at a time from one coalesced read of their phases, and body(s) runs for each listed scene.  (One workgroup per
+// (share, scene) instead left almost all workgroups without work: only the few scenes that have just equilibrated
+// sample in a given sweep.)  A workgroup of 256 threads; the order of the list does not matter, since each site of
+// a scene is summed by one thread.
+template <class Body>
+__device__ __forceinline__ void for_sampling_scenes(const BatchRun* runs, int n_scenes, Body body)
+{
+    __shared__ int list[256];
+    __shared__ int cnt;
+    for (int i0 = 0; i0 < n_scenes; i0 += 256) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        const int i = i0 + (int)threadIdx.x;
+        if (i < n_scenes && runs[i].phase == 1) list[atomicAdd(&cnt, 1)] = i;
+        __syncthreads();
+        const int m = cnt;
+        for (int j = 0; j < m; ++j) body(list[j]);
+        __syncthreads();   // the list and its count are rewritten for the next 256 scenes
+    }
+}
+
+// The work list of the scenes still running (one workgroup of 256 threads, after the phase transitions):
+// prefix[i] = the work of the running scenes among order[0 .. i), prefix[n_scenes] the total, *n_active their
+// number.  An exclusive scan over 256 scenes at a time: wave scans by shuffles, then the four wave totals.
+template <class WorkOf>
+__device__ __forceinline__ void running_work_prefix(const BatchRun* runs, const int* order, int64_t* prefix,
+                                                    int n_scenes, int* n_active, WorkOf work_of)
+{
+    __shared__ long long wsum[4];
+    __shared__ int wcnt[4];
+    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    long long base = 0;
+    int active = 0;
+    for (int i0 = 0; i0 < n_scenes; i0 += 256) {
+        const int i = i0 + (int)threadIdx.x;
+        long long w = 0;
+        bool running = false;
+        if (i < n_scenes) {
+            const int s = order[i];
+            if (runs[s].phase < 2) {
+                w = (long long)work_of(s);
+                running = true;
+            }
+        }
+        long long x = w;                    // inclusive scan of w within the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        const int nrun = __popcll(__ballot(running));
+        if (lane == 63) {
+            wsum[wv] = x;
+            wcnt[wv] = nrun;
+        }
+        __syncthreads();
+        long long before = 0;
+        for (int j = 0; j < wv; ++j) before += wsum[j];
+        if (i < n_scenes) prefix[i] = base + before + (x - w);
+        base += ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+        active += ((wcnt[0] + wcnt[1]) + wcnt[2]) + wcnt[3];
+        __syncthreads();                    // the wave totals are rewritten for the next 256 scenes
+    }
+    if (threadIdx.x == 0) {
+        prefix[n_scenes] = base;
+        *n_active = active;
+    }
+}
+
 // Sampling scenes: acc += sum over realizations (in order) of the state after this sweep.
 __global__ __launch_bounds__(256) void k_batch_accumulate(const BatchScene* scenes, const BatchRun* runs,
-                                                           const BatchCtl* ctl, BatchCfg c)
+                                                           const BatchCtl* ctl, BatchCfg c, int n_scenes)
 {
-    const int s = blockIdx.y;
-    const BatchRun run = runs[s];
-    if (run.phase != 1) return;
-    const BatchScene& d = scenes[s];
-    const float* st = d.buf[ctl->k & 1];
-    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
-        if (d.mask[n]) {
-            if (run.samp == 0) d.acc[n] = 0.0;
-            continue;
+    const int k = ctl->k;
+    for_sampling_scenes(runs, n_scenes, [&](int s) {
+        const BatchRun run = runs[s];
+        const BatchScene& d = scenes[s];
+        const float* st = d.buf[k & 1];
+        for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
+            if (d.mask[n]) {
+                if (run.samp == 0) d.acc[n] = 0.0;
+                continue;
+            }
+            double acc = run.samp == 0 ? 0.0 : d.acc[n];
+            for (int r = 0; r < c.R; ++r) acc += (double)st[(int64_t)r * d.HW + n];
+            d.acc[n] = acc;
         }
-        double acc = run.samp == 0 ? 0.0 : d.acc[n];
-        for (int r = 0; r < c.R; ++r) acc += (double)st[(int64_t)r * d.HW + n];
-        d.acc[n] = acc;
-    }
+    });
 }
 
 // Sec. 3.4 test on the device (same reading as the single-scene driver): OLS slope of the last n_fit energies,
@@ -199,20 +270,8 @@ __global__ __launch_bounds__(256) void k_batch_phase(const BatchScene* scenes, B
         runs[s] = run;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        int active = 0;
-        for (int i = 0; i < n_scenes; ++i) {
-            prefix[i] = acc;
-            const int s = order[i];
-            if (runs[s].phase < 2) {
-                acc += (int64_t)scenes[s].ntiles[variant] * scenes[s].nchunks[variant];
-                ++active;
-            }
-        }
-        prefix[n_scenes] = acc;
-        ctl->n_active = active;
-    }
+    running_work_prefix(runs, order, prefix, n_scenes, &ctl->n_active,
+                        [&](int s) { return (int64_t)scenes[s].ntiles[variant] * scenes[s].nchunks[variant]; });
 }
 
 hipError_t launch_batch_sweep(const BatchDev& b, int variant, int grid, hipStream_t s)
@@ -242,7 +301,7 @@ hipError_t launch_batch_step(const BatchDev& b, int variant, int next_variant, i
                            b.cfg, b.n);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_batch_accumulate, dim3(acc_blocks, b.n), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg);
+    hipLaunchKernelGGL(k_batch_accumulate, dim3(acc_blocks), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg, b.n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.ctl, b.cfg,
                        b.n, next_variant);
@@ -290,22 +349,23 @@ __global__ __launch_bounds__(256) void k_batchl_energy_mean(const BatchLaneScene
 
 // Sampling scenes: acc += sum over realizations (in order) of the state after this sweep (lane layout).
 __global__ __launch_bounds__(256) void k_batchl_accumulate(const BatchLaneScene* scenes, const BatchRun* runs,
-                                                            const BatchLaneCtl* ctl, int R)
+                                                            const BatchLaneCtl* ctl, int R, int n_scenes)
 {
-    const int s = blockIdx.y;
-    const BatchRun run = runs[s];
-    if (run.phase != 1) return;
-    const BatchLaneScene& d = scenes[s];
-    const float* st = d.buf[ctl->k & 1];
-    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
-        if (d.mask[n]) {
-            if (run.samp == 0) d.acc[n] = 0.0;
-            continue;
+    const int k = ctl->k;
+    for_sampling_scenes(runs, n_scenes, [&](int s) {
+        const BatchRun run = runs[s];
+        const BatchLaneScene& d = scenes[s];
+        const float* st = d.buf[k & 1];
+        for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < d.HW; n += (int64_t)gridDim.x * 256) {
+            if (d.mask[n]) {
+                if (run.samp == 0) d.acc[n] = 0.0;
+                continue;
+            }
+            double acc = run.samp == 0 ? 0.0 : d.acc[n];
+            for (int r = 0; r < R; ++r) acc += (double)st[((int64_t)(r >> 6) * d.HW + n) * 64 + (r & 63)];
+            d.acc[n] = acc;
         }
-        double acc = run.samp == 0 ? 0.0 : d.acc[n];
-        for (int r = 0; r < R; ++r) acc += (double)st[((int64_t)(r >> 6) * d.HW + n) * 64 + (r & 63)];
-        d.acc[n] = acc;
-    }
+    });
 }
 
 // Phase transitions after sweep k (the test of the single-scene driver), then the work list of the scenes still
@@ -339,20 +399,7 @@ __global__ __launch_bounds__(256) void k_batchl_phase(const BatchLaneScene* scen
         runs[s] = run;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        int active = 0;
-        for (int i = 0; i < n_scenes; ++i) {
-            prefix[i] = acc;
-            const int s = order[i];
-            if (runs[s].phase < 2) {
-                acc += scenes[s].work;
-                ++active;
-            }
-        }
-        prefix[n_scenes] = acc;
-        ctl->n_active = active;
-    }
+    running_work_prefix(runs, order, prefix, n_scenes, &ctl->n_active, [&](int s) { return scenes[s].work; });
 }
 
 hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, hipStream_t s)
@@ -368,7 +415,7 @@ hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, h
                            b.cfg.R, b.n);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_batchl_accumulate, dim3(acc_blocks, b.n), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg.R);
+    hipLaunchKernelGGL(k_batchl_accumulate, dim3(acc_blocks), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg.R, b.n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batchl_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.ctl, b.cfg,
                        b.n);
