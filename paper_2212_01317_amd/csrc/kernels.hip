@@ -391,16 +391,26 @@ hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, 
     return hipGetLastError();
 }
 
-__global__ void k_global_mean(const double* Ts, const int* No, int64_t B, float* gmean)
+// One wave: the block sums are read 64 at a time (one coalesced load per lane) and added in block order through lane
+// broadcasts, one sequential FP64 sum with the rounding of a loop over the blocks (a loop of single loads waited for
+// each load in turn).
+__global__ __launch_bounds__(64) void k_global_mean(const double* Ts, const int* No, int64_t B, float* gmean)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    const int lane = (int)threadIdx.x;
     double sum = 0.0;
     long long cnt = 0;
-    for (int64_t b = 0; b < B; ++b) {
-        sum += Ts[b];
-        cnt += No[b];
+    for (int64_t b0 = 0; b0 < B; b0 += 64) {
+        const int64_t b = b0 + lane;
+        const double t = b < B ? Ts[b] : 0.0;
+        const int n = b < B ? No[b] : 0;
+        const int m = B - b0 < 64 ? (int)(B - b0) : 64;
+        for (int j = 0; j < m; ++j) {
+            sum += __shfl(t, j, 64);
+            cnt += __shfl(n, j, 64);
+        }
     }
-    *gmean = cnt > 0 ? (float)(sum / (double)cnt) : 0.0f;
+    if (lane == 0) *gmean = cnt > 0 ? (float)(sum / (double)cnt) : 0.0f;
 }
 
 hipError_t launch_global_mean(const double* Ts, const int* No, int64_t B, float* gmean, hipStream_t s)
