@@ -501,16 +501,20 @@ size_t batch_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg,
 }
 
 // The lane batch: per scene its temperature table, window bits, two lane-layout state buffers and reductions.
+// The scenes' starts run on kSetupLanes streams (the caller's and three private ones), each with its own scratch for
+// the block means: with many small scenes one stream leaves the device mostly idle between their short launches.
+constexpr int kSetupLanes = 4;
+
 struct BatchLaneWs {
     mpr::BatchLaneScene* scenes;
     mpr::BatchRun* runs;
     int* order;
     int64_t* prefix;
     mpr::BatchLaneCtl* ctl;
-    StatsWs st;
-    double* Ts;
-    int* No;
-    float* gmean;
+    StatsWs st[kSetupLanes];
+    double* Ts[kSetupLanes];
+    int* No[kSetupLanes];
+    float* gmean[kSetupLanes];
     std::vector<mpr::TBand*> tp;
     std::vector<uint2*> cells;
     std::vector<float*> buf0, buf1;
@@ -533,13 +537,15 @@ size_t batchl_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg
         max_np = std::max<int64_t>(max_np, g.B() * g.nchunk);
         max_B = std::max<int64_t>(max_B, g.B());
     }
-    x.st.pS = c.take<double>(max_np);
-    x.st.pTs = c.take<double>(max_np);
-    x.st.pN = c.take<int>(max_np);
-    x.st.pNo = c.take<int>(max_np);
-    x.Ts = c.take<double>(max_B);
-    x.No = c.take<int>(max_B);
-    x.gmean = c.take<float>(1);
+    for (int j = 0; j < kSetupLanes; ++j) {
+        x.st[j].pS = c.take<double>(max_np);
+        x.st[j].pTs = c.take<double>(max_np);
+        x.st[j].pN = c.take<int>(max_np);
+        x.st[j].pNo = c.take<int>(max_np);
+        x.Ts[j] = c.take<double>(max_B);
+        x.No[j] = c.take<int>(max_B);
+        x.gmean[j] = c.take<float>(1);
+    }
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     for (int i = 0; i < n; ++i) {
         const int64_t H = sc[i].H, W = sc[i].W;
@@ -556,6 +562,27 @@ size_t batchl_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg
     if (w) *w = std::move(x);
     return c.used;
 }
+
+// private streams of the batched starts (default priority, created once per thread and device)
+hipStream_t setup_stream(int j)
+{
+    static thread_local hipStream_t ss[kMaxDevices][kSetupLanes - 1] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    hipStream_t& st = ss[dev][j];
+    if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    return st;
+}
+
+// events of one fork of the caller's stream into the setup streams and of their join, released on every return
+struct SetupFork {
+    hipEvent_t ev[kSetupLanes] = {};
+    ~SetupFork()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
 
 // private stream used only to capture graphs (graphs are launched on the caller's stream)
 hipStream_t capture_stream()
@@ -1433,22 +1460,35 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
 
     std::vector<mpr::BatchLaneScene> hs(n_scenes);
     std::vector<int64_t> work(n_scenes);
+    // fork: the setup streams start after the work the caller queued on its stream (the scenes' inputs)
+    SetupFork fork;
+    hipStream_t lane_stream[kSetupLanes] = {s};
+    MPR_HIP(hipEventCreateWithFlags(&fork.ev[0], hipEventDisableTiming));
+    MPR_HIP(hipEventRecord(fork.ev[0], s));
+    for (int j = 1; j < kSetupLanes; ++j) {
+        lane_stream[j] = setup_stream(j - 1);
+        if (!lane_stream[j]) return fail(MPR_ERR_HIP, "could not create a setup stream");
+        MPR_HIP(hipStreamWaitEvent(lane_stream[j], fork.ev[0], 0));
+    }
     for (int i = 0; i < n_scenes; ++i) {
         const mpr_scene& sc = scenes[i];
+        const int lane = i % kSetupLanes;
+        hipStream_t ss = lane_stream[lane];
         mpr::StatsGeom g = mpr::stats_geom(sc.H, sc.W, sc.lb_h, sc.lb_w);
         if (c.init_mode == MPR_INIT_BLOCK_MEAN) {
-            MPR_HIP(mpr::launch_block_stats(sc.t, sc.mask, g, 2.0 * mpr::kPi * (double)c.q, (double)c.J, w.st.pS,
-                                            w.st.pN, w.st.pTs, w.st.pNo, nullptr, nullptr, w.Ts, w.No, s));
-            MPR_HIP(mpr::launch_global_mean(w.Ts, w.No, g.B(), w.gmean, s));
+            const StatsWs& st = w.st[lane];
+            MPR_HIP(mpr::launch_block_stats(sc.t, sc.mask, g, 2.0 * mpr::kPi * (double)c.q, (double)c.J, st.pS,
+                                            st.pN, st.pTs, st.pNo, nullptr, nullptr, w.Ts[lane], w.No[lane], ss));
+            MPR_HIP(mpr::launch_global_mean(w.Ts[lane], w.No[lane], g.B(), w.gmean[lane], ss));
         }
         mpr::InitArgs ia;
         ia.state = sc.state;
         ia.state2 = nullptr;
         ia.t = sc.t;
         ia.mask = sc.mask;
-        ia.Ts = w.Ts;
-        ia.No = w.No;
-        ia.gmean = w.gmean;
+        ia.Ts = w.Ts[lane];
+        ia.No = w.No[lane];
+        ia.gmean = w.gmean[lane];
         ia.H = sc.H;
         ia.W = sc.W;
         ia.lb_h = sc.lb_h;
@@ -1462,19 +1502,19 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         ia.mode = c.init_mode;
         // (the start goes through the [R][H][W] state here: with many small scenes the per-site kernels of the
         // plane layout keep more of the device busy than the lane-layout start, which is written for large grids)
-        MPR_HIP(mpr::launch_init(ia, s));
-        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], s));
+        MPR_HIP(mpr::launch_init(ia, ss));
+        MPR_HIP(mpr::launch_tpairs(sc.T_blocks, g.B(), c.J, mpr::kDeltaE * c.J, w.tp[i], ss));
         const int64_t HW = sc.H * sc.W;
         const int64_t nbonds = sc.H * (sc.W - 1) + sc.W * (sc.H - 1);
         const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
-            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
-            MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
+            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, ss));
+            MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], ss));
         }
-        if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, s));
-        MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], s));
-        MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], s));
+        if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, ss));
+        MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], ss));
+        MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], ss));
         const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
         mpr::BatchLaneScene& d = hs[i];
         mpr::RlArgs& ra = d.a;
@@ -1517,6 +1557,12 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         d.nparts = rg.nbands * rg.nseg;
         d.inv_norm = inv_norm;
         work[i] = rg.n_items;
+    }
+    // join: the caller's stream waits for the starts queued on the setup streams
+    for (int j = 1; j < kSetupLanes; ++j) {
+        MPR_HIP(hipEventCreateWithFlags(&fork.ev[j], hipEventDisableTiming));
+        MPR_HIP(hipEventRecord(fork.ev[j], lane_stream[j]));
+        MPR_HIP(hipStreamWaitEvent(s, fork.ev[j], 0));
     }
     // largest scenes first
     std::vector<int> order(n_scenes);
