@@ -244,7 +244,10 @@ mpr_status mpr_validate(const float* zhat, const float* truth, const uint8_t* ev
  * provided every scene's sides are below 65536 and all scenes share one temperature-lookup form (their lb_w all
  * multiples of the 12-column band, all at least 15 wide, or all otherwise); else (or with TILES) the tile sweep over
  * (scene, tile, realization chunk) items.  The sweeps, energies, stopping tests and sampling are replayed from a HIP
- * graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph replay.  The
+ * graph captured once per call (n_f sweeps per graph); the stream is synchronised once per graph replay.  On the
+ * lane sweep the scenes' starts are spread over the caller's stream and three private streams of the library
+ * (created once per host thread and device, default priority), forked from the caller's stream and joined back into
+ * it by events, so that the call still begins after and ends before the caller's other work on `stream`.  The
  * per-chain stopping test (MPR_STOP_AUTO_CHAIN) is refused (MPR_ERR_INVALID_ARG).  tile_h: 16 or 32 (tile height of
  * the tile sweep; results do not depend on it), or 0 to time one sweep with each and keep the faster
  * (*tile_h_used_out reports the choice, 0 when the lane sweep ran).
