@@ -391,9 +391,9 @@ hipError_t launch_calibrate(const double* S, const int* N, int64_t B, double J, 
     return hipGetLastError();
 }
 
-// One wave: the block sums are read 64 at a time (one coalesced load per lane) and added in block order through lane
-// broadcasts, one sequential FP64 sum with the rounding of a loop over the blocks (a loop of single loads waited for
-// each load in turn).
+// One wave: the block sums are read 64 at a time (one coalesced load per lane) and added in block order from the
+// lanes' registers (reads of fixed lanes, independent of the sum), one sequential FP64 sum with the rounding of a loop
+// over the blocks (a loop of single loads waited for each load in turn).
 __global__ __launch_bounds__(64) void k_global_mean(const double* Ts, const int* No, int64_t B, float* gmean)
 {
     if (blockIdx.x != 0) return;
@@ -404,10 +404,14 @@ __global__ __launch_bounds__(64) void k_global_mean(const double* Ts, const int*
         const int64_t b = b0 + lane;
         const double t = b < B ? Ts[b] : 0.0;
         const int n = b < B ? No[b] : 0;
+        const int tlo = __double2loint(t), thi = __double2hiint(t);
         const int m = B - b0 < 64 ? (int)(B - b0) : 64;
-        for (int j = 0; j < m; ++j) {
-            sum += __shfl(t, j, 64);
-            cnt += __shfl(n, j, 64);
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            if (j < m) {
+                sum += __hiloint2double(__builtin_amdgcn_readlane(thi, j), __builtin_amdgcn_readlane(tlo, j));
+                cnt += __builtin_amdgcn_readlane(n, j);
+            }
         }
     }
     if (lane == 0) *gmean = cnt > 0 ? (float)(sum / (double)cnt) : 0.0f;
