@@ -584,14 +584,15 @@ struct SetupFork {
     }
 };
 
-// private stream used only to capture graphs (graphs are launched on the caller's stream)
+// private stream used only to capture graphs (graphs are launched on the caller's stream), one per host thread and
+// device
 hipStream_t capture_stream()
 {
-    static thread_local hipStream_t cs = nullptr;
-    if (!cs) {
-        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
-    }
-    return cs;
+    static thread_local hipStream_t cs[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    if (!cs[dev] && hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking) != hipSuccess) cs[dev] = nullptr;
+    return cs[dev];
 }
 
 }  // namespace
@@ -947,7 +948,9 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
     SweepRunner runner(state, w.alt, mask, H, W, w.tp, t_lb(lb_h, c), t_lb(lb_w, c), c, w.epart, w.e_real, s);
     const int nfull = mpr::energy_full_parts(H, W);
     if (need_energy) {
-        if (rl) MPR_HIP(mpr::launch_rl_energy_full(w.rl[0], H, W, R, c.q, w.epart, nfull, s));
+        if (rl)
+            MPR_HIP(mpr::launch_rl_energy_full(w.rl[0], H, W, R, c.q, w.epart, nfull,
+                                               c.init_mode == MPR_INIT_BLOCK_MEAN, s));
         else MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
         MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series, s));
     }

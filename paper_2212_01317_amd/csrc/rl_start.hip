@@ -75,6 +75,14 @@ __global__ __launch_bounds__(256) void k_rl_energy_full(const float* __restrict_
         partial[(int64_t)r * gridDim.x + blockIdx.x] = s_red[0][l] + s_red[1][l] + s_red[2][l] + s_red[3][l];
 }
 
+// rows 1 .. R - 1 of partial[R][nparts] from row 0
+__global__ __launch_bounds__(256) void k_rows_from_first(long long* __restrict__ partial, int nparts, int R)
+{
+    const int64_t n = (int64_t)(R - 1) * nparts;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        partial[nparts + i] = partial[i % nparts];
+}
+
 }  // namespace
 
 hipError_t launch_rl_init(const InitArgs& a, int Rp, float* out0, float* out1, hipStream_t s)
@@ -87,10 +95,16 @@ hipError_t launch_rl_init(const InitArgs& a, int Rp, float* out0, float* out1, h
 }
 
 hipError_t launch_rl_energy_full(const float* lanes, int64_t H, int64_t W, int R, float q, long long* partial,
-                                 int nparts, hipStream_t s)
+                                 int nparts, bool same_start, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rl_energy_full, dim3((unsigned)nparts, (unsigned)((R + 63) / 64)), dim3(256), 0, s, lanes, H,
-                       W, R, q, partial);
+    const unsigned groups = same_start ? 1u : (unsigned)((R + 63) / 64);
+    hipLaunchKernelGGL(k_rl_energy_full, dim3((unsigned)nparts, groups), dim3(256), 0, s, lanes, H, W, R, q, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !same_start || R <= 1) return e;
+    const int64_t n = (int64_t)(R - 1) * nparts;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_rows_from_first, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, partial,
+                       nparts, R);
     return hipGetLastError();
 }
 

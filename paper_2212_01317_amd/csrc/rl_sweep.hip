@@ -706,18 +706,33 @@ __global__ __launch_bounds__(256) void k_rl_from_lanes(const float* __restrict__
 }
 
 // acc[n] += sum over realizations (in order) of the gap angle; the first pass starts from 0.
+// A workgroup sums 64 consecutive sites: per group of 64 realizations its waves read the gap sites' 256-byte
+// realization rows (one coalesced load per site) into an LDS tile, and lane l of the first wave adds site n0 + l's
+// realizations in order r = 0 .. R - 1 (the order of a loop over the realizations).  Sample sites are not read.
 __global__ __launch_bounds__(256) void k_rl_accumulate(const float* __restrict__ S, const uint8_t* __restrict__ mask,
                                                         int64_t HW, int R, int first, double* __restrict__ acc)
 {
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (n >= HW) return;
-    if (mask[n]) {
-        if (first) acc[n] = 0.0;
-        return;
+    __shared__ float tile[64 * 65];                 // [site][realization], rows padded against bank conflicts
+    const int64_t n0 = (int64_t)blockIdx.x * 64;
+    const int wv = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63u);
+    const int64_t ns = n0 + l;
+    const bool mine = wv == 0 && ns < HW;
+    const bool gap = mine && !mask[ns];
+    double v = gap && !first ? acc[ns] : 0.0;
+    for (int g = 0; g * 64 < R; ++g) {
+        for (int j = wv; j < 64; j += 4) {
+            const int64_t n = n0 + j;
+            if (n < HW && !mask[n]) tile[j * 65 + l] = S[((int64_t)g * HW + n) * 64 + l];
+        }
+        __syncthreads();
+        if (gap) {
+            const int m = R - g * 64 < 64 ? R - g * 64 : 64;
+            for (int k = 0; k < m; ++k) v += (double)tile[l * 65 + k];
+        }
+        __syncthreads();
     }
-    double v = first ? 0.0 : acc[n];
-    for (int r = 0; r < R; ++r) v += (double)S[((int64_t)(r >> 6) * HW + n) * 64 + (r & 63)];
-    acc[n] = v;
+    if (gap) acc[ns] = v;
+    else if (mine && first) acc[ns] = 0.0;
 }
 
 }  // namespace
@@ -783,7 +798,7 @@ hipError_t launch_rl_from_lanes(const float* in, int64_t HW, int R, float* out, 
 hipError_t launch_rl_accumulate(const float* S, const uint8_t* mask, int64_t HW, int R, int first, double* acc,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rl_accumulate, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, S, mask, HW, R, first,
+    hipLaunchKernelGGL(k_rl_accumulate, dim3((unsigned)((HW + 63) / 64)), dim3(256), 0, s, S, mask, HW, R, first,
                        acc);
     return hipGetLastError();
 }
