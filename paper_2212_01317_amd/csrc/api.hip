@@ -563,6 +563,17 @@ size_t batchl_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg
     return c.used;
 }
 
+// The energy partials of a start in the [R][H][W] layout: a block-mean start holds the same state in every
+// realization (it has no random part), so realization 0's partials are computed and copied to the others.
+hipError_t start_energy_partials(const float* state, int64_t H, int64_t W, int R, const mpr_sim_config& c,
+                                 long long* partial, int nparts, hipStream_t s)
+{
+    const bool same = c.init_mode == MPR_INIT_BLOCK_MEAN;
+    hipError_t e = mpr::launch_energy_full(state, H, W, same ? 1 : R, c.q, c.J, partial, nparts, s);
+    if (e == hipSuccess && same) e = mpr::launch_rows_from_first(partial, nparts, R, s);
+    return e;
+}
+
 // private streams of the batched starts (default priority, created once per thread and device)
 hipStream_t setup_stream(int j)
 {
@@ -951,7 +962,7 @@ mpr_status mpr_simulate(const float* t, const uint8_t* mask, int64_t H, int64_t 
         if (rl)
             MPR_HIP(mpr::launch_rl_energy_full(w.rl[0], H, W, R, c.q, w.epart, nfull,
                                                c.init_mode == MPR_INIT_BLOCK_MEAN, s));
-        else MPR_HIP(mpr::launch_energy_full(state, H, W, R, c.q, c.J, w.epart, nfull, s));
+        else MPR_HIP(start_energy_partials(state, H, W, R, c, w.epart, nfull, s));
         MPR_HIP(mpr::launch_energy_reduce(w.epart, nfull, R, runner.inv_norm, w.e_real, w.series, s));
     }
     // double checkerboard: in place in `state`, energy of the whole grid after the sweep
@@ -1259,7 +1270,7 @@ static mpr_status batched_tiles(const mpr_scene* scenes, int32_t n_scenes, const
         const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy || sc.energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
-            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, s));
+            MPR_HIP(start_energy_partials(sc.state, sc.H, sc.W, R, c, w.epart[i], nfull, s));
             MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], s));
         }
         if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)(sc.H * sc.W), s));
@@ -1512,7 +1523,7 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         const double inv_norm = nbonds > 0 ? 1.0 / (double)nbonds : 0.0;
         if (energy) {
             const int nfull = mpr::energy_full_parts(sc.H, sc.W);
-            MPR_HIP(mpr::launch_energy_full(sc.state, sc.H, sc.W, R, c.q, c.J, w.epart[i], nfull, ss));
+            MPR_HIP(start_energy_partials(sc.state, sc.H, sc.W, R, c, w.epart[i], nfull, ss));
             MPR_HIP(mpr::launch_energy_reduce(w.epart[i], nfull, R, inv_norm, w.e_real[i], w.series[i], ss));
         }
         if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, ss));

@@ -100,7 +100,13 @@ hipError_t launch_rl_energy_full(const float* lanes, int64_t H, int64_t W, int R
     const unsigned groups = same_start ? 1u : (unsigned)((R + 63) / 64);
     hipLaunchKernelGGL(k_rl_energy_full, dim3((unsigned)nparts, groups), dim3(256), 0, s, lanes, H, W, R, q, partial);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !same_start || R <= 1) return e;
+    if (e != hipSuccess || !same_start) return e;
+    return launch_rows_from_first(partial, nparts, R, s);
+}
+
+hipError_t launch_rows_from_first(long long* partial, int nparts, int R, hipStream_t s)
+{
+    if (R <= 1 || nparts <= 0) return hipSuccess;
     const int64_t n = (int64_t)(R - 1) * nparts;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_rows_from_first, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, partial,

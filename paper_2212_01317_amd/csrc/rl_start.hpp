@@ -15,6 +15,8 @@ namespace mpr {
 hipError_t launch_rl_init(const InitArgs& a, int Rp, float* out0, float* out1, hipStream_t s);
 // the energy partials of k_energy_full (the same per-site terms, so the same integer sums) from a lane buffer:
 // partial[r][part], part < nparts
+// rows 1 .. R - 1 of partial[R][nparts] from row 0: the start energy of a start that every realization shares
+hipError_t launch_rows_from_first(long long* partial, int nparts, int R, hipStream_t s);
 // same_start: every realization holds the same start (the block-mean start has no random part), so the partials of
 // the first group of 64 realizations are computed and realization 0's row is copied to the others
 hipError_t launch_rl_energy_full(const float* lanes, int64_t H, int64_t W, int R, float q, long long* partial,
