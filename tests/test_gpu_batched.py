@@ -150,3 +150,26 @@ def test_batched_matches_oracle(kernel):
         gap = mask == 0
         dphi = 2 * np.pi * np.abs(host(out.acc)[gap] - o.acc[gap]) / R
         assert dphi.size == 0 or dphi.mean() <= 1e-3, i
+
+
+def test_lane_batch_waits_for_inputs_on_the_callers_stream():
+    """The lane batch spreads the scenes' starts over private streams forked from the caller's stream: inputs that a
+    non-default caller stream is still producing (behind a ~20 ms spin kernel) must be complete before any start
+    reads them, so the results equal those of the same call on inputs made ready beforehand."""
+    scenes = _scenes()
+    cfg = M.SimConfig(n_real=64, init_mode=M.INIT_BLOCK_MEAN, stop_mode=M.STOP_AUTO, n_samp=1, n_max=120, seed=91)
+    ref = M.mpr_simulate_batched(scenes, cfg, want_energy=True)
+    assert ref.tile_h == 0
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    print("[batched] lane batch on a side stream behind a spin kernel", flush=True)
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)
+        late = [dict(sc, t=sc["t"].clone(), mask=sc["mask"].clone(), T_blocks=sc["T_blocks"].clone()) for sc in scenes]
+        b = M.mpr_simulate_batched(late, cfg, want_energy=True)
+    torch.cuda.synchronize()
+    for o, r in zip(b.outputs, ref.outputs):
+        assert o.sweeps == r.sweeps
+        assert np.array_equal(host(o.state), host(r.state))
+        assert np.array_equal(host(o.acc), host(r.acc))
+        assert np.array_equal(host(o.energy), host(r.energy))
