@@ -515,6 +515,7 @@ struct BatchLaneWs {
     double* Ts[kSetupLanes];
     int* No[kSetupLanes];
     float* gmean[kSetupLanes];
+    int64_t* gaps;                 // [n] gap sites per scene (the XCD split of the work list)
     std::vector<mpr::TBand*> tp;
     std::vector<uint2*> cells;
     std::vector<float*> buf0, buf1;
@@ -546,6 +547,7 @@ size_t batchl_ws(Carve& c, const mpr_scene* sc, int n, const mpr_sim_config* cfg
         x.No[j] = c.take<int>(max_B);
         x.gmean[j] = c.take<float>(1);
     }
+    x.gaps = c.take<int64_t>(n);
     const int64_t cap = cfg->stop_mode == MPR_STOP_AUTO ? cfg->n_max : cfg->n_eq;
     for (int i = 0; i < n; ++i) {
         const int64_t H = sc[i].H, W = sc[i].W;
@@ -1477,6 +1479,7 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
     // fork: the setup streams start after the work the caller queued on its stream (the scenes' inputs)
     SetupFork fork;
     hipStream_t lane_stream[kSetupLanes] = {s};
+    MPR_HIP(hipMemsetAsync(w.gaps, 0, sizeof(int64_t) * (size_t)n_scenes, s));
     MPR_HIP(hipEventCreateWithFlags(&fork.ev[0], hipEventDisableTiming));
     MPR_HIP(hipEventRecord(fork.ev[0], s));
     for (int j = 1; j < kSetupLanes; ++j) {
@@ -1528,6 +1531,7 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
         }
         if (c.n_samp == 0) MPR_HIP(hipMemsetAsync(sc.acc, 0, sizeof(double) * (size_t)HW, ss));
         MPR_HIP(mpr::launch_rl_cells(sc.mask, sc.H, sc.W, w.cells[i], ss));
+        MPR_HIP(mpr::launch_count_gaps(sc.mask, HW, w.gaps + i, ss));
         MPR_HIP(mpr::launch_rl_to_lanes(sc.state, HW, R, w.buf0[i], w.buf1[i], ss));
         const mpr::RlGeom rg = mpr::rl_geometry_full(sc.H, sc.W, R);
         mpr::BatchLaneScene& d = hs[i];
@@ -1602,6 +1606,7 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
     b.ctl = w.ctl;
     b.n = n_scenes;
     b.tm = mpr::rl_tm(scenes[0].lb_w);
+    b.gaps = w.gaps;
     b.cfg.R = R;
     b.cfg.real_offset = (uint32_t)c.real_offset;
     b.cfg.key0 = key0;
@@ -1624,6 +1629,7 @@ static mpr_status batched_lanes(const mpr_scene* scenes, int32_t n_scenes, const
     const int grid = 256 * 4 * mpr::kRlWaves;          // one wave per workgroup, every wave slot of the device
     const int32_t cap = c.stop_mode == MPR_STOP_AUTO ? c.n_max : c.n_eq;
     const int32_t total_max = cap + c.n_samp;
+    MPR_HIP(mpr::launch_batchl_bounds(b, s));         // the XCD split of the first sweep's work list
 
     // the sweep loop: a graph of n_f sweeps replayed until every scene is done
     const int per_graph = c.stop_mode == MPR_STOP_AUTO ? std::max(1, c.n_f) : 5;

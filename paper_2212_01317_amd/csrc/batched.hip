@@ -368,10 +368,101 @@ __global__ __launch_bounds__(256) void k_batchl_accumulate(const BatchLaneScene*
     });
 }
 
+// Estimated time of one sweep of a scene, relative: every site costs kSiteCost (its angle, cos, sin and energy term
+// and its share of the row's loads and waits) and every gap site kGapCost more (its update), the costs per site and
+// per update that fit the lane sweep's measured times on the 4096^2 input at p = 0.3, 0.6 and 0.9.
+constexpr int64_t kSiteCost = 32, kGapCost = 59;
+
+// The XCD bounds of the work list of the running scenes (one workgroup of 256 threads, after `prefix` holds the
+// list's item offsets): bound[x] is the item at which x eighths of the estimated time are reached, the time of a
+// scene spread evenly over its items.  Integer costs, so that the scenes' cost intervals tile [0, total) exactly
+// and every eighth's boundary falls in exactly one of them.
+__device__ __forceinline__ void xcd_bounds(const BatchLaneScene* scenes, const BatchRun* runs, const int* order,
+                                           const int64_t* prefix, const int64_t* gaps, int n_scenes,
+                                           int64_t* bound)
+{
+    __shared__ long long csum[4];
+    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    auto cost_of = [&](int i) -> long long {
+        if (i >= n_scenes) return 0;
+        const int s = order[i];
+        return runs[s].phase < 2 ? (long long)(kSiteCost * scenes[s].HW + kGapCost * gaps[s]) : 0;
+    };
+    // total
+    long long total = 0;
+    for (int i0 = 0; i0 < n_scenes; i0 += 256) {
+        long long x = cost_of(i0 + (int)threadIdx.x);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) csum[wv] = x;
+        __syncthreads();
+        total += ((csum[0] + csum[1]) + csum[2]) + csum[3];
+        __syncthreads();
+    }
+    const int64_t N = prefix[n_scenes];
+    if (threadIdx.x == 0) {
+        bound[0] = 0;
+        bound[8] = N;
+    }
+    if (total <= 0) {
+        if (threadIdx.x >= 1 && threadIdx.x < 8) bound[threadIdx.x] = N;
+        return;
+    }
+    // the scene whose cost interval holds x eighths of the total sets bound[x]
+    long long base = 0;
+    for (int i0 = 0; i0 < n_scenes; i0 += 256) {
+        const int i = i0 + (int)threadIdx.x;
+        const long long c = cost_of(i);
+        long long x = c;                    // inclusive scan of the costs within the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) csum[wv] = x;
+        __syncthreads();
+        long long before = base;
+        for (int j = 0; j < wv; ++j) before += csum[j];
+        before += x - c;
+        if (c > 0) {
+            const int s = order[i];
+            for (int q = 1; q < 8; ++q) {
+                const long long t = total / 8 * q + (total % 8) * q / 8;     // floor(total q / 8) without overflow
+                if (before <= t && t < before + c)
+                    bound[q] = prefix[i] + (int64_t)((t - before) * scenes[s].work / c);
+            }
+        }
+        base += ((csum[0] + csum[1]) + csum[2]) + csum[3];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batchl_bounds(const BatchLaneScene* scenes, const BatchRun* runs,
+                                                        const int* order, const int64_t* prefix,
+                                                        const int64_t* gaps, BatchLaneCtl* ctl, int n_scenes)
+{
+    xcd_bounds(scenes, runs, order, prefix, gaps, n_scenes, ctl->bound);
+}
+
+__global__ __launch_bounds__(256) void k_count_gaps(const uint8_t* __restrict__ mask, int64_t HW,
+                                                     unsigned long long* out)
+{
+    __shared__ unsigned long long wsum[4];
+    unsigned long long c = 0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < HW; n += (int64_t)gridDim.x * 256)
+        c += mask[n] ? 0u : 1u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]);
+}
+
 // Phase transitions after sweep k (the test of the single-scene driver), then the work list of the scenes still
 // running (one workgroup).
 __global__ __launch_bounds__(256) void k_batchl_phase(const BatchLaneScene* scenes, BatchRun* runs, const int* order,
-                                                       int64_t* prefix, BatchLaneCtl* ctl, BatchCfg c, int n_scenes)
+                                                       int64_t* prefix, const int64_t* gaps, BatchLaneCtl* ctl,
+                                                       BatchCfg c, int n_scenes)
 {
     const int k = ctl->k;
     for (int s = threadIdx.x; s < n_scenes; s += 256) {
@@ -400,6 +491,8 @@ __global__ __launch_bounds__(256) void k_batchl_phase(const BatchLaneScene* scen
     }
     __syncthreads();
     running_work_prefix(runs, order, prefix, n_scenes, &ctl->n_active, [&](int s) { return scenes[s].work; });
+    __syncthreads();
+    xcd_bounds(scenes, runs, order, prefix, gaps, n_scenes, ctl->bound);
 }
 
 hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, hipStream_t s)
@@ -417,8 +510,23 @@ hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, h
     }
     hipLaunchKernelGGL(k_batchl_accumulate, dim3(acc_blocks), dim3(256), 0, s, b.scenes, b.runs, b.ctl, b.cfg.R, b.n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batchl_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.ctl, b.cfg,
+    hipLaunchKernelGGL(k_batchl_phase, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.gaps, b.ctl,
+                       b.cfg, b.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batchl_bounds(const BatchLaneDev& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batchl_bounds, dim3(1), dim3(256), 0, s, b.scenes, b.runs, b.order, b.prefix, b.gaps, b.ctl,
                        b.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_gaps(const uint8_t* mask, int64_t HW, int64_t* out, hipStream_t s)
+{
+    const int64_t blocks = (HW + 255) / 256;
+    hipLaunchKernelGGL(k_count_gaps, dim3((unsigned)(blocks < 256 ? (blocks > 0 ? blocks : 1) : 256)), dim3(256), 0, s,
+                       mask, HW, reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 

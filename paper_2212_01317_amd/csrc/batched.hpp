@@ -76,12 +76,14 @@ struct BatchLaneScene {
     double inv_norm;      // 1 / (J * number of bonds)
 };
 
-// Eight work queues, one per XCD: an XCD takes the items of its eighth of the work list in order, so adjacent
-// bands of a scene run on one XCD (their shared columns come from its L2 cache).
+// Eight work queues, one per XCD: XCD x takes the items [bound[x], bound[x + 1]) of the work list in order, so
+// adjacent bands of a scene run on one XCD (their shared columns come from its L2 cache); the bounds split the
+// estimated time of the sweep (sites and gap sites of the running scenes) into eighths.
 struct BatchLaneCtl {
     int k;
     int n_active;
     unsigned long long queue[8];
+    int64_t bound[9];
 };
 
 struct BatchLaneDev {
@@ -93,12 +95,17 @@ struct BatchLaneDev {
     BatchCfg cfg;
     int n;
     int tm;               // temperature lookup of every scene's sweep (TM_ALIGNED / TM_TWO / TM_ANY)
+    const int64_t* gaps;  // [n] gap sites of each scene
 };
 
 // the persistent lane sweep of all running scenes (rl_sweep.hip)
 hipError_t launch_batchl_sweep(const BatchLaneDev& b, int grid, hipStream_t s);
 // one sweep of the lane batch: counter, sweep, energies, accumulation, phases and the next work list
 hipError_t launch_batchl_step(const BatchLaneDev& b, int grid, int acc_blocks, hipStream_t s);
+// the XCD bounds of the current work list (before the first sweep; the phase kernel renews them after each sweep)
+hipError_t launch_batchl_bounds(const BatchLaneDev& b, hipStream_t s);
+// *out += number of gap sites (mask 0) among mask[0 .. HW)
+hipError_t launch_count_gaps(const uint8_t* mask, int64_t HW, int64_t* out, hipStream_t s);
 
 hipError_t launch_batch_sweep(const BatchDev& b, int variant, int grid, hipStream_t s);
 hipError_t launch_batch_step(const BatchDev& b, int variant, int next_variant, int grid, int acc_blocks,

@@ -566,9 +566,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRlWaves, kR
     volatile BatchLaneLoop& VL = L;
     if (threadIdx.x == 0) {
         const uint32_t xcd = blockIdx.x & 7u;
-        const int64_t N = prefix[n_scenes];
-        VL.first = N * (int64_t)xcd / 8;
-        VL.last = N * (int64_t)(xcd + 1) / 8;
+        VL.first = ctl->bound[xcd];
+        VL.last = ctl->bound[xcd + 1];
         VL.k = ctl->k;
     }
     __syncthreads();
