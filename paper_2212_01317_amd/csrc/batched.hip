@@ -428,8 +428,8 @@ __device__ __forceinline__ void xcd_bounds(const BatchLaneScene* scenes, const B
             const int s = order[i];
             for (int q = 1; q < 8; ++q) {
                 const long long t = total / 8 * q + (total % 8) * q / 8;     // floor(total q / 8) without overflow
-                if (before <= t && t < before + c)
-                    bound[q] = prefix[i] + (int64_t)((t - before) * scenes[s].work / c);
+                if (before <= t && t < before + c)      // (a 128-bit product: cost x items can pass 2^63)
+                    bound[q] = prefix[i] + (int64_t)((__int128)(t - before) * scenes[s].work / c);
             }
         }
         base += ((csum[0] + csum[1]) + csum[2]) + csum[3];
